@@ -1,0 +1,202 @@
+"""Whole-lattice pins of the oracle: closed-form flows and the paper's worked numbers.
+
+Sec. 9 of the paper validates the method on a body-force-driven channel
+(analytical parabola), Womersley flow and a square duct (Eq. ductFourier), with
+half-way bounce-back walls, and quotes Reynolds and Womersley numbers for its
+parameters.  The paper does not say where its walls sit; its own numbers fix
+that: with N nodes across and one solid layer at each end, the half-width is
+a = (N - 2)/2.  The start-up transients used below follow from the same
+momentum equation, du/dt = nu Laplacian(u) + F/rho, by Fourier series.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import lbm
+from oracle.lattice import D3Q15, D3Q27
+
+
+def nu_of(omega):
+    # nu = c_s^2 (1/omega - 1/2), end of Sec. 7
+    return (1.0 / omega - 0.5) / 3.0
+
+
+def channel_startup(zc, a, F, nu, t, nterms=400):
+    """u(z, t) between walls at z = +-a, from rest, under constant force F."""
+    u = F * (a * a - zc * zc) / (2 * nu)
+    for n in range(nterms):
+        k = 2 * n + 1
+        u = u - 16 * F * a * a / (nu * math.pi**3) * (-1) ** n / k**3 \
+            * np.cos(k * math.pi * zc / (2 * a)) * math.exp(-k * k * math.pi**2 * nu * t / (4 * a * a))
+    return u
+
+
+def duct_startup(yc, zc, a, F, nu, t, nterms=80):
+    """u(y, z, t) in the square duct |y|, |z| <= a, from rest (double series)."""
+    u = np.zeros(np.broadcast(yc, zc).shape)
+    for m in range(1, 2 * nterms, 2):
+        for n in range(1, 2 * nterms, 2):
+            k2 = (math.pi / (2 * a)) ** 2 * (m * m + n * n)
+            c = 16 * (-1) ** ((m - 1) // 2 + (n - 1) // 2) / (math.pi**2 * m * n)
+            u = u + c * F / (nu * k2) * (1 - math.exp(-nu * k2 * t)) \
+                * np.cos(m * math.pi * yc / (2 * a)) * np.cos(n * math.pi * zc / (2 * a))
+    return u
+
+
+def duct_steady_paper(y, z, a, F, nu, rho=1.0, nterms=200):
+    """Eq. ductFourier, as printed."""
+    s = 0.0
+    for n in range(1, nterms + 1):
+        k = 2 * n - 1
+        s = s + (-1) ** (n - 1) * (1 - np.cosh(k * math.pi * z / (2 * a)) / math.cosh(k * math.pi / 2)) \
+            * np.cos(k * math.pi * y / (2 * a)) / k**3
+    return 16 * a * a * F / (rho * nu * math.pi**3) * s
+
+
+# ----------------------------------------------------------------------------
+# Worked numbers of Sec. 9
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("F,omega,Re", [(2e-7, 1.818, 3.6), (4e-7, 1.818, 7.2), (6e-7, 1.818, 10.7),
+                                        (1e-6, 1.923, 111.8), (1e-6, 1.961, 447.2)])
+def test_channel_reynolds_numbers(F, omega, Re):
+    nu = nu_of(omega)
+    a = (45 - 2) / 2
+    u0 = F * a * a / (2 * nu)                   # centerline, u0 = F L^2 / (2 nu)
+    assert abs(u0 * a / nu - Re) / Re < 0.015
+    for a_wrong in ((45 - 1) / 2, 45 / 2):          # walls on the nodes, or one node out
+        u0w = F * a_wrong**2 / (2 * nu)
+        assert abs(u0w * a_wrong / nu - Re) / Re > 0.05
+
+
+def test_viscosity_quoted():
+    assert abs(nu_of(1.818) - 0.0167) < 5e-5       # "nu (= 0.0167 here)"
+
+
+def test_womersley_numbers():
+    a = (45 - 2) / 2
+    Om = 2 * math.pi / 10000
+    for omega, Wo in [(1.724, 3.3), (1.923, 6.6)]:
+        assert abs(math.sqrt(Om / nu_of(omega)) * a - Wo) < 0.01
+
+
+def test_duct_reynolds_number():
+    a = (45 - 2) / 2
+    nu = nu_of(1.923)
+    umax = duct_steady_paper(0.0, 0.0, a, 1e-6, nu)
+    assert abs(umax * a / nu - 65.7) < 0.1
+    # centerline coefficient of the series: u_max = 0.2946854 a^2 F / (rho nu)
+    assert abs(umax / (a * a * 1e-6 / nu) - 0.2946854) < 1e-7
+
+
+def test_grid_convergence_case_reynolds_slip():
+    # N = 13 with F = 6.958e-6 gives Re = 2.08; the printed 20.8 is a
+    # power-of-ten slip (F = 6.958e-5 would give 20.8).
+    a = (13 - 2) / 2
+    nu = nu_of(1.818)
+    for F, Re in [(6.958e-6, 2.08), (6.958e-5, 20.8)]:
+        assert abs(F * a * a / (2 * nu) * a / nu - Re) / Re < 0.005
+
+
+def test_duct_series_limits_agree():
+    a, F, nu = 10.5, 1e-6, 0.05
+    ys = np.linspace(-a, a, 7)
+    Y, Z = np.meshgrid(ys, ys, indexing="ij")
+    steady = duct_steady_paper(Y, Z, a, F, nu)
+    late = duct_startup(Y, Z, a, F, nu, t=1e9)
+    assert np.abs(steady - late).max() < 1e-6 * np.abs(steady).max()
+
+
+# ----------------------------------------------------------------------------
+# Simulations with the oracle
+# ----------------------------------------------------------------------------
+def _walls_z(N, nx=3, ny=3):
+    solid = np.zeros((N, ny, nx), dtype=bool)
+    solid[0] = solid[-1] = True
+    return solid
+
+
+@pytest.mark.parametrize("lat", [D3Q15, D3Q27], ids=str)
+def test_channel_startup_matches_series(lat):
+    # Sec. 9 channel: 3 x 3 x 45, omega^nu = 1.818, other rates 1, F_x = 6e-7.
+    N, omega, F, T = 45, 1.818, 6e-7, 600
+    solid = _walls_z(N)
+    Fv = np.array([F, 0.0, 0.0])
+    om = [omega] * 5 + [1.0] * (lat.Q - 9)
+    f = lbm.initial_state(lat, np.ones((N, 3, 3)), np.zeros((3, N, 3, 3)), Fv, solid)
+    f = lbm.run(lat, f, Fv, om, T, solid)
+    rho, u = lbm.macroscopic_fields(lat, f, Fv, solid)
+    zc = np.arange(1, N - 1) - (N - 1) / 2
+    ua = channel_startup(zc, (N - 2) / 2, F, nu_of(omega), T)
+    un = u[0, 1:-1, 1, 1]
+    assert np.linalg.norm(un - ua) / np.linalg.norm(ua) < 4e-3
+    assert np.abs(u[1:]).max() < 1e-10                      # no cross flow (rounding only)
+    # the wrong wall position is clearly worse
+    ub = channel_startup(zc, (N - 1) / 2, F, nu_of(omega), T)
+    assert np.linalg.norm(un - ub) / np.linalg.norm(ub) > 2e-2
+
+
+@pytest.mark.parametrize("lat", [D3Q15, D3Q27], ids=str)
+def test_duct_startup_matches_series(lat):
+    # Duct of Sec. 9, smaller: 3 x 23 x 23 nodes, walls on y and z, omega 1.25.
+    N, omega, F, T = 23, 1.25, 1e-6, 250
+    solid = np.zeros((N, N, 3), dtype=bool)
+    solid[0] = solid[-1] = True
+    solid[:, 0] = solid[:, -1] = True
+    Fv = np.array([F, 0.0, 0.0])
+    om = [omega] * 5 + [1.0] * (lat.Q - 9)
+    f = lbm.initial_state(lat, np.ones((N, N, 3)), np.zeros((3, N, N, 3)), Fv, solid)
+    f = lbm.run(lat, f, Fv, om, T, solid)
+    rho, u = lbm.macroscopic_fields(lat, f, Fv, solid)
+    c = np.arange(1, N - 1) - (N - 1) / 2
+    Z, Y = np.meshgrid(c, c, indexing="ij")
+    ua = duct_startup(Y, Z, (N - 2) / 2, F, nu_of(omega), T)
+    un = u[0, 1:-1, 1:-1, 1]
+    assert np.linalg.norm(un - ua) / np.linalg.norm(ua) < 1e-2
+
+
+@pytest.mark.parametrize("lat", [D3Q15, D3Q27], ids=str)
+def test_lattice_conservation_periodic_and_walls(lat):
+    rng = np.random.default_rng(3)
+    n = 6
+    rho0 = 1 + 0.01 * rng.standard_normal((n, n, n))
+    u0 = 0.03 * rng.standard_normal((3, n, n, n))
+    F = 1e-4 * rng.standard_normal((3, n, n, n))
+    om = list(rng.uniform(0.6, 1.9, lat.Q - 4))
+    f = lbm.initial_state(lat, rho0, u0, F)
+    T0 = lbm.totals(lat, f, F)
+    f1 = lbm.step(lat, f, F, om)
+    T1 = lbm.totals(lat, f1, F)
+    assert abs(T1[0] - T0[0]) < 1e-12
+    # momentum: + sum F per step, F/2 bookkeeping on both sides uses the same F
+    assert np.abs(T1[1:] - T0[1:] - F.reshape(3, -1).sum(axis=1)).max() < 1e-13
+    # with walls, mass is still exact (bounce-back returns every population)
+    solid = np.zeros((n, n, n), dtype=bool)
+    solid[0] = True
+    solid[:, :, 2] = True
+    f = lbm.initial_state(lat, rho0, u0, F, solid)
+    m0 = lbm.totals(lat, f, F, solid)[0]
+    f = lbm.run(lat, f, F, om, 3, solid)
+    assert abs(lbm.totals(lat, f, F, solid)[0] - m0) < 1e-12
+
+
+def test_initial_state_velocity_is_u0():
+    rng = np.random.default_rng(4)
+    n = 4
+    rho0 = 1 + 0.01 * rng.standard_normal((n, n, n))
+    u0 = 0.05 * rng.standard_normal((3, n, n, n))
+    F = 1e-3 * rng.standard_normal((3, n, n, n))
+    for lat in (D3Q27, D3Q15):
+        f = lbm.initial_state(lat, rho0, u0, F)
+        rho, u = lbm.macroscopic_fields(lat, f, F)
+        assert np.abs(rho - rho0).max() < 1e-14 and np.abs(u - u0).max() < 1e-14
+
+
+def test_streaming_periodic_shift():
+    # A single marked population travels one link per step along e_a.
+    lat = D3Q27
+    post = np.zeros((27, 4, 5, 6))
+    post[:, 1, 2, 3] = np.arange(27) + 1.0
+    out = lbm.stream(lat, post)
+    for a, (ex, ey, ez) in enumerate(lat.E):
+        assert out[a, (1 + ez) % 4, (2 + ey) % 5, (3 + ex) % 6] == a + 1
