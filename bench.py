@@ -1,0 +1,161 @@
+#!/usr/bin/env python3
+"""Throughput of the fused D3Q27 central-moment LBM step on one MI355X.
+
+Workload (one "step" = one pull-stream + collide + force pass over the whole
+lattice): D3Q27, 512^3 periodic, FP32 storage and arithmetic, Kolmogorov body
+force field F_x = 1e-6 sin(2 pi 4 y / 512) (read as an FP32 field, 12 B/node),
+shear rate omega_4..omega_8 = 1.9, all other rates 1, fluid at rest initially.
+Synthetic inputs, no dataset.
+
+Prints ONE JSON line: MLUPS (whole job), the HBM roofline of the step kernel
+(algorithmic 228 B per node update: 27 FP32 loads + 27 FP32 stores + 3 FP32
+force loads), the FP64 CPU oracle timed on a bounded sample, and the
+adjoint/forward time ratio of a 100-step checkpointed adjoint.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS + % HBM roofline, D3Q27 512^3 FP32 step; adjoint/forward time ratio"
+HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
+BYTES_PER_NODE = 27 * 4 * 2 + 3 * 4
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_step_d3q27_f32_512_counters.json")
+KERNEL_SOURCES = ["paper_1202_6081_amd/csrc/kernels.hip", "paper_1202_6081_amd/csrc/collide_d3q27.hpp",
+                  "paper_1202_6081_amd/csrc/lattice.hpp", "paper_1202_6081_amd/csrc/kernels.hpp"]
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(n_nodes):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    try:
+        with open(COUNTERS_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != kernel_source_hash() or rec.get("nodes") != n_nodes:
+        return None
+    return rec.get("hbm_bytes_per_dispatch")
+
+
+def cpu_baseline(seconds_target=15.0):
+    """The FP64 oracle on a bounded sample of the same workload: single steps of
+    a 40^3 D3Q27 box with the same rates and a Kolmogorov force."""
+    import numpy as np
+    from oracle import lbm
+    from oracle.lattice import D3Q27
+    import lbm_inputs as inp
+    n = 40
+    F = inp.kolmogorov_force(n, waves=4)
+    om = [1.9] * 5 + [1.0] * 18
+    f = lbm.initial_state(D3Q27, np.ones((n, n, n)), np.zeros((3, n, n, n)), F)
+    t0 = time.perf_counter()
+    steps = 0
+    while True:
+        f = lbm.step(D3Q27, f, F, om)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el > seconds_target * 0.5 or steps >= 8:
+            break
+    return {"value": n**3 * steps / el / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} step(s) of a {n}^3 D3Q27 periodic box, FP64 NumPy oracle, "
+                      f"Kolmogorov force, shear rate 1.9 ({el:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--adjoint-steps", type=int, default=100)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the build targets single-GPU runs only "
+              "(multi-GPU z-slab decomposition is a design note, not built).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import lbm_inputs as inp
+    from paper_1202_6081_amd import cmlbm
+
+    n = args.n
+    N = n**3
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    sim = cmlbm.Sim(27, n, n, n, cmlbm.F32)
+    sim.set_rates([1.9] * 5 + [1.0] * 18)
+    F = torch.from_numpy(inp.kolmogorov_force(n, amplitude=1e-6, waves=4)).to(dev, torch.float32)
+    sim.set_force(F)
+    del F
+    a = sim.populations()
+    b = sim.populations()
+    rho0 = torch.ones((n, n, n), device=dev, dtype=torch.float32)
+    u0 = torch.zeros((3, n, n, n), device=dev, dtype=torch.float32)
+    sim.init_equilibrium(rho0, u0, f_post=a, f_pre=b)
+    del rho0, u0
+    stream = torch.cuda.current_stream()
+    bufs = [a, b]
+    for i in range(args.warmup):
+        sim.step(bufs[i & 1], bufs[(i + 1) & 1])
+    k0 = args.warmup
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for i in range(args.steps):
+        j = k0 + i
+        sim.step(bufs[j & 1], bufs[(j + 1) & 1])
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    last = bufs[(k0 + args.steps) & 1]
+    ms_per_step = ms / args.steps
+    mlups = N / (ms_per_step * 1e-3) / 1e6
+    achieved = BYTES_PER_NODE * N / (ms_per_step * 1e-3) / 1e9
+    traffic = measured_traffic(N)
+    tot = sim.totals(last)
+
+    result = {
+        "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"D3Q27 central-moment LBM {n}^3 periodic, FP32, Kolmogorov force field "
+                               f"F_x=1e-6 sin(2 pi 4 y/{n}), shear rate 1.9, others 1.0, from rest",
+                   "lattice": "D3Q27", "nodes": N, "storage": "f32", "force": "field"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None if traffic is None else round(traffic / (ms_per_step * 1e-3) / 1e9, 1),
+                     "algorithmic_bytes_per_node": BYTES_PER_NODE, "kernel": "k_step<27,StF32,false>"},
+        "mass_total_fp64": tot[0],
+    }
+    if not args.no_adjoint:
+        from paper_1202_6081_amd import autograd as ag
+        result["adjoint"] = ag.benchmark_adjoint_ratio(sim, bufs[(k0 + args.steps) & 1], args.adjoint_steps,
+                                                       forward_ms_per_step=ms_per_step)
+    else:
+        result["adjoint"] = None
+    del a, b, bufs
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

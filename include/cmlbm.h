@@ -1,0 +1,168 @@
+/*
+ * cmlbm -- C ABI of the 3D central-moment lattice Boltzmann step on MI355X.
+ *
+ * The method is Premnath & Banerjee, "On the Three-dimensional Central Moment
+ * Lattice Boltzmann Method" (arXiv:1202.6081): D3Q27 and D3Q15 lattices,
+ * central moments relaxed toward factorized attractors in cascade, and a
+ * de-aliased body-force source treated semi-implicitly with the implicitness
+ * removed by fbar = f - S/2.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Status:     every call returns cmlbm_status; 0 is success, negative values
+ *             are errors.  No C++ exception crosses this boundary.  After an
+ *             error, cmlbm_last_error(sim) holds a message.
+ * Ownership:  the caller allocates and owns every device buffer (populations,
+ *             fields, mask, gradients).  The library borrows a pointer for the
+ *             duration of a call, except the force field and the mask, which
+ *             are borrowed until replaced or until cmlbm_destroy.  The library
+ *             owns only the opaque handle and a few kilobytes of device scratch
+ *             for reductions.  Device pointers must be 256-byte aligned.
+ * Streams:    `stream` is a hipStream_t (NULL = the default stream).  Work is
+ *             enqueued asynchronously; only cmlbm_totals synchronizes.
+ * Threads:    a handle must not be used by two host threads at once.
+ * Layout:     structure of arrays, x fastest.  Populations f[a][nz][ny][nx]
+ *             with directions a in the paper's order (Eq. velocityd3qq27 and
+ *             Appendix A for D3Q27; Appendix G for D3Q15).  Vector fields
+ *             (velocity, force, force gradient) are [3][nz][ny][nx].
+ *             Scalars are [nz][ny][nx].
+ * State:      the population buffers passed to cmlbm_step / cmlbm_run hold the
+ *             post-collision, not yet streamed populations fbar~ (Eq.
+ *             cascadedcollision1).  The paper's state, the pre-collision
+ *             fbar(x, t), is read out by cmlbm_gather_precollision.
+ * Types:      "real" means double for CMLBM_F64 and float for the other three
+ *             precisions.  Population buffers are double (F64), float (F32),
+ *             IEEE binary16 (F32_F16DEV) or bfloat16 (F32_BF16DEV); the 16-bit
+ *             formats hold fbar - w_a, the deviation from the rest-state weight
+ *             w_a (8/27, 2/27, 1/54, 1/216 for D3Q27; 2/9, 1/9, 1/72 for
+ *             D3Q15), rounded to nearest even.  Arithmetic is in "real".
+ */
+#ifndef CMLBM_H
+#define CMLBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CMLBM_OK = 0,
+  CMLBM_EINVAL = -1,       /* bad argument: null pointer, size, rate, aliasing */
+  CMLBM_EUNSUPPORTED = -2, /* valid request this build does not provide */
+  CMLBM_EDEVICE = -3,      /* HIP runtime error; message in cmlbm_last_error */
+  CMLBM_ENOMEM = -4,       /* device scratch allocation failed */
+  CMLBM_ESTATE = -5        /* call order violated */
+} cmlbm_status;
+
+typedef enum { CMLBM_D3Q15 = 15, CMLBM_D3Q27 = 27 } cmlbm_lattice;
+
+typedef enum {
+  CMLBM_F64 = 0,         /* FP64 storage and arithmetic */
+  CMLBM_F32 = 1,         /* FP32 storage and arithmetic */
+  CMLBM_F32_F16DEV = 2,  /* FP32 arithmetic, FP16 storage of fbar - w */
+  CMLBM_F32_BF16DEV = 3  /* FP32 arithmetic, BF16 storage of fbar - w */
+} cmlbm_precision;
+
+typedef struct cmlbm_sim cmlbm_sim; /* opaque; host memory owned by the library */
+
+/* Create a handle for a nx * ny * nz lattice, periodic in all directions until
+ * a mask is set.  q: 15 or 27 (Eq. velocityd3qq27, Appendix G).  All rates
+ * start at 1, the force at zero, the force scale at 1.  Limits: 1 <= n*,
+ * ny, nz <= 65535, nx * ny * nz < 2^31.  Errors: EINVAL (sizes, q, precision,
+ * out == NULL), EDEVICE (no HIP device), ENOMEM. */
+cmlbm_status cmlbm_create(int q, int nx, int ny, int nz, int precision, cmlbm_sim **out);
+
+/* Release the handle and its device scratch.  NULL is allowed. */
+void cmlbm_destroy(cmlbm_sim *sim);
+
+/* Relaxation rates omega_4 .. omega_(q-1) of the collision kernels g_4 ..
+ * g_(q-1) (Sec. 7; Appendix G for D3Q15), n == q - 4 values, each in the open
+ * interval (0, 2) (end of Sec. 7).  The shear viscosity is
+ * nu = (1/omega - 1/2)/3 with omega = omega_4 = ... = omega_8.  Host array,
+ * copied.  Errors: EINVAL (n, NULL, a rate outside (0, 2)). */
+cmlbm_status cmlbm_set_rates(cmlbm_sim *sim, const double *omega, int n);
+
+/* Uniform body force F (force per unit volume, Sec. 3 Eq. forcingaliased).
+ * Replaces any force field. */
+cmlbm_status cmlbm_set_force_uniform(cmlbm_sim *sim, double fx, double fy, double fz);
+
+/* Spatially varying body force, device array [3][nz][ny][nx] of "real",
+ * borrowed until replaced.  NULL returns to the uniform force. */
+cmlbm_status cmlbm_set_force_field(cmlbm_sim *sim, const void *F_dev);
+
+/* Multiplier applied to the force (uniform or field) from the next call on,
+ * e.g. cos(Omega t) for the time-periodic forcing of Sec. 9.  Default 1. */
+cmlbm_status cmlbm_set_force_scale(cmlbm_sim *sim, double scale);
+
+/* Solid mask for half-way bounce-back walls (Sec. 9): device array
+ * [nz][ny][nx] of uint8, 0 = fluid, nonzero = solid; borrowed until replaced.
+ * Solid nodes are never collided or written by cmlbm_step; a population that
+ * would stream into a solid node returns reversed to its source node in the
+ * same step.  NULL returns to fully periodic. */
+cmlbm_status cmlbm_set_mask(cmlbm_sim *sim, const uint8_t *mask_dev);
+
+/* Initial state.  rho_dev [nz][ny][nx] and u_dev [3][nz][ny][nx] ("real",
+ * device) give the macroscopic fields; the pre-collision state is
+ * fbar(x, 0) = f^eq(rho, u) - S(F, u)/2 (the transformation of Sec. 4 applied
+ * to the equilibrium with the Maxwellian central moments of Sec. 3), so that
+ * the velocity read back is u.  It is written, as full "real" populations,
+ * into f_pre_dev [q][nz][ny][nx]; f_post_dev (population storage type) receives
+ * the post-collision buffer whose first step pulls exactly fbar(x, 0).  Uses
+ * the current force and mask.  Errors: EINVAL (NULL, f_pre_dev == f_post_dev). */
+cmlbm_status cmlbm_init_equilibrium(cmlbm_sim *sim, const void *rho_dev, const void *u_dev, void *f_pre_dev,
+                                    void *f_post_dev, void *stream);
+
+/* One time step (Eqs. cascadedcollision1 and cascadedstreaming1): pull-stream
+ * f_in (post-collision of step t-1), collide with forcing, write the
+ * post-collision populations of step t into f_out.  f_in != f_out. */
+cmlbm_status cmlbm_step(cmlbm_sim *sim, const void *f_in, void *f_out, void *stream);
+
+/* nsteps >= 0 steps ping-ponging between f_a and f_b, starting from f_a.
+ * *result_in_b (may be NULL) is set to 1 when the last state is in f_b. */
+cmlbm_status cmlbm_run(cmlbm_sim *sim, void *f_a, void *f_b, int nsteps, void *stream, int *result_in_b);
+
+/* The paper's state: pre-collision fbar(x, t) pulled from the post-collision
+ * buffer f_post, as full "real" populations [q][nz][ny][nx] (zeros at solid
+ * nodes).  f_post != f_pre. */
+cmlbm_status cmlbm_gather_precollision(cmlbm_sim *sim, const void *f_post, void *f_pre, void *stream);
+
+/* Density and velocity (Eqs. densitycalculation, velocitycalculation,
+ * rho u = sum fbar e + F/2) of the pre-collision state of f_post; "real"
+ * outputs rho [nz][ny][nx], u [3][nz][ny][nx]; zeros at solid nodes. */
+cmlbm_status cmlbm_macroscopic(cmlbm_sim *sim, const void *f_post, void *rho, void *u, void *stream);
+
+/* FP64 totals over fluid nodes of the pre-collision state: out4 = (sum rho,
+ * sum rho u_x, sum rho u_y, sum rho u_z) with rho u including F/2.  Host
+ * output; synchronizes `stream`. */
+cmlbm_status cmlbm_totals(cmlbm_sim *sim, const void *f_post, double out4[4], void *stream);
+
+/* Adjoint of one D3Q27 step (reverse streaming plus the transposed Jacobian
+ * of the central-moment collision and force terms).  Forward step n maps the
+ * pre-collision state fbar^n, pulled from f_post_prev, to fbar^(n+1).  Given
+ * lam_next = dL/dfbar^(n+1) ("real" [27][nz][ny][nx]), writes
+ * lam = dL/dfbar^n and accumulates (adds) into
+ *   dLdF_dev:     FP64 [3][nz][ny][nx] when a force field is set, or FP64 [3]
+ *                 (dL/dF of the uniform force) otherwise;
+ *   dLdomega_dev: FP64 [23], dL/domega_4 .. dL/domega_26.
+ * The force and rates must be those of the forward step.  lam, lam_next and
+ * f_post_prev must not overlap.  Errors: EUNSUPPORTED for q = 15. */
+cmlbm_status cmlbm_adjoint_step(cmlbm_sim *sim, const void *f_post_prev, const void *lam_next, void *lam,
+                                double *dLdF_dev, double *dLdomega_dev, void *stream);
+
+/* Message for a status code (static string). */
+const char *cmlbm_status_string(cmlbm_status code);
+
+/* Message of the last failed call on this handle (valid until the next call);
+ * "" when the last call succeeded.  NULL sim returns the message of the last
+ * failed cmlbm_create on this thread. */
+const char *cmlbm_last_error(const cmlbm_sim *sim);
+
+/* Library version string, "major.minor.patch". */
+const char *cmlbm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CMLBM_H */

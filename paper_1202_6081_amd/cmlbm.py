@@ -1,0 +1,281 @@
+"""ctypes binding of libcmlbm.so (include/cmlbm.h): argument marshalling only.
+
+Each ``cmlbm_*`` function mirrors the C function of the same name; device
+buffers are torch tensors on the current HIP device (their ``data_ptr()`` is
+passed), streams default to torch's current stream.  Every numerical step runs
+in the library's HIP kernels; there is no fallback: importing this module on a
+machine without the built library raises.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcmlbm.so")
+
+D3Q15, D3Q27 = 15, 27
+F64, F32, F32_F16DEV, F32_BF16DEV = 0, 1, 2, 3
+PRECISION_NAMES = {F64: "f64", F32: "f32", F32_F16DEV: "f16dev", F32_BF16DEV: "bf16dev"}
+
+_lib = None
+
+
+class CmlbmError(RuntimeError):
+    def __init__(self, code, message):
+        super().__init__(f"cmlbm error {code}: {message}")
+        self.code = code
+
+
+def load_library():
+    """Load libcmlbm.so (built in-tree by paper_1202_6081_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise CmlbmError(-2, f"{LIB_PATH} is missing: run `python -m paper_1202_6081_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    sig = {
+        "cmlbm_create": (i, [i, i, i, i, i, ctypes.POINTER(vp)]),
+        "cmlbm_destroy": (None, [vp]),
+        "cmlbm_set_rates": (i, [vp, ctypes.POINTER(d), i]),
+        "cmlbm_set_force_uniform": (i, [vp, d, d, d]),
+        "cmlbm_set_force_field": (i, [vp, vp]),
+        "cmlbm_set_force_scale": (i, [vp, d]),
+        "cmlbm_set_mask": (i, [vp, vp]),
+        "cmlbm_init_equilibrium": (i, [vp, vp, vp, vp, vp, vp]),
+        "cmlbm_step": (i, [vp, vp, vp, vp]),
+        "cmlbm_run": (i, [vp, vp, vp, i, vp, ctypes.POINTER(i)]),
+        "cmlbm_gather_precollision": (i, [vp, vp, vp, vp]),
+        "cmlbm_macroscopic": (i, [vp, vp, vp, vp, vp]),
+        "cmlbm_totals": (i, [vp, vp, ctypes.POINTER(d), vp]),
+        "cmlbm_adjoint_step": (i, [vp, vp, vp, vp, vp, vp, vp]),
+        "cmlbm_status_string": (ctypes.c_char_p, [i]),
+        "cmlbm_last_error": (ctypes.c_char_p, [vp]),
+        "cmlbm_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    return ["cmlbm_create", "cmlbm_destroy", "cmlbm_set_rates", "cmlbm_set_force_uniform",
+            "cmlbm_set_force_field", "cmlbm_set_force_scale", "cmlbm_set_mask", "cmlbm_init_equilibrium",
+            "cmlbm_step", "cmlbm_run", "cmlbm_gather_precollision", "cmlbm_macroscopic", "cmlbm_totals",
+            "cmlbm_adjoint_step", "cmlbm_status_string", "cmlbm_last_error", "cmlbm_version"]
+
+
+# ----------------------------------------------------------------------------
+# marshalling helpers
+# ----------------------------------------------------------------------------
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    if not t.is_cuda:
+        raise CmlbmError(-1, "device buffers must be torch tensors on the GPU")
+    if not t.is_contiguous():
+        raise CmlbmError(-1, "device buffers must be contiguous")
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _check(code, handle=None):
+    if code != 0:
+        lib = load_library()
+        msg = lib.cmlbm_last_error(handle).decode() if handle is not None else ""
+        if not msg:
+            msg = lib.cmlbm_status_string(code).decode()
+        raise CmlbmError(code, msg)
+
+
+def real_dtype(precision):
+    return torch.float64 if precision == F64 else torch.float32
+
+
+def storage_dtype(precision):
+    return {F64: torch.float64, F32: torch.float32, F32_F16DEV: torch.float16,
+            F32_BF16DEV: torch.bfloat16}[precision]
+
+
+# ----------------------------------------------------------------------------
+# one Python function per C entry point
+# ----------------------------------------------------------------------------
+def cmlbm_create(q, nx, ny, nz, precision):
+    lib = load_library()
+    h = ctypes.c_void_p()
+    code = lib.cmlbm_create(q, nx, ny, nz, precision, ctypes.byref(h))
+    if code != 0:
+        raise CmlbmError(code, lib.cmlbm_last_error(None).decode())
+    return h
+
+
+def cmlbm_destroy(h):
+    load_library().cmlbm_destroy(h)
+
+
+def cmlbm_set_rates(h, omega):
+    arr = (ctypes.c_double * len(omega))(*[float(w) for w in omega])
+    _check(load_library().cmlbm_set_rates(h, arr, len(omega)), h)
+
+
+def cmlbm_set_force_uniform(h, fx, fy, fz):
+    _check(load_library().cmlbm_set_force_uniform(h, float(fx), float(fy), float(fz)), h)
+
+
+def cmlbm_set_force_field(h, F):
+    _check(load_library().cmlbm_set_force_field(h, _ptr(F)), h)
+
+
+def cmlbm_set_force_scale(h, scale):
+    _check(load_library().cmlbm_set_force_scale(h, float(scale)), h)
+
+
+def cmlbm_set_mask(h, mask):
+    _check(load_library().cmlbm_set_mask(h, _ptr(mask)), h)
+
+
+def cmlbm_init_equilibrium(h, rho, u, f_pre, f_post, stream=None):
+    _check(load_library().cmlbm_init_equilibrium(h, _ptr(rho), _ptr(u), _ptr(f_pre), _ptr(f_post),
+                                                  _stream(stream)), h)
+
+
+def cmlbm_step(h, f_in, f_out, stream=None):
+    _check(load_library().cmlbm_step(h, _ptr(f_in), _ptr(f_out), _stream(stream)), h)
+
+
+def cmlbm_run(h, f_a, f_b, nsteps, stream=None):
+    flag = ctypes.c_int(0)
+    _check(load_library().cmlbm_run(h, _ptr(f_a), _ptr(f_b), int(nsteps), _stream(stream), ctypes.byref(flag)), h)
+    return bool(flag.value)
+
+
+def cmlbm_gather_precollision(h, f_post, f_pre, stream=None):
+    _check(load_library().cmlbm_gather_precollision(h, _ptr(f_post), _ptr(f_pre), _stream(stream)), h)
+
+
+def cmlbm_macroscopic(h, f_post, rho, u, stream=None):
+    _check(load_library().cmlbm_macroscopic(h, _ptr(f_post), _ptr(rho), _ptr(u), _stream(stream)), h)
+
+
+def cmlbm_totals(h, f_post, stream=None):
+    out = (ctypes.c_double * 4)()
+    _check(load_library().cmlbm_totals(h, _ptr(f_post), out, _stream(stream)), h)
+    return [out[i] for i in range(4)]
+
+
+def cmlbm_adjoint_step(h, f_post_prev, lam_next, lam, dLdF, dLdomega, stream=None):
+    _check(load_library().cmlbm_adjoint_step(h, _ptr(f_post_prev), _ptr(lam_next), _ptr(lam), _ptr(dLdF),
+                                              _ptr(dLdomega), _stream(stream)), h)
+
+
+def cmlbm_version():
+    return load_library().cmlbm_version().decode()
+
+
+# ----------------------------------------------------------------------------
+# A handle with its buffers' shapes (still marshalling only)
+# ----------------------------------------------------------------------------
+class Sim:
+    """Owns one cmlbm handle.  Shapes: populations (Q, nz, ny, nx), scalars
+    (nz, ny, nx), vectors (3, nz, ny, nx)."""
+
+    def __init__(self, q, nx, ny, nz, precision=F32, device=None):
+        self.q, self.nx, self.ny, self.nz, self.precision = q, nx, ny, nz, precision
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        with torch.cuda.device(self.device):
+            self.h = cmlbm_create(q, nx, ny, nz, precision)
+        self.real = real_dtype(precision)
+        self.store = storage_dtype(precision)
+        self._keep = {}
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            cmlbm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # buffers -----------------------------------------------------------
+    def populations(self):
+        return torch.empty((self.q, self.nz, self.ny, self.nx), dtype=self.store, device=self.device)
+
+    def real_populations(self):
+        return torch.empty((self.q, self.nz, self.ny, self.nx), dtype=self.real, device=self.device)
+
+    # settings ----------------------------------------------------------
+    def set_rates(self, omega):
+        cmlbm_set_rates(self.h, list(omega))
+
+    def set_force(self, F):
+        """F: 3 numbers (uniform) or a (3, nz, ny, nx) real tensor (field)."""
+        if isinstance(F, torch.Tensor) and F.dim() == 4:
+            F = F.to(device=self.device, dtype=self.real).contiguous()
+            self._keep["force"] = F
+            cmlbm_set_force_field(self.h, F)
+        else:
+            self._keep.pop("force", None)
+            fx, fy, fz = [float(v) for v in F]
+            cmlbm_set_force_uniform(self.h, fx, fy, fz)
+
+    def set_force_scale(self, scale):
+        cmlbm_set_force_scale(self.h, scale)
+
+    def set_mask(self, solid):
+        if solid is None:
+            self._keep.pop("mask", None)
+            cmlbm_set_mask(self.h, None)
+            return
+        m = solid.to(device=self.device, dtype=torch.uint8).contiguous()
+        self._keep["mask"] = m
+        cmlbm_set_mask(self.h, m)
+
+    # work --------------------------------------------------------------
+    def init_equilibrium(self, rho, u, f_post=None, f_pre=None, stream=None):
+        rho = rho.to(device=self.device, dtype=self.real).contiguous()
+        u = u.to(device=self.device, dtype=self.real).contiguous()
+        f_post = self.populations() if f_post is None else f_post
+        f_pre = self.real_populations() if f_pre is None else f_pre
+        cmlbm_init_equilibrium(self.h, rho, u, f_pre, f_post, stream)
+        return f_post, f_pre
+
+    def step(self, f_in, f_out, stream=None):
+        cmlbm_step(self.h, f_in, f_out, stream)
+
+    def run(self, f_a, f_b, nsteps, stream=None):
+        """Returns the buffer holding the last state."""
+        return f_b if cmlbm_run(self.h, f_a, f_b, nsteps, stream) else f_a
+
+    def gather(self, f_post, out=None, stream=None):
+        out = self.real_populations() if out is None else out
+        cmlbm_gather_precollision(self.h, f_post, out, stream)
+        return out
+
+    def macroscopic(self, f_post, stream=None):
+        rho = torch.empty((self.nz, self.ny, self.nx), dtype=self.real, device=self.device)
+        u = torch.empty((3, self.nz, self.ny, self.nx), dtype=self.real, device=self.device)
+        cmlbm_macroscopic(self.h, f_post, rho, u, stream)
+        return rho, u
+
+    def totals(self, f_post, stream=None):
+        return cmlbm_totals(self.h, f_post, stream)
+
+    def adjoint_step(self, f_post_prev, lam_next, lam, dLdF, dLdomega, stream=None):
+        cmlbm_adjoint_step(self.h, f_post_prev, lam_next, lam, dLdF, dLdomega, stream)

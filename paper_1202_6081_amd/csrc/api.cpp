@@ -1,0 +1,330 @@
+// C ABI of the central-moment LBM library (declared in include/cmlbm.h).
+// Argument checking, handle state and kernel dispatch; no arithmetic of the
+// method lives here.
+#include "cmlbm.h"
+
+#include <hip/hip_runtime_api.h>
+
+#include <cmath>
+#include <cstdio>
+#include <string>
+
+#include "kernels.hpp"
+
+struct cmlbm_sim {
+  int q = 27;
+  int prec = 1;
+  int device = 0;
+  cmlbm::Geom g{};
+  double omega[23] = {};
+  double F[3] = {0, 0, 0};
+  const void* Ffield = nullptr;
+  double fscale = 1.0;
+  const uint8_t* mask = nullptr;
+  double* totals_partials = nullptr;   // [kTotalsBlocks][4]
+  double* totals_out = nullptr;        // [4]
+  double* adj_partials = nullptr;      // [adj_nblk][26]
+  int adj_nblk = 0;
+  std::string err;
+};
+
+namespace {
+
+thread_local std::string g_create_error;
+
+cmlbm_status fail(cmlbm_sim* s, cmlbm_status code, const std::string& msg) {
+  if (s) s->err = msg;
+  return code;
+}
+
+cmlbm_status ok(cmlbm_sim* s) {
+  s->err.clear();
+  return CMLBM_OK;
+}
+
+cmlbm_status check_hip(cmlbm_sim* s, hipError_t e, const char* what) {
+  if (e == hipSuccess) return ok(s);
+  return fail(s, CMLBM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <typename R>
+cmlbm::Rates<R> make_rates(const cmlbm_sim* s) {
+  cmlbm::Rates<R> r{};
+  for (int b = 0; b < 27; ++b) {
+    r.w[b] = R(0);
+    r.wc[b] = R(1);
+  }
+  for (int b = 4; b < s->q; ++b) {
+    r.w[b] = R(s->omega[b - 4]);
+    r.wc[b] = R(1.0 - s->omega[b - 4]);
+  }
+  return r;
+}
+
+template <typename R>
+cmlbm::ForceArgs<R> make_force(const cmlbm_sim* s) {
+  cmlbm::ForceArgs<R> f{};
+  for (int i = 0; i < 3; ++i) f.uni[i] = R(s->F[i] * s->fscale);
+  f.field = static_cast<const R*>(s->Ffield);
+  f.scale = R(s->fscale);
+  return f;
+}
+
+template <typename R>
+cmlbm::AuxArgs<R> make_aux(const cmlbm_sim* s, const void* in0, void* out0, void* out1) {
+  cmlbm::AuxArgs<R> a{};
+  a.g = s->g;
+  a.in0 = in0;
+  a.out0 = out0;
+  a.out1 = out1;
+  a.mask = s->mask;
+  a.force = make_force<R>(s);
+  return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* cmlbm_version(void) { return "0.1.0"; }
+
+const char* cmlbm_status_string(cmlbm_status code) {
+  switch (code) {
+    case CMLBM_OK: return "ok";
+    case CMLBM_EINVAL: return "invalid argument";
+    case CMLBM_EUNSUPPORTED: return "unsupported";
+    case CMLBM_EDEVICE: return "device error";
+    case CMLBM_ENOMEM: return "out of device memory";
+    case CMLBM_ESTATE: return "invalid call order";
+  }
+  return "unknown status";
+}
+
+const char* cmlbm_last_error(const cmlbm_sim* sim) {
+  if (!sim) return g_create_error.c_str();
+  return sim->err.c_str();
+}
+
+cmlbm_status cmlbm_create(int q, int nx, int ny, int nz, int precision, cmlbm_sim** out) {
+  g_create_error.clear();
+  if (!out) {
+    g_create_error = "out is NULL";
+    return CMLBM_EINVAL;
+  }
+  *out = nullptr;
+  if (q != 15 && q != 27) {
+    g_create_error = "q must be 15 or 27";
+    return CMLBM_EINVAL;
+  }
+  if (nx < 1 || ny < 1 || nz < 1 || nx > 65535 || ny > 65535 || nz > 65535) {
+    g_create_error = "lattice dimensions must be in [1, 65535]";
+    return CMLBM_EINVAL;
+  }
+  const uint64_t N = uint64_t(nx) * uint64_t(ny) * uint64_t(nz);
+  if (N >= (uint64_t(1) << 31)) {
+    g_create_error = "nx*ny*nz must be below 2^31";
+    return CMLBM_EINVAL;
+  }
+  if (precision < CMLBM_F64 || precision > CMLBM_F32_BF16DEV) {
+    g_create_error = "unknown precision";
+    return CMLBM_EINVAL;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+    g_create_error = "no HIP device";
+    return CMLBM_EDEVICE;
+  }
+  cmlbm_sim* s = new cmlbm_sim();
+  s->q = q;
+  s->prec = precision;
+  hipGetDevice(&s->device);
+  s->g.nx = nx;
+  s->g.ny = ny;
+  s->g.nz = nz;
+  s->g.nxy = uint32_t(nx) * uint32_t(ny);
+  s->g.N = N;
+  for (double& w : s->omega) w = 1.0;
+  if (hipMalloc(&s->totals_partials, sizeof(double) * 4 * cmlbm::kTotalsBlocks) != hipSuccess ||
+      hipMalloc(&s->totals_out, sizeof(double) * 4) != hipSuccess) {
+    g_create_error = "device scratch allocation failed";
+    cmlbm_destroy(s);
+    return CMLBM_ENOMEM;
+  }
+  *out = s;
+  return CMLBM_OK;
+}
+
+void cmlbm_destroy(cmlbm_sim* sim) {
+  if (!sim) return;
+  if (sim->totals_partials) hipFree(sim->totals_partials);
+  if (sim->totals_out) hipFree(sim->totals_out);
+  if (sim->adj_partials) hipFree(sim->adj_partials);
+  delete sim;
+}
+
+cmlbm_status cmlbm_set_rates(cmlbm_sim* s, const double* omega, int n) {
+  if (!s) return CMLBM_EINVAL;
+  if (!omega) return fail(s, CMLBM_EINVAL, "omega is NULL");
+  if (n != s->q - 4) return fail(s, CMLBM_EINVAL, "expected q-4 rates (omega_4 .. omega_(q-1))");
+  for (int i = 0; i < n; ++i) {
+    if (!(omega[i] > 0.0 && omega[i] < 2.0))
+      return fail(s, CMLBM_EINVAL, "omega_" + std::to_string(i + 4) + " outside (0, 2)");
+  }
+  for (int i = 0; i < n; ++i) s->omega[i] = omega[i];
+  return ok(s);
+}
+
+cmlbm_status cmlbm_set_force_uniform(cmlbm_sim* s, double fx, double fy, double fz) {
+  if (!s) return CMLBM_EINVAL;
+  if (!std::isfinite(fx) || !std::isfinite(fy) || !std::isfinite(fz))
+    return fail(s, CMLBM_EINVAL, "force must be finite");
+  s->F[0] = fx;
+  s->F[1] = fy;
+  s->F[2] = fz;
+  s->Ffield = nullptr;
+  return ok(s);
+}
+
+cmlbm_status cmlbm_set_force_field(cmlbm_sim* s, const void* F_dev) {
+  if (!s) return CMLBM_EINVAL;
+  s->Ffield = F_dev;
+  if (!F_dev) s->F[0] = s->F[1] = s->F[2] = 0.0;
+  return ok(s);
+}
+
+cmlbm_status cmlbm_set_force_scale(cmlbm_sim* s, double scale) {
+  if (!s) return CMLBM_EINVAL;
+  if (!std::isfinite(scale)) return fail(s, CMLBM_EINVAL, "scale must be finite");
+  s->fscale = scale;
+  return ok(s);
+}
+
+cmlbm_status cmlbm_set_mask(cmlbm_sim* s, const uint8_t* mask_dev) {
+  if (!s) return CMLBM_EINVAL;
+  s->mask = mask_dev;
+  return ok(s);
+}
+
+cmlbm_status cmlbm_init_equilibrium(cmlbm_sim* s, const void* rho_dev, const void* u_dev, void* f_pre_dev,
+                                    void* f_post_dev, void* stream) {
+  if (!s) return CMLBM_EINVAL;
+  if (!rho_dev || !u_dev || !f_pre_dev || !f_post_dev) return fail(s, CMLBM_EINVAL, "NULL buffer");
+  if (f_pre_dev == f_post_dev) return fail(s, CMLBM_EINVAL, "f_pre and f_post must differ");
+  hipError_t e = cmlbm::launch_init(s->q, s->prec, s->g, rho_dev, u_dev, make_force<double>(s),
+                                    make_force<float>(s), s->mask, f_pre_dev, f_post_dev,
+                                    static_cast<hipStream_t>(stream));
+  return check_hip(s, e, "init_equilibrium");
+}
+
+cmlbm_status cmlbm_step(cmlbm_sim* s, const void* f_in, void* f_out, void* stream) {
+  if (!s) return CMLBM_EINVAL;
+  if (!f_in || !f_out) return fail(s, CMLBM_EINVAL, "NULL population buffer");
+  if (f_in == f_out) return fail(s, CMLBM_EINVAL, "f_in and f_out must differ (pull streaming)");
+  cmlbm::StepArgs<double> a64{};
+  cmlbm::StepArgs<float> a32{};
+  if (s->prec == CMLBM_F64) {
+    a64.g = s->g;
+    a64.fin = f_in;
+    a64.fout = f_out;
+    a64.mask = s->mask;
+    a64.force = make_force<double>(s);
+    a64.rates = make_rates<double>(s);
+  } else {
+    a32.g = s->g;
+    a32.fin = f_in;
+    a32.fout = f_out;
+    a32.mask = s->mask;
+    a32.force = make_force<float>(s);
+    a32.rates = make_rates<float>(s);
+  }
+  return check_hip(s, cmlbm::launch_step(s->q, s->prec, a64, a32, static_cast<hipStream_t>(stream)), "step");
+}
+
+cmlbm_status cmlbm_run(cmlbm_sim* s, void* f_a, void* f_b, int nsteps, void* stream, int* result_in_b) {
+  if (!s) return CMLBM_EINVAL;
+  if (nsteps < 0) return fail(s, CMLBM_EINVAL, "nsteps < 0");
+  if (!f_a || !f_b) return fail(s, CMLBM_EINVAL, "NULL population buffer");
+  if (f_a == f_b) return fail(s, CMLBM_EINVAL, "f_a and f_b must differ");
+  void* bufs[2] = {f_a, f_b};
+  for (int n = 0; n < nsteps; ++n) {
+    cmlbm_status st = cmlbm_step(s, bufs[n & 1], bufs[(n + 1) & 1], stream);
+    if (st != CMLBM_OK) return st;
+  }
+  if (result_in_b) *result_in_b = nsteps & 1;
+  return ok(s);
+}
+
+cmlbm_status cmlbm_gather_precollision(cmlbm_sim* s, const void* f_post, void* f_pre, void* stream) {
+  if (!s) return CMLBM_EINVAL;
+  if (!f_post || !f_pre) return fail(s, CMLBM_EINVAL, "NULL buffer");
+  if (f_post == f_pre) return fail(s, CMLBM_EINVAL, "f_post and f_pre must differ");
+  hipError_t e = cmlbm::launch_gather(s->q, s->prec, make_aux<double>(s, f_post, f_pre, nullptr),
+                                      make_aux<float>(s, f_post, f_pre, nullptr), static_cast<hipStream_t>(stream));
+  return check_hip(s, e, "gather_precollision");
+}
+
+cmlbm_status cmlbm_macroscopic(cmlbm_sim* s, const void* f_post, void* rho, void* u, void* stream) {
+  if (!s) return CMLBM_EINVAL;
+  if (!f_post || !rho || !u) return fail(s, CMLBM_EINVAL, "NULL buffer");
+  hipError_t e = cmlbm::launch_macro(s->q, s->prec, make_aux<double>(s, f_post, rho, u),
+                                     make_aux<float>(s, f_post, rho, u), static_cast<hipStream_t>(stream));
+  return check_hip(s, e, "macroscopic");
+}
+
+cmlbm_status cmlbm_totals(cmlbm_sim* s, const void* f_post, double out4[4], void* stream) {
+  if (!s) return CMLBM_EINVAL;
+  if (!f_post || !out4) return fail(s, CMLBM_EINVAL, "NULL buffer");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = cmlbm::launch_totals(s->q, s->prec, make_aux<double>(s, f_post, nullptr, nullptr),
+                                      make_aux<float>(s, f_post, nullptr, nullptr), s->totals_partials,
+                                      cmlbm::kTotalsBlocks, s->totals_out, st);
+  if (e != hipSuccess) return check_hip(s, e, "totals");
+  e = hipMemcpyAsync(out4, s->totals_out, sizeof(double) * 4, hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess) return check_hip(s, e, "totals copy");
+  return check_hip(s, hipStreamSynchronize(st), "totals sync");
+}
+
+cmlbm_status cmlbm_adjoint_step(cmlbm_sim* s, const void* f_post_prev, const void* lam_next, void* lam,
+                                double* dLdF_dev, double* dLdomega_dev, void* stream) {
+  if (!s) return CMLBM_EINVAL;
+  if (s->q != 27) return fail(s, CMLBM_EUNSUPPORTED, "the adjoint step is provided for D3Q27");
+  if (!f_post_prev || !lam_next || !lam || !dLdF_dev || !dLdomega_dev) return fail(s, CMLBM_EINVAL, "NULL buffer");
+  if (lam == lam_next || lam == f_post_prev || lam_next == f_post_prev)
+    return fail(s, CMLBM_EINVAL, "lam, lam_next and f_post_prev must differ");
+  const int nblk = cmlbm::adjoint_blocks(s->g);
+  if (nblk > s->adj_nblk) {
+    if (s->adj_partials) hipFree(s->adj_partials);
+    s->adj_partials = nullptr;
+    s->adj_nblk = 0;
+    if (hipMalloc(&s->adj_partials, sizeof(double) * 26 * size_t(nblk)) != hipSuccess)
+      return fail(s, CMLBM_ENOMEM, "adjoint scratch allocation failed");
+    s->adj_nblk = nblk;
+  }
+  cmlbm::AdjArgs<double> a64{};
+  cmlbm::AdjArgs<float> a32{};
+  if (s->prec == CMLBM_F64) {
+    a64.g = s->g;
+    a64.fpost = f_post_prev;
+    a64.lam_next = static_cast<const double*>(lam_next);
+    a64.lam = static_cast<double*>(lam);
+    a64.dLdF = dLdF_dev;
+    a64.mask = s->mask;
+    a64.force = make_force<double>(s);
+    a64.rates = make_rates<double>(s);
+  } else {
+    a32.g = s->g;
+    a32.fpost = f_post_prev;
+    a32.lam_next = static_cast<const float*>(lam_next);
+    a32.lam = static_cast<float*>(lam);
+    a32.dLdF = dLdF_dev;
+    a32.mask = s->mask;
+    a32.force = make_force<float>(s);
+    a32.rates = make_rates<float>(s);
+  }
+  double* dLdF_uniform = s->Ffield ? nullptr : dLdF_dev;
+  hipError_t e = cmlbm::launch_adjoint(s->prec, a64, a32, s->adj_partials, nblk, dLdomega_dev, dLdF_uniform,
+                                       static_cast<hipStream_t>(stream));
+  return check_hip(s, e, "adjoint_step");
+}
+
+}  // extern "C"

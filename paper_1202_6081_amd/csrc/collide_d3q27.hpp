@@ -1,0 +1,423 @@
+// D3Q27 central-moment collision with forcing, and its hand-written adjoint.
+//
+// The cascaded collision of Premnath & Banerjee (arXiv:1202.6081, Sec. 7 and
+// Sec. 8) produces post-collision populations whose central moments about the
+// local velocity u are the pre-collision ones relaxed toward the factorized
+// attractors.  On D3Q27 the central moments of all 27 monomials
+// (e_x-u_x)^a (e_y-u_y)^b (e_z-u_z)^c, a, b, c in {0, 1, 2}, factorize per axis,
+// so the raw-moment sums of Appendix B followed by the binomial shift of Sec. 6
+// become three passes of 3-point transforms over a 3x3x3 cube, and the return
+// to populations (the K g + S rows of Sec. 8) becomes three inverse passes.
+//
+// Source term (Sec. 5, Eq. discretecentralsources): S changes only the three
+// first-order central moments, by F.  Adding S to fbar therefore sets the
+// first central moments to -F/2 + F = F/2, which the collision conserves; the
+// velocity includes F/2 (Eq. velocitycalculation).
+//
+// Cube layout: m[a*9 + b*3 + c] holds the population with e = (a-1, b-1, c-1)
+// before the forward passes and the central moment with exponents (a, b, c)
+// after them.
+#pragma once
+
+#include "lattice.hpp"
+
+namespace cmlbm {
+
+constexpr int K3(int a, int b, int c) { return a * 9 + b * 3 + c; }
+
+// Relaxation rates indexed by the paper's kernel number b = 4..26 (entries
+// 0..3 unused): w[b] = omega_b and wc[b] = 1 - omega_b.
+template <typename R>
+struct Rates {
+  R w[27];
+  R wc[27];
+};
+
+// -- 3-point transforms along one axis --------------------------------------
+// Populations (p_-, p_0, p_+) -> central moments (k0, k1, k2) about u:
+// k_n = sum_e p_e (e - u)^n.
+template <typename R>
+CMLBM_HD void fwd_line(R& a, R& b, R& c, R u) {
+  const R k0 = a + b + c;
+  const R d = c - a;
+  const R k1 = d - u * k0;
+  const R k2 = (c + a) - u * (d + k1);
+  a = k0;
+  b = k1;
+  c = k2;
+}
+
+// Central moments (m0, m1, m2) about u -> populations (p_-, p_0, p_+).
+template <typename R>
+CMLBM_HD void inv_line(R& a, R& b, R& c, R u) {
+  const R m0 = a, m1 = b, m2 = c;
+  const R r1 = m1 + u * m0;              // raw first moment
+  const R r2 = m2 + u * (m1 + r1);       // raw second moment
+  a = R(0.5) * (r2 - r1);
+  b = m0 - r2;
+  c = R(0.5) * (r2 + r1);
+}
+
+// Adjoint of fwd_line: (a, b, c) are the forward inputs, (ga, gb, gc) hold
+// the adjoints of the outputs on entry and of the inputs on exit.
+template <typename R>
+CMLBM_HD void fwd_line_adj(R a, R b, R c, R u, R& ga, R& gb, R& gc, R& gu) {
+  const R k0 = a + b + c;
+  const R d = c - a;
+  const R k1 = d - u * k0;
+  const R g0 = ga, g1 = gb, g2 = gc;
+  gu -= (d + k1) * g2;
+  const R gt = -u * g2;                   // adjoint of (d + k1)
+  const R g1t = g1 + gt;
+  const R gd = gt + g1t;
+  gu -= k0 * g1t;
+  const R g0t = g0 - u * g1t;
+  ga = g2 - gd + g0t;
+  gb = g0t;
+  gc = g2 + gd + g0t;
+}
+
+// Adjoint of inv_line, same conventions.
+template <typename R>
+CMLBM_HD void inv_line_adj(R m0, R m1, R m2, R u, R& ga, R& gb, R& gc, R& gu) {
+  const R r1 = m1 + u * m0;
+  const R pa = ga, pb = gb, pc = gc;
+  const R gr2 = R(0.5) * (pa + pc) - pb;
+  R gr1 = R(0.5) * (pc - pa);
+  R gm0 = pb;
+  const R gm2 = gr2;
+  gu += gr2 * (m1 + r1);
+  R gm1 = gr2 * u;
+  gr1 += gr2 * u;
+  gm1 += gr1;
+  gm0 += gr1 * u;
+  gu += gr1 * m0;
+  ga = gm0;
+  gb = gm1;
+  gc = gm2;
+}
+
+// Base index and stride of line l (0..8) along an axis (0 = x, 1 = y, 2 = z).
+template <int AXIS>
+CMLBM_HDC int line_base(int l) {
+  return AXIS == 2 ? (l / 3) * 9 + (l % 3) * 3 : AXIS == 1 ? (l / 3) * 9 + (l % 3) : l;
+}
+template <int AXIS>
+CMLBM_HDC int line_stride() {
+  return AXIS == 0 ? 9 : AXIS == 1 ? 3 : 1;
+}
+
+template <int AXIS, typename R>
+CMLBM_HD void fwd_pass(R (&m)[27], R u) {
+  constexpr int S = line_stride<AXIS>();
+#pragma unroll
+  for (int l = 0; l < 9; ++l) {
+    const int o = line_base<AXIS>(l);
+    fwd_line(m[o], m[o + S], m[o + 2 * S], u);
+  }
+}
+
+template <int AXIS, typename R>
+CMLBM_HD void inv_pass(R (&m)[27], R u) {
+  constexpr int S = line_stride<AXIS>();
+#pragma unroll
+  for (int l = 0; l < 9; ++l) {
+    const int o = line_base<AXIS>(l);
+    inv_line(m[o], m[o + S], m[o + 2 * S], u);
+  }
+}
+
+template <int AXIS, typename R>
+CMLBM_HD void fwd_pass_adj(const R (&m)[27], R u, R (&g)[27], R& gu) {
+  constexpr int S = line_stride<AXIS>();
+#pragma unroll
+  for (int l = 0; l < 9; ++l) {
+    const int o = line_base<AXIS>(l);
+    fwd_line_adj(m[o], m[o + S], m[o + 2 * S], u, g[o], g[o + S], g[o + 2 * S], gu);
+  }
+}
+
+template <int AXIS, typename R>
+CMLBM_HD void inv_pass_adj(const R (&m)[27], R u, R (&g)[27], R& gu) {
+  constexpr int S = line_stride<AXIS>();
+#pragma unroll
+  for (int l = 0; l < 9; ++l) {
+    const int o = line_base<AXIS>(l);
+    inv_line_adj(m[o], m[o + S], m[o + 2 * S], u, g[o], g[o + S], g[o + 2 * S], gu);
+  }
+}
+
+// Density and velocity of cube-ordered populations (Eqs. densitycalculation,
+// velocitycalculation).
+template <typename R>
+CMLBM_HD void moments0_27(const R (&m)[27], R Fx, R Fy, R Fz, R& rho, R& ux, R& uy, R& uz) {
+  R s[3] = {R(0), R(0), R(0)};   // sums over the planes e_x = -1, 0, +1
+  R ty[3] = {R(0), R(0), R(0)};
+  R tz[3] = {R(0), R(0), R(0)};
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const R v = m[K3(a, b, c)];
+        s[a] += v;
+        ty[b] += v;
+        tz[c] += v;
+      }
+  rho = s[0] + s[1] + s[2];
+  const R inv = R(1) / rho;
+  ux = (s[2] - s[0] + R(0.5) * Fx) * inv;
+  uy = (ty[2] - ty[0] + R(0.5) * Fy) * inv;
+  uz = (tz[2] - tz[0] + R(0.5) * Fz) * inv;
+}
+
+// Relax the central moments in m (cube layout) in place.  Returns the
+// post-collision second-order diagonal moments through kxx, kyy, kzz.
+template <typename R>
+CMLBM_HD void relax27(R (&m)[27], R rho, R Fx, R Fy, R Fz, const Rates<R>& p) {
+  // conserved: density and first central moments F/2
+  m[K3(0, 0, 0)] = rho;
+  m[K3(1, 0, 0)] = R(0.5) * Fx;
+  m[K3(0, 1, 0)] = R(0.5) * Fy;
+  m[K3(0, 0, 1)] = R(0.5) * Fz;
+  // second order, off-diagonal (g4, g5, g6): attractor 0
+  m[K3(1, 1, 0)] *= p.wc[4];
+  m[K3(1, 0, 1)] *= p.wc[5];
+  m[K3(0, 1, 1)] *= p.wc[6];
+  // second order, diagonal: xx-yy (g7), xx+yy-2zz (g8) toward 0, xx+yy+zz (g9) toward rho
+  const R xx = m[K3(2, 0, 0)], yy = m[K3(0, 2, 0)], zz = m[K3(0, 0, 2)];
+  const R d1 = p.wc[7] * (xx - yy);
+  const R d2 = p.wc[8] * (xx + yy - R(2) * zz);
+  const R t = p.wc[9] * (xx + yy + zz) + p.w[9] * rho;
+  const R kxx = (R(2) * t + d2 + R(3) * d1) * R(1.0 / 6.0);
+  const R kyy = (R(2) * t + d2 - R(3) * d1) * R(1.0 / 6.0);
+  const R kzz = (t - d2) * R(1.0 / 3.0);
+  m[K3(2, 0, 0)] = kxx;
+  m[K3(0, 2, 0)] = kyy;
+  m[K3(0, 0, 2)] = kzz;
+  // third order: xyy+xzz (g10) with xyy-xzz (g13), and the y, z analogues
+  {
+    const R s = p.wc[10] * (m[K3(1, 2, 0)] + m[K3(1, 0, 2)]);
+    const R d = p.wc[13] * (m[K3(1, 2, 0)] - m[K3(1, 0, 2)]);
+    m[K3(1, 2, 0)] = R(0.5) * (s + d);
+    m[K3(1, 0, 2)] = R(0.5) * (s - d);
+  }
+  {
+    const R s = p.wc[11] * (m[K3(2, 1, 0)] + m[K3(0, 1, 2)]);
+    const R d = p.wc[14] * (m[K3(2, 1, 0)] - m[K3(0, 1, 2)]);
+    m[K3(2, 1, 0)] = R(0.5) * (s + d);
+    m[K3(0, 1, 2)] = R(0.5) * (s - d);
+  }
+  {
+    const R s = p.wc[12] * (m[K3(2, 0, 1)] + m[K3(0, 2, 1)]);
+    const R d = p.wc[15] * (m[K3(2, 0, 1)] - m[K3(0, 2, 1)]);
+    m[K3(2, 0, 1)] = R(0.5) * (s + d);
+    m[K3(0, 2, 1)] = R(0.5) * (s - d);
+  }
+  m[K3(1, 1, 1)] *= p.wc[16];
+  // fourth order, diagonal pairs (g17, g18, g19) toward the factorized attractors
+  {
+    const R axy = kxx * kyy, axz = kxx * kzz, ayz = kyy * kzz;
+    const R A = m[K3(2, 2, 0)], B = m[K3(2, 0, 2)], C = m[K3(0, 2, 2)];
+    const R q1 = p.wc[17] * (A + B + C) + p.w[17] * (axy + axz + ayz);
+    const R q2 = p.wc[18] * (A + B - R(2) * C) + p.w[18] * (axy + axz - R(2) * ayz);
+    const R q3 = p.wc[19] * (A - B) + p.w[19] * (axy - axz);
+    const R ab = (R(2) * q1 + q2) * R(1.0 / 3.0);
+    m[K3(0, 2, 2)] = (q1 - q2) * R(1.0 / 3.0);
+    m[K3(2, 2, 0)] = R(0.5) * (ab + q3);
+    m[K3(2, 0, 2)] = R(0.5) * (ab - q3);
+  }
+  m[K3(2, 1, 1)] *= p.wc[20];
+  m[K3(1, 2, 1)] *= p.wc[21];
+  m[K3(1, 1, 2)] *= p.wc[22];
+  // fifth order
+  m[K3(1, 2, 2)] *= p.wc[23];
+  m[K3(2, 1, 2)] *= p.wc[24];
+  m[K3(2, 2, 1)] *= p.wc[25];
+  // sixth order toward kxx kyy kzz (g26)
+  m[K3(2, 2, 2)] = p.wc[26] * m[K3(2, 2, 2)] + p.w[26] * (kxx * kyy * kzz);
+}
+
+// Full collision: cube-ordered pre-collision populations in, post-collision out.
+template <typename R>
+CMLBM_HD void collide27(R (&m)[27], R Fx, R Fy, R Fz, const Rates<R>& p) {
+  R rho, ux, uy, uz;
+  moments0_27(m, Fx, Fy, Fz, rho, ux, uy, uz);
+  fwd_pass<2>(m, uz);
+  fwd_pass<1>(m, uy);
+  fwd_pass<0>(m, ux);
+  relax27(m, rho, Fx, Fy, Fz, p);
+  inv_pass<0>(m, ux);
+  inv_pass<1>(m, uy);
+  inv_pass<2>(m, uz);
+}
+
+// Adjoint of relax27.  m: pre-relaxation central moments (unchanged).  g: on
+// entry the adjoint of the relaxed moments, on exit the adjoint of m.  Adds to
+// grho, gF*, gw[b] (adjoint of omega_b).
+template <typename R>
+CMLBM_HD void relax27_adj(const R (&m)[27], R rho, const Rates<R>& p, R (&g)[27], R& grho,
+                                            R& gFx, R& gFy, R& gFz, R (&gw)[27]) {
+  // recompute the second-order post values and attractor inputs
+  const R xx = m[K3(2, 0, 0)], yy = m[K3(0, 2, 0)], zz = m[K3(0, 0, 2)];
+  const R D1 = xx - yy, D2 = xx + yy - R(2) * zz, T = xx + yy + zz;
+  const R d1 = p.wc[7] * D1, d2 = p.wc[8] * D2, t = p.wc[9] * T + p.w[9] * rho;
+  const R kxx = (R(2) * t + d2 + R(3) * d1) * R(1.0 / 6.0);
+  const R kyy = (R(2) * t + d2 - R(3) * d1) * R(1.0 / 6.0);
+  const R kzz = (t - d2) * R(1.0 / 3.0);
+  R gkxx = R(0), gkyy = R(0), gkzz = R(0);
+
+  // sixth order
+  {
+    const R G = g[K3(2, 2, 2)];
+    const R P = kxx * kyy * kzz;
+    gw[26] += (P - m[K3(2, 2, 2)]) * G;
+    const R gP = p.w[26] * G;
+    gkxx += gP * kyy * kzz;
+    gkyy += gP * kxx * kzz;
+    gkzz += gP * kxx * kyy;
+    g[K3(2, 2, 2)] = p.wc[26] * G;
+  }
+  // fifth order and fourth-order off-diagonal: m~ = (1 - w) m
+#define CMLBM_SCALE_ADJ(I, B)         \
+  {                                   \
+    const R G = g[I];                 \
+    gw[B] -= m[I] * G;                \
+    g[I] = p.wc[B] * G;               \
+  }
+  CMLBM_SCALE_ADJ(K3(1, 2, 2), 23)
+  CMLBM_SCALE_ADJ(K3(2, 1, 2), 24)
+  CMLBM_SCALE_ADJ(K3(2, 2, 1), 25)
+  CMLBM_SCALE_ADJ(K3(2, 1, 1), 20)
+  CMLBM_SCALE_ADJ(K3(1, 2, 1), 21)
+  CMLBM_SCALE_ADJ(K3(1, 1, 2), 22)
+  // fourth order diagonal
+  {
+    const R axy = kxx * kyy, axz = kxx * kzz, ayz = kyy * kzz;
+    const R A = m[K3(2, 2, 0)], B = m[K3(2, 0, 2)], C = m[K3(0, 2, 2)];
+    const R Q1 = A + B + C, Q2 = A + B - R(2) * C, Q3 = A - B;
+    const R a1 = axy + axz + ayz, a2 = axy + axz - R(2) * ayz, a3 = axy - axz;
+    const R gA = g[K3(2, 2, 0)], gB = g[K3(2, 0, 2)], gC = g[K3(0, 2, 2)];
+    const R gab = R(0.5) * (gA + gB);
+    const R gq3 = R(0.5) * (gA - gB);
+    const R gq1 = (gC + R(2) * gab) * R(1.0 / 3.0);
+    const R gq2 = (gab - gC) * R(1.0 / 3.0);
+    gw[17] += (a1 - Q1) * gq1;
+    gw[18] += (a2 - Q2) * gq2;
+    gw[19] += (a3 - Q3) * gq3;
+    const R ga1 = p.w[17] * gq1, ga2 = p.w[18] * gq2, ga3 = p.w[19] * gq3;
+    const R gQ1 = p.wc[17] * gq1, gQ2 = p.wc[18] * gq2, gQ3 = p.wc[19] * gq3;
+    const R gaxy = ga1 + ga2 + ga3, gaxz = ga1 + ga2 - ga3, gayz = ga1 - R(2) * ga2;
+    gkxx += gaxy * kyy + gaxz * kzz;
+    gkyy += gaxy * kxx + gayz * kzz;
+    gkzz += gaxz * kxx + gayz * kyy;
+    g[K3(2, 2, 0)] = gQ1 + gQ2 + gQ3;
+    g[K3(2, 0, 2)] = gQ1 + gQ2 - gQ3;
+    g[K3(0, 2, 2)] = gQ1 - R(2) * gQ2;
+  }
+  // third order
+  CMLBM_SCALE_ADJ(K3(1, 1, 1), 16)
+#define CMLBM_PAIR_ADJ(IA, IB, BS, BD)                  \
+  {                                                     \
+    const R gs = R(0.5) * (g[IA] + g[IB]);              \
+    const R gd = R(0.5) * (g[IA] - g[IB]);              \
+    gw[BS] -= (m[IA] + m[IB]) * gs;                     \
+    gw[BD] -= (m[IA] - m[IB]) * gd;                     \
+    const R a = p.wc[BS] * gs, b = p.wc[BD] * gd;       \
+    g[IA] = a + b;                                      \
+    g[IB] = a - b;                                      \
+  }
+  CMLBM_PAIR_ADJ(K3(1, 2, 0), K3(1, 0, 2), 10, 13)
+  CMLBM_PAIR_ADJ(K3(2, 1, 0), K3(0, 1, 2), 11, 14)
+  CMLBM_PAIR_ADJ(K3(2, 0, 1), K3(0, 2, 1), 12, 15)
+#undef CMLBM_PAIR_ADJ
+  // second order diagonal; total adjoint of kxx, kyy, kzz
+  {
+    const R Gx = g[K3(2, 0, 0)] + gkxx, Gy = g[K3(0, 2, 0)] + gkyy, Gz = g[K3(0, 0, 2)] + gkzz;
+    const R gt = (Gx + Gy) * R(1.0 / 3.0) + Gz * R(1.0 / 3.0);
+    const R gd2 = (Gx + Gy) * R(1.0 / 6.0) - Gz * R(1.0 / 3.0);
+    const R gd1 = R(0.5) * (Gx - Gy);
+    gw[7] -= D1 * gd1;
+    gw[8] -= D2 * gd2;
+    gw[9] += (rho - T) * gt;
+    grho += p.w[9] * gt;
+    const R gD1 = p.wc[7] * gd1, gD2 = p.wc[8] * gd2, gT = p.wc[9] * gt;
+    g[K3(2, 0, 0)] = gD1 + gD2 + gT;
+    g[K3(0, 2, 0)] = -gD1 + gD2 + gT;
+    g[K3(0, 0, 2)] = R(-2) * gD2 + gT;
+  }
+  CMLBM_SCALE_ADJ(K3(1, 1, 0), 4)
+  CMLBM_SCALE_ADJ(K3(1, 0, 1), 5)
+  CMLBM_SCALE_ADJ(K3(0, 1, 1), 6)
+#undef CMLBM_SCALE_ADJ
+  // conserved rows were overwritten by rho and F/2
+  grho += g[K3(0, 0, 0)];
+  gFx += R(0.5) * g[K3(1, 0, 0)];
+  gFy += R(0.5) * g[K3(0, 1, 0)];
+  gFz += R(0.5) * g[K3(0, 0, 1)];
+  g[K3(0, 0, 0)] = g[K3(1, 0, 0)] = g[K3(0, 1, 0)] = g[K3(0, 0, 1)] = R(0);
+}
+
+// Adjoint of collide27.  f: cube-ordered pre-collision populations.  g: on
+// entry the adjoint of the post-collision populations, on exit the adjoint of
+// f.  s: scratch.  Adds the force and rate adjoints.
+template <typename R>
+CMLBM_HD void collide27_adj(const R (&f)[27], R Fx, R Fy, R Fz, const Rates<R>& p, R (&g)[27],
+                                              R (&s)[27], R& gFx, R& gFy, R& gFz, R (&gw)[27]) {
+  R rho, ux, uy, uz;
+  moments0_27(f, Fx, Fy, Fz, rho, ux, uy, uz);
+  R gux = R(0), guy = R(0), guz = R(0), grho = R(0);
+
+  // relaxed moments, then replay the inverse passes to get each pass's input
+#pragma unroll
+  for (int k = 0; k < 27; ++k) s[k] = f[k];
+  fwd_pass<2>(s, uz);
+  fwd_pass<1>(s, uy);
+  fwd_pass<0>(s, ux);
+  relax27(s, rho, Fx, Fy, Fz, p);
+  inv_pass<0>(s, ux);
+  inv_pass<1>(s, uy);                        // s = input of the z inverse pass
+  inv_pass_adj<2>(s, uz, g, guz);
+  fwd_pass<1>(s, uy);                        // undo the y pass: s = input of the y inverse pass
+  inv_pass_adj<1>(s, uy, g, guy);
+  fwd_pass<0>(s, ux);                        // s = relaxed central moments
+  inv_pass_adj<0>(s, ux, g, gux);
+
+  // relaxation (needs the pre-relaxation moments)
+#pragma unroll
+  for (int k = 0; k < 27; ++k) s[k] = f[k];
+  fwd_pass<2>(s, uz);
+  fwd_pass<1>(s, uy);
+  fwd_pass<0>(s, ux);
+  relax27_adj(s, rho, p, g, grho, gFx, gFy, gFz, gw);
+
+  // forward passes z, y, x in reverse order, recomputing each pass's input
+#pragma unroll
+  for (int k = 0; k < 27; ++k) s[k] = f[k];
+  fwd_pass<2>(s, uz);
+  fwd_pass<1>(s, uy);                        // s = input of the x pass
+  fwd_pass_adj<0>(s, ux, g, gux);
+#pragma unroll
+  for (int k = 0; k < 27; ++k) s[k] = f[k];
+  fwd_pass<2>(s, uz);                        // s = input of the y pass
+  fwd_pass_adj<1>(s, uy, g, guy);
+  fwd_pass_adj<2>(f, uz, g, guz);
+
+  // u = (sum f e + F/2) / rho, rho = sum f
+  const R inv = R(1) / rho;
+  const R gjx = gux * inv, gjy = guy * inv, gjz = guz * inv;
+  grho -= (ux * gux + uy * guy + uz * guz) * inv;
+  gFx += R(0.5) * gjx;
+  gFy += R(0.5) * gjy;
+  gFz += R(0.5) * gjz;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        g[K3(a, b, c)] += grho + R(a - 1) * gjx + R(b - 1) * gjy + R(c - 1) * gjz;
+}
+
+}  // namespace cmlbm

@@ -1,0 +1,81 @@
+// Internal interface between the C ABI (api.cpp) and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+
+#include "collide_d3q27.hpp"   // Rates<R>
+
+namespace cmlbm {
+
+struct Geom {
+  int nx, ny, nz;
+  uint32_t nxy;
+  uint64_t N;   // nodes
+};
+
+// Body force: a uniform vector (already multiplied by the time scale) or a
+// field [3][nz][ny][nx] times `scale`.
+template <typename FT>
+struct ForceArgs {
+  FT uni[3];
+  const FT* field;
+  FT scale;
+};
+
+template <typename R>
+struct StepArgs {
+  Geom g;
+  const void* fin;
+  void* fout;
+  const uint8_t* mask;
+  ForceArgs<R> force;
+  Rates<R> rates;
+};
+
+template <typename R>
+struct AuxArgs {
+  Geom g;
+  const void* in0;
+  void* out0;
+  void* out1;
+  const uint8_t* mask;
+  ForceArgs<R> force;
+};
+
+template <typename R>
+struct AdjArgs {
+  Geom g;
+  const void* fpost;      // forward post-collision state of step n (storage type)
+  const R* lam_next;      // dL/dfbar^{n+1} (compute type)
+  R* lam;                 // dL/dfbar^n (compute type)
+  double* dLdF;           // [3][N], accumulated (force field mode)
+  const uint8_t* mask;
+  ForceArgs<R> force;
+  Rates<R> rates;
+};
+
+// prec: 0 FP64, 1 FP32, 2 FP32 compute / FP16 deviation storage, 3 BF16 deviations.
+hipError_t launch_step(int q, int prec, const StepArgs<double>& a64, const StepArgs<float>& a32, hipStream_t st);
+hipError_t launch_gather(int q, int prec, const AuxArgs<double>& a64, const AuxArgs<float>& a32, hipStream_t st);
+hipError_t launch_macro(int q, int prec, const AuxArgs<double>& a64, const AuxArgs<float>& a32, hipStream_t st);
+hipError_t launch_totals(int q, int prec, const AuxArgs<double>& a64, const AuxArgs<float>& a32, double* partials,
+                         int nblk, double* out4, hipStream_t st);
+hipError_t launch_init(int q, int prec, const Geom& g, const void* rho0, const void* u0, const ForceArgs<double>& f64,
+                       const ForceArgs<float>& f32, const uint8_t* mask, void* fpre, void* fpost, hipStream_t st);
+hipError_t launch_adjoint(int prec, const AdjArgs<double>& a64, const AdjArgs<float>& a32, double* partials,
+                          int nblk, double* dLdomega, double* dLdF_uniform, hipStream_t st);
+
+// Blocks of the grid-stride adjoint launch (each thread visits at most 8 nodes).
+inline int adjoint_blocks(const Geom& g) {
+  const int bx = g.nx < 256 ? ((g.nx + 63) / 64) * 64 : 256;
+  const uint64_t items = uint64_t((g.nx + bx - 1) / bx) * uint64_t(g.ny) * uint64_t(g.nz);
+  uint64_t nb = (items + 7) / 8;
+  if (nb < 1) nb = 1;
+  return int(nb);
+}
+
+constexpr int kTotalsBlocks = 2048;
+
+}  // namespace cmlbm

@@ -1,0 +1,56 @@
+"""Host-side checks of the C ABI library (no GPU needed): it loads, exports
+every symbol the header declares, and rejects bad arguments before touching a
+device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    with open(os.path.join(ROOT, "include", "cmlbm.h")) as fh:
+        text = fh.read()
+    return sorted(set(re.findall(r"\b(cmlbm_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    from paper_1202_6081_amd import cmlbm
+    assert _declared() == sorted(cmlbm.exported_symbols())
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1202_6081_amd import cmlbm
+    lib = cmlbm.load_library()
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_status_strings_and_version():
+    from paper_1202_6081_amd import cmlbm
+    lib = cmlbm.load_library()
+    assert lib.cmlbm_status_string(0) == b"ok"
+    assert lib.cmlbm_status_string(-1) == b"invalid argument"
+    assert re.match(rb"\d+\.\d+\.\d+", lib.cmlbm_version())
+
+
+@pytest.mark.parametrize("args", [(26, 8, 8, 8, 1), (27, 0, 8, 8, 1), (27, 8, 8, 8, 7), (15, 70000, 2, 2, 1),
+                                  (27, 2048, 2048, 1024, 1)])
+def test_create_rejects_bad_arguments_before_the_device(args):
+    from paper_1202_6081_amd import cmlbm
+    lib = cmlbm.load_library()
+    h = ctypes.c_void_p()
+    assert lib.cmlbm_create(*args, ctypes.byref(h)) == -1
+    assert h.value is None
+    assert lib.cmlbm_last_error(None) != b""
+
+
+def test_null_handle_and_out():
+    from paper_1202_6081_amd import cmlbm
+    lib = cmlbm.load_library()
+    assert lib.cmlbm_create(27, 4, 4, 4, 1, None) == -1
+    assert lib.cmlbm_step(None, None, None, None) == -1
+    assert lib.cmlbm_set_rates(None, None, 23) == -1
+    lib.cmlbm_destroy(None)

@@ -1,0 +1,246 @@
+"""GPU parity of the forward step (through the C ABI) against the FP64 oracle.
+
+Tolerances: FP64 mode 1e-12 relative (populations, max norm); FP32 mode 2e-5
+relative velocity L2 and 2e-6 absolute on populations; 16-bit deviation
+storage: half a unit in the last place of the stored deviation plus 2e-6.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import lbm_inputs as inp
+from gpu_helpers import (gpu_initial, gpu_pre, gpu_setup, lib, oracle_run, rel_err, shear_rates, to_dev,
+                         velocity_l2)
+from oracle import collision, lbm
+from oracle.lattice import LATTICES
+
+pytestmark = pytest.mark.gpu
+
+F64, F32, F16, BF16 = 0, 1, 2, 3
+
+
+def _fields(shape, seed, umax=0.05):
+    rng = np.random.default_rng(seed)
+    rho0 = 1.0 + 0.01 * rng.standard_normal(shape)
+    u0 = umax * rng.uniform(-1, 1, (3,) + shape)
+    return rho0, u0
+
+
+def _force(kind, shape, seed):
+    if kind is None:
+        return None
+    if kind == "uniform":
+        return np.array([2e-4, -1e-4, 5e-5])
+    return inp.gaussian_force(shape, 1e-4, seed)
+
+
+def _mask(kind, shape):
+    nz, ny, nx = shape
+    if kind is None:
+        return None
+    if kind == "duct":
+        return inp.duct_mask(nx, ny, nz)
+    solid = np.zeros(shape, dtype=bool)          # scattered obstacles + one wall
+    solid[0] = True
+    solid[nz // 2, ny // 2, nx // 3] = True
+    solid[nz // 2, 1, 2 * nx // 3] = True
+    return solid
+
+
+CASES = [
+    # q, precision, (nz, ny, nx), force, mask, steps
+    (27, F64, (5, 6, 70), "uniform", None, 3),
+    (27, F64, (6, 5, 67), "field", "walls", 3),
+    (27, F64, (9, 8, 66), "uniform", "duct", 4),
+    (15, F64, (5, 6, 70), "field", None, 3),
+    (15, F64, (6, 5, 67), "uniform", "walls", 3),
+    (27, F32, (5, 6, 70), "field", None, 3),
+    (27, F32, (9, 8, 66), "uniform", "duct", 3),
+    (15, F32, (5, 6, 70), "field", "walls", 3),
+    # degenerate lattices: every neighbour is the node itself or its mirror
+    (27, F64, (1, 1, 1), "uniform", None, 2),
+    (27, F64, (2, 3, 1), "field", None, 2),
+    (15, F64, (1, 1, 5), "field", None, 2),
+    (27, F32, (3, 1, 129), None, None, 2),
+]
+
+
+def _ids(c):
+    return f"q{c[0]}-p{c[1]}-{'x'.join(map(str, c[2]))}-{c[3]}-{c[4]}-n{c[5]}"
+
+
+@pytest.mark.parametrize("case", CASES, ids=[_ids(c) for c in CASES])
+def test_forward_matches_oracle(case):
+    q, prec, shape, fkind, mkind, steps = case
+    print(f"case {_ids(case)}", flush=True)
+    rng = np.random.default_rng(7)
+    omega = list(rng.uniform(0.7, 1.9, q - 4))
+    F = _force(fkind, shape, 3)
+    solid = _mask(mkind, shape)
+    rho0, u0 = _fields(shape, 5)
+    fluid = None if solid is None else ~solid
+    sim = gpu_setup(q, shape, prec, omega, F, solid)
+    f_post, f_pre0 = gpu_initial(sim, rho0, u0)
+    states = oracle_run(q, rho0, u0, F, omega, steps, solid)
+    tol = 1e-12 if prec == F64 else None
+    # initial pre-collision state, from the kernel that builds it and from the
+    # post-collision buffer through the pull
+    for got in (f_pre0.double().cpu().numpy(), gpu_pre(sim, f_post)):
+        if prec == F64:
+            assert rel_err(got, states[0], fluid) < tol
+        else:
+            assert _absdiff(got, states[0], fluid) < 2e-7
+    other = sim.populations()
+    for n in range(1, steps + 1):
+        sim.step(f_post, other)
+        f_post, other = other, f_post
+        got = gpu_pre(sim, f_post)
+        want = states[n]
+        if prec == F64:
+            assert rel_err(got, want, fluid) < tol, (n, rel_err(got, want, fluid))
+        else:
+            assert _absdiff(got, want, fluid) < 2e-6, (n, _absdiff(got, want, fluid))
+    lat = LATTICES[q]
+    Fo = np.zeros(3) if F is None else F
+    rho_o, u_o = lbm.macroscopic_fields(lat, states[-1], Fo, solid)
+    rho_g, u_g = sim.macroscopic(f_post)
+    rho_g = rho_g.double().cpu().numpy()
+    u_g = u_g.double().cpu().numpy()
+    if prec == F64:
+        assert rel_err(rho_g, rho_o, fluid) < 1e-12
+        assert velocity_l2(u_g, u_o, fluid) < 1e-11
+    else:
+        assert velocity_l2(u_g, u_o, fluid) < 2e-5
+    tot = np.array(sim.totals(f_post))
+    tot_o = lbm.totals(lat, states[-1], Fo, solid)
+    nodes = int(np.prod(shape))
+    assert np.abs(tot - tot_o).max() < (1e-12 if prec == F64 else 1e-6) * nodes
+
+
+def _absdiff(a, b, fluid):
+    d = a - b
+    if fluid is not None:
+        d = d[:, fluid]
+    return float(np.abs(d).max())
+
+
+def _ulp16(x, fmt):
+    a = np.abs(x)
+    a = np.where(a == 0, 1e-30, a)
+    e = np.floor(np.log2(a))
+    mant = 10 if fmt == F16 else 7
+    sub = -14 if fmt == F16 else -126
+    return 2.0 ** (np.maximum(e, sub) - mant)
+
+
+@pytest.mark.parametrize("q", [27, 15])
+@pytest.mark.parametrize("prec", [F16, BF16])
+def test_deviation_storage_one_step(q, prec):
+    print(f"case dev16 q{q} p{prec}", flush=True)
+    shape = (6, 7, 68)
+    rng = np.random.default_rng(11)
+    omega = list(rng.uniform(0.7, 1.9, q - 4))
+    F = inp.gaussian_force(shape, 1e-4, 2)
+    rho0, u0 = _fields(shape, 9)
+    sim = gpu_setup(q, shape, prec, omega, F)
+    f_post, _ = gpu_initial(sim, rho0, u0)
+    pre = gpu_pre(sim, f_post)                       # decoded stored state
+    other = sim.populations()
+    sim.step(f_post, other)
+    got = gpu_pre(sim, other)
+    lat = LATTICES[q]
+    want = lbm.step(lat, pre, F, omega)              # oracle from the same decoded input
+    w = collision.equilibrium(lat, np.array(1.0), np.zeros(3))
+    dev = want - w[:, None, None, None]
+    bound = 0.5 * _ulp16(dev, prec) + 2e-6
+    assert (np.abs(got - want) <= bound).all(), np.abs(got - want).max()
+
+
+def test_fp32_taylor_green_velocity_l2():
+    # Taylor-Green of the 32^3 configuration, 10 steps, FP32 GPU vs FP64 oracle.
+    print("case tg32 f32", flush=True)
+    n, steps = 32, 10
+    q = 27
+    omega = shear_rates(q, 1.6)
+    u0 = inp.taylor_green(n, 0.02)
+    rho0 = np.ones((n, n, n))
+    F = np.array([1e-6, 0, 0])
+    sim = gpu_setup(q, (n, n, n), F32, omega, F)
+    f_post, _ = gpu_initial(sim, rho0, u0)
+    f_last = sim.run(f_post, sim.populations(), steps)
+    _, u_g = sim.macroscopic(f_last)
+    states = oracle_run(q, rho0, u0, F, omega, steps)
+    _, u_o = lbm.macroscopic_fields(LATTICES[q], states[-1], F)
+    assert velocity_l2(u_g.double().cpu().numpy(), u_o) < 2e-5
+
+
+def test_run_ping_pong_and_errors():
+    cm = lib()
+    sim = gpu_setup(27, (4, 4, 64), F32, shear_rates(27, 1.5))
+    f_post, _ = gpu_initial(sim, np.ones((4, 4, 64)), np.zeros((3, 4, 4, 64)))
+    b = sim.populations()
+    assert sim.run(f_post, b, 3) is b
+    assert sim.run(f_post, b, 2) is f_post
+    with pytest.raises(cm.CmlbmError):
+        sim.step(f_post, f_post)                        # aliasing is rejected
+    with pytest.raises(cm.CmlbmError):
+        sim.set_rates([2.5] * 23)                      # outside (0, 2)
+    with pytest.raises(cm.CmlbmError):
+        sim.set_rates([1.0] * 11)                      # wrong count
+    s15 = cm.Sim(15, 8, 8, 8, F32)
+    with pytest.raises(cm.CmlbmError) as e:
+        s15.adjoint_step(f_post, f_post, b, b, b)
+    assert e.value.code == -2
+
+
+@pytest.mark.parametrize("q", [27, 15])
+def test_full_size_sampled_nodes(q):
+    # The benchmark configuration: 512^3 FP32 D3Q27 (and D3Q15) with the
+    # Kolmogorov force field F_x = 1e-6 sin(2 pi 4 y / 512), shear rate 1.9.
+    # One step from a perturbed state; the oracle collides 4096 sampled nodes
+    # from the pre-collision populations the GPU pulled.
+    print(f"case full512 q{q}", flush=True)
+    n = 512
+    sim = gpu_setup(q, (n, n, n), F32, shear_rates(q, 1.9))
+    F = torch.from_numpy(inp.kolmogorov_force(n)).to("cuda", torch.float32)
+    sim.set_force(F)
+    rho0 = torch.ones((n, n, n), device="cuda", dtype=torch.float32)
+    g = torch.Generator(device="cuda").manual_seed(1)
+    u0 = 0.03 * (torch.rand((3, n, n, n), device="cuda", generator=g) - 0.5)
+    f_post, f_pre = sim.init_equilibrium(rho0, u0)
+    del u0, rho0
+    out = sim.populations()
+    sim.step(f_post, out)
+    pre = sim.gather(f_post, out=f_pre)
+    rng = np.random.default_rng(3)
+    idx = rng.integers(0, n**3, 4096)
+    idx[:4] = [0, n - 1, n * n - 1, n**3 - 1]          # corners of the periodic box
+    idx_t = torch.from_numpy(idx).to("cuda")
+    f_in = pre.reshape(q, -1)[:, idx_t].double().cpu().numpy().T
+    f_gpu = out.reshape(q, -1)[:, idx_t].double().cpu().numpy().T
+    Fs = F.reshape(3, -1)[:, idx_t].double().cpu().numpy().T
+    want = collision.collide(LATTICES[q], f_in, Fs, shear_rates(q, 1.9))
+    assert np.abs(f_gpu - want).max() < 2e-6
+
+
+def test_duct_128_transient_closed_form():
+    # 128^3 D3Q27 FP32 duct: walls y, z in {0, 127}, F_x = 1e-6, omega 1.8,
+    # 20000 steps from rest vs the closed-form start-up series (same momentum
+    # equation the paper's steady duct profile solves).
+    print("case duct128", flush=True)
+    n, steps, omega, Fx = 128, 20000, 1.8, 1e-6
+    solid = inp.duct_mask(n, n, n)
+    sim = gpu_setup(27, (n, n, n), F32, shear_rates(27, omega), np.array([Fx, 0, 0]), solid)
+    f_post, _ = gpu_initial(sim, np.ones((n, n, n)), np.zeros((3, n, n, n)))
+    f_last = sim.run(f_post, sim.populations(), steps)
+    _, u = sim.macroscopic(f_last)
+    ux = u[0, 1:-1, 1:-1, n // 2].double().cpu().numpy()
+    from test_oracle_flows import duct_startup, nu_of
+    c = np.arange(1, n - 1) - (n - 1) / 2
+    Z, Y = np.meshgrid(c, c, indexing="ij")
+    ua = duct_startup(Y, Z, (n - 2) / 2, Fx, nu_of(omega), steps, nterms=60)
+    err = np.linalg.norm(ux - ua) / np.linalg.norm(ua)
+    print(f"duct128 relative L2 {err:.3e}  center {ux[62, 62]:.6e} vs {ua[62, 62]:.6e}", flush=True)
+    assert err < 1e-2
