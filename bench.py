@@ -144,13 +144,15 @@ def main():
                      "algorithmic_bytes_per_node": BYTES_PER_NODE, "kernel": "k_step<27,StF32,false>"},
         "mass_total_fp64": tot[0],
     }
+    del a, b, bufs, last
+    torch.cuda.empty_cache()
     if not args.no_adjoint:
         from paper_1202_6081_amd import autograd as ag
-        result["adjoint"] = ag.benchmark_adjoint_ratio(sim, bufs[(k0 + args.steps) & 1], args.adjoint_steps,
-                                                       forward_ms_per_step=ms_per_step)
+        result["adjoint"] = ag.benchmark_adjoint_ratio(sim, args.adjoint_steps, forward_ms_per_step=ms_per_step)
+        result["adjoint_forward_ratio"] = result["adjoint"]["ratio_backward_over_forward_steps"]
     else:
         result["adjoint"] = None
-    del a, b, bufs
+        result["adjoint_forward_ratio"] = None
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline()

@@ -150,6 +150,28 @@ cmlbm_status cmlbm_totals(cmlbm_sim *sim, const void *f_post, double out4[4], vo
 cmlbm_status cmlbm_adjoint_step(cmlbm_sim *sim, const void *f_post_prev, const void *lam_next, void *lam,
                                 double *dLdF_dev, double *dLdomega_dev, void *stream);
 
+/* Kinetic-energy loss of a pre-collision state: *out = sum over fluid nodes of
+ * |rho u|^2 / (2 rho), rho u = sum fbar e + F/2 (Eqs. densitycalculation,
+ * velocitycalculation), accumulated in FP64.  f_pre: "real" [q][nz][ny][nx]
+ * (as written by cmlbm_gather_precollision).  Host output; synchronizes. */
+cmlbm_status cmlbm_kinetic_energy_sum(cmlbm_sim *sim, const void *f_pre, double *out, void *stream);
+
+/* Seed of the adjoint sweep for the loss L = scale * (the sum above):
+ * writes lam = dL/dfbar ("real" [q][nz][ny][nx]; dL/dfbar_a = scale (u.e_a -
+ * |u|^2/2), zero at solid nodes) and accumulates dL/dF of the direct F/2 term,
+ * scale * u/2, into dLdF_dev (FP64 [3][nz][ny][nx] for a force field, FP64 [3]
+ * for a uniform force). */
+cmlbm_status cmlbm_kinetic_energy_seed(cmlbm_sim *sim, const void *f_pre, double scale, void *lam,
+                                       double *dLdF_dev, void *stream);
+
+/* Adjoint of the initial state of cmlbm_init_equilibrium with respect to the
+ * force: fbar(x, 0) = f^eq(rho, u0) - S(F, u0)/2 depends on F through S (Sec. 5
+ * matching principle).  Accumulates -(1/2) (dS/dF)^T lam0 into dLdF_dev (same
+ * layout as above).  u0_dev: "real" [3][nz][ny][nx]; lam0_dev = dL/dfbar(0).
+ * D3Q27 only (EUNSUPPORTED otherwise). */
+cmlbm_status cmlbm_init_adjoint(cmlbm_sim *sim, const void *u0_dev, const void *lam0_dev, double *dLdF_dev,
+                                void *stream);
+
 /* Message for a status code (static string). */
 const char *cmlbm_status_string(cmlbm_status code);
 

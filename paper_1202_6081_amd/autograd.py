@@ -1,0 +1,350 @@
+"""Differentiable D3Q27 runs: torch.autograd.Function over the HIP adjoint step,
+with checkpoint-and-recompute over time.
+
+Forward: fbar(0) = f^eq(rho0, u0) - S/2 (cmlbm_init_equilibrium), N steps of
+cmlbm_step, output the pre-collision populations fbar(N).  Backward: for
+n = N-1 .. 0, lam(n) = (step n)^T lam(n+1) by cmlbm_adjoint_step, which needs
+the post-collision buffer x(n) of step n; then cmlbm_init_adjoint adds the
+dependence of fbar(0) on F.  dL/dF and dL/domega accumulate in FP64 on the
+device.
+
+x(n) is recovered from stored snapshots by recomputation.  Two schedules:
+``every=k`` keeps x(0), x(k), x(2k), ... and replays one segment at a time with
+all its states stored; ``snapshots=s`` keeps at most s states and places them
+by the binomial (optimal offline) rule: reversing n steps from a stored state
+with s free slots costs min over m of [m + cost(n - m, s - 1) + cost(m, s)]
+recomputed steps, cost(1, s) = 0, cost(n, 0) = n(n - 1)/2.
+"""
+import functools
+import math
+import time
+
+import torch
+
+from . import cmlbm
+
+
+# ----------------------------------------------------------------------------
+# binomial checkpoint schedule
+# ----------------------------------------------------------------------------
+@functools.lru_cache(maxsize=None)
+def _cost(n, s):
+    if n <= 1:
+        return 0, 0
+    if s == 0:
+        return n * (n - 1) // 2, 0
+    best, arg = None, 1
+    for m in range(1, n):
+        c = m + _cost(n - m, s - 1)[0] + _cost(m, s)[0]
+        if best is None or c < best:
+            best, arg = c, m
+    return best, arg
+
+
+def recompute_steps(nsteps, snapshots):
+    """Forward steps recomputed by the backward sweep of the binomial schedule,
+    given `snapshots` stored states besides x(0) that the forward pass places
+    along the first right-hand chain of splits."""
+    chain = _right_chain(0, nsteps, snapshots)
+    total, l, s = 0, 0, snapshots
+    for m in chain:
+        total += _cost(m - l, s)[0]          # left part reversed with the remaining slots
+        l, s = m, s - 1
+    total += _cost(nsteps - l, s)[0]
+    return total
+
+
+def _right_chain(l, r, s):
+    """Positions the forward pass stores: m1 = split(l, r, s), m2 = split(m1, r, s-1), ..."""
+    chain = []
+    while s > 0 and r - l > 1:
+        m = l + _cost(r - l, s)[1]
+        chain.append(m)
+        l, s = m, s - 1
+    return chain
+
+
+class _Pool:
+    """Population buffers reused by the sweeps."""
+
+    def __init__(self, sim):
+        self.sim = sim
+        self.free = []
+        self.allocated = 0
+
+    def get(self):
+        if self.free:
+            return self.free.pop()
+        self.allocated += 1
+        return self.sim.populations()
+
+    def put(self, t):
+        self.free.append(t)
+
+
+def _advance(sim, pool, x, k):
+    """k steps from x (left untouched); returns a fresh buffer (or x if k == 0)."""
+    if k == 0:
+        return x
+    cur = x
+    for i in range(k):
+        nxt = pool.get()
+        sim.step(cur, nxt)
+        if cur is not x:
+            pool.put(cur)
+        cur = nxt
+    return cur
+
+
+class _Sweep:
+    """Reverse sweep over steps [l, r) given stored x(l)."""
+
+    def __init__(self, sim, pool, lam, lam_tmp, dLdF, dLdw):
+        self.sim, self.pool = sim, pool
+        self.lam, self.lam_tmp = lam, lam_tmp
+        self.dLdF, self.dLdw = dLdF, dLdw
+        self.recomputed = 0
+        self.adjoint_steps = 0
+
+    def adjoint(self, x):
+        self.sim.adjoint_step(x, self.lam, self.lam_tmp, self.dLdF, self.dLdw)
+        self.lam, self.lam_tmp = self.lam_tmp, self.lam
+        self.adjoint_steps += 1
+
+    def binomial(self, l, r, xl, s):
+        n = r - l
+        if n == 1:
+            self.adjoint(xl)
+            return
+        if s == 0:
+            for t in range(r - 1, l - 1, -1):
+                x = _advance(self.sim, self.pool, xl, t - l)
+                self.recomputed += t - l
+                self.adjoint(x)
+                if x is not xl:
+                    self.pool.put(x)
+            return
+        m = l + _cost(n, s)[1]
+        xm = _advance(self.sim, self.pool, xl, m - l)
+        self.recomputed += m - l
+        self.binomial(m, r, xm, s - 1)
+        self.pool.put(xm)
+        self.binomial(l, m, xl, s)
+
+    def segment(self, l, r, xl):
+        """Replay [l, r) once, keeping every state, then reverse it."""
+        states = [xl]
+        cur = xl
+        for _ in range(l, r - 1):
+            nxt = self.pool.get()
+            self.sim.step(cur, nxt)
+            self.recomputed += 1
+            states.append(nxt)
+            cur = nxt
+        for x in reversed(states):
+            self.adjoint(x)
+        for x in states[1:]:
+            self.pool.put(x)
+
+
+def forward_sweep(sim, pool, x0, nsteps, keep):
+    """Advance x0 by nsteps, keeping the states at the positions in `keep`.
+    Returns ({position: buffer} with 0 -> x0, final buffer)."""
+    stored = {0: x0}
+    cur = x0
+    for n in range(nsteps):
+        nxt = pool.get()
+        sim.step(cur, nxt)
+        if stored.get(n) is not cur:
+            pool.put(cur)
+        cur = nxt
+        if n + 1 in keep:
+            stored[n + 1] = cur
+    return stored, cur
+
+
+def backward_sweep(sw, stored, nsteps, every, snapshots):
+    """Run the adjoint steps N-1 .. 0 with recomputation from `stored`."""
+    if every:
+        starts = sorted(stored)
+        for i in range(len(starts) - 1, -1, -1):
+            l = starts[i]
+            r = starts[i + 1] if i + 1 < len(starts) else nsteps
+            sw.segment(l, r, stored[l])
+        return
+    chain = sorted(k for k in stored if k > 0)
+    bounds = [0] + chain + [nsteps]
+    for i in range(len(bounds) - 2, -1, -1):
+        l, r = bounds[i], bounds[i + 1]
+        # interval i is reversed while the snapshots at m_1..m_i are still held
+        sw.binomial(l, r, stored[l], max(snapshots - i, 0))
+        if l > 0:
+            sw.pool.put(stored.pop(l))
+
+
+def keep_positions(nsteps, every, snapshots):
+    if every:
+        return set(range(every, nsteps, every))
+    return set(_right_chain(0, nsteps, snapshots))
+
+
+class _Run(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, F, omega, sim, rho0, u0, nsteps, every, snapshots):
+        sim.set_rates([float(w) for w in omega.detach().cpu()])
+        Fr = F.detach().to(device=sim.device, dtype=sim.real).contiguous()
+        sim.set_force(Fr)
+        pool = _Pool(sim)
+        x0 = pool.get()
+        pre = sim.real_populations()
+        u0r = u0.to(device=sim.device, dtype=sim.real).contiguous()
+        sim.init_equilibrium(rho0.to(device=sim.device, dtype=sim.real).contiguous(), u0r, f_post=x0, f_pre=pre)
+        stored, last = forward_sweep(sim, pool, x0, nsteps, keep_positions(nsteps, every, snapshots))
+        sim.gather(last, out=pre)
+        if not any(last is v for v in stored.values()):
+            pool.put(last)
+        ctx.sim, ctx.pool, ctx.stored = sim, pool, stored
+        ctx.u0, ctx.nsteps, ctx.every, ctx.snapshots = u0r, nsteps, every, snapshots
+        ctx.F_dtype, ctx.w_dtype, ctx.F_shape = F.dtype, omega.dtype, F.shape
+        ctx.Fr = Fr
+        return pre
+
+    @staticmethod
+    def backward(ctx, g):
+        sim, pool, stored = ctx.sim, ctx.pool, ctx.stored
+        sim.set_force(ctx.Fr)
+        lam = g.detach().to(dtype=sim.real).contiguous().clone()
+        lam_tmp = sim.real_populations()
+        dLdF = torch.zeros(ctx.F_shape, dtype=torch.float64, device=sim.device)
+        dLdw = torch.zeros(23, dtype=torch.float64, device=sim.device)
+        sw = _Sweep(sim, pool, lam, lam_tmp, dLdF, dLdw)
+        backward_sweep(sw, stored, ctx.nsteps, ctx.every, ctx.snapshots)
+        sim.init_adjoint(ctx.u0, sw.lam, dLdF)
+        ctx.stats = {"recomputed": sw.recomputed, "adjoint_steps": sw.adjoint_steps, "buffers": pool.allocated}
+        _last_stats.update(ctx.stats)
+        _last_stats["dLdF_fp64"] = dLdF
+        _last_stats["dLdomega_fp64"] = dLdw
+        return (dLdF.to(ctx.F_dtype), dLdw.to(ctx.w_dtype), None, None, None, None, None, None)
+
+
+_last_stats = {}
+
+
+def last_backward_stats():
+    """Recompute counts of the last backward sweep and its FP64 gradients."""
+    return dict(_last_stats)
+
+
+def run(sim, rho0, u0, F, omega, nsteps, every=None, snapshots=None):
+    """Differentiable D3Q27 run: returns the pre-collision populations fbar(N)
+    (Q, nz, ny, nx), differentiable with respect to the force field F
+    (3, nz, ny, nx) and the rates omega (23,).  Exactly one of `every`
+    (uniform checkpoint interval) or `snapshots` (binomial schedule with that
+    many stored states besides x(0)) must be given."""
+    if sim.q != 27:
+        raise cmlbm.CmlbmError(-2, "the adjoint is provided for D3Q27")
+    if (every is None) == (snapshots is None):
+        raise ValueError("give exactly one of every= or snapshots=")
+    return _Run.apply(F, omega, sim, rho0, u0, int(nsteps), int(every or 0), int(snapshots or 0))
+
+
+class _KineticEnergy(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, f_pre, F, sim, n_fluid):
+        total = sim.kinetic_energy_sum(f_pre.detach().contiguous())
+        ctx.sim, ctx.n_fluid, ctx.F_dtype, ctx.F_shape = sim, n_fluid, F.dtype, F.shape
+        ctx.save_for_backward(f_pre)
+        return torch.tensor(total / n_fluid, dtype=torch.float64, device=f_pre.device)
+
+    @staticmethod
+    def backward(ctx, g):
+        (f_pre,) = ctx.saved_tensors
+        sim = ctx.sim
+        lam = torch.empty_like(f_pre)
+        dLdF = torch.zeros(ctx.F_shape, dtype=torch.float64, device=f_pre.device)
+        sim.kinetic_energy_seed(f_pre.detach().contiguous(), float(g) / ctx.n_fluid, lam, dLdF)
+        return lam, dLdF.to(ctx.F_dtype), None, None
+
+
+def kinetic_energy(sim, f_pre, F, n_fluid=None):
+    """Mean kinetic energy (1/N) sum |rho u|^2 / (2 rho) over the N fluid nodes
+    of a pre-collision state, with rho u including F/2; differentiable in f_pre
+    and F.  The sim's force must be F (as set by `run`)."""
+    if n_fluid is None:
+        n_fluid = sim.nx * sim.ny * sim.nz
+    return _KineticEnergy.apply(f_pre, F, sim, int(n_fluid))
+
+
+def binomial_snapshots_for_budget(state_bytes, budget_bytes, fixed_bytes):
+    """Largest snapshot count fitting `budget_bytes` next to `fixed_bytes`."""
+    return max(0, int((budget_bytes - fixed_bytes) // state_bytes))
+
+
+def benchmark_adjoint_ratio(sim, nsteps, forward_ms_per_step, budget_gib=200.0):
+    """Time a checkpointed D3Q27 adjoint of `nsteps` steps on sim's lattice
+    under a device memory budget and return the adjoint/forward time ratio.
+
+    Loss: mean kinetic energy of fbar(N).  Fixed memory: two forward work
+    buffers, two adjoint buffers, the pre-collision output, the force field,
+    the FP64 force gradient; the rest of the budget holds snapshots."""
+    dev = sim.device
+    n = sim.nx * sim.ny * sim.nz
+    state = n * 27 * torch.tensor([], dtype=sim.store).element_size()
+    real_state = n * 27 * torch.tensor([], dtype=sim.real).element_size()
+    fixed = 2 * state + 3 * real_state + 3 * n * (8 + torch.tensor([], dtype=sim.real).element_size())
+    budget = budget_gib * 2**30
+    snaps = binomial_snapshots_for_budget(state, budget, fixed)
+    snaps = max(1, min(snaps, nsteps - 1))
+    import lbm_inputs as inp   # Kolmogorov field of the benchmark workload
+    F = torch.from_numpy(inp.kolmogorov_force(sim.nx, amplitude=1e-6, waves=4, nz=sim.nz, ny=sim.ny,
+                                              nx=sim.nx)).to(dev, torch.float32).requires_grad_(True)
+    omega = torch.tensor([1.9] * 5 + [1.0] * 18, dtype=torch.float64, requires_grad=True)
+    rho0 = torch.ones((sim.nz, sim.ny, sim.nx), device=dev, dtype=sim.real)
+    u0 = torch.zeros((3, sim.nz, sim.ny, sim.nx), device=dev, dtype=sim.real)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = run(sim, rho0, u0, F, omega, nsteps, snapshots=snaps)
+    loss = kinetic_energy(sim, out, F)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    loss.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    st = last_backward_stats()
+    peak = torch.cuda.max_memory_allocated(dev)
+    fwd_ms = (t1 - t0) * 1e3
+    bwd_ms = (t2 - t1) * 1e3
+    dLdw_shear = float(st["dLdomega_fp64"][:5].sum())
+    del out, loss, st
+    _last_stats.clear()
+    # average duration of the adjoint step kernel alone (events on the launch stream)
+    x = sim.populations()
+    lam_a, lam_b = sim.real_populations(), sim.real_populations()
+    sim.init_equilibrium(rho0, u0, f_post=x, f_pre=lam_a)
+    lam_a.zero_()
+    dLdF = torch.zeros((3, sim.nz, sim.ny, sim.nx), dtype=torch.float64, device=dev)
+    dLdw = torch.zeros(23, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    sim.adjoint_step(x, lam_a, lam_b, dLdF, dLdw)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    k = 5
+    e0.record(stream)
+    for i in range(k):
+        sim.adjoint_step(x, lam_a, lam_b, dLdF, dLdw)
+        lam_a, lam_b = lam_b, lam_a
+    e1.record(stream)
+    torch.cuda.synchronize()
+    adj_ms = e0.elapsed_time(e1) / k
+    del x, lam_a, lam_b, dLdF
+    return {
+        "steps": nsteps, "snapshots": snaps, "budget_gib": budget_gib,
+        "peak_alloc_gib": round(peak / 2**30, 1),
+        "recomputed_steps": st["recomputed"], "adjoint_steps": st["adjoint_steps"],
+        "forward_pass_ms": round(fwd_ms, 1), "backward_ms": round(bwd_ms, 1),
+        "ratio_backward_over_forward_steps": round(bwd_ms / (nsteps * forward_ms_per_step), 3),
+        "adjoint_step_ms": round(adj_ms, 3),
+        "adjoint_step_bytes_per_node": 27 * 4 * 3 + 12 + 48,
+        "adjoint_step_GBs": round((27 * 4 * 3 + 12 + 48) * n / (adj_ms * 1e-3) / 1e9, 1),
+        "dLdomega_shear": dLdw_shear,
+        "loss": float(loss),
+    }

@@ -51,6 +51,9 @@ def load_library():
         "cmlbm_macroscopic": (i, [vp, vp, vp, vp, vp]),
         "cmlbm_totals": (i, [vp, vp, ctypes.POINTER(d), vp]),
         "cmlbm_adjoint_step": (i, [vp, vp, vp, vp, vp, vp, vp]),
+        "cmlbm_kinetic_energy_sum": (i, [vp, vp, ctypes.POINTER(d), vp]),
+        "cmlbm_kinetic_energy_seed": (i, [vp, vp, d, vp, vp, vp]),
+        "cmlbm_init_adjoint": (i, [vp, vp, vp, vp, vp]),
         "cmlbm_status_string": (ctypes.c_char_p, [i]),
         "cmlbm_last_error": (ctypes.c_char_p, [vp]),
         "cmlbm_version": (ctypes.c_char_p, []),
@@ -67,7 +70,8 @@ def exported_symbols():
     return ["cmlbm_create", "cmlbm_destroy", "cmlbm_set_rates", "cmlbm_set_force_uniform",
             "cmlbm_set_force_field", "cmlbm_set_force_scale", "cmlbm_set_mask", "cmlbm_init_equilibrium",
             "cmlbm_step", "cmlbm_run", "cmlbm_gather_precollision", "cmlbm_macroscopic", "cmlbm_totals",
-            "cmlbm_adjoint_step", "cmlbm_status_string", "cmlbm_last_error", "cmlbm_version"]
+            "cmlbm_adjoint_step", "cmlbm_kinetic_energy_sum", "cmlbm_kinetic_energy_seed", "cmlbm_init_adjoint",
+            "cmlbm_status_string", "cmlbm_last_error", "cmlbm_version"]
 
 
 # ----------------------------------------------------------------------------
@@ -182,6 +186,21 @@ def cmlbm_adjoint_step(h, f_post_prev, lam_next, lam, dLdF, dLdomega, stream=Non
                                               _ptr(dLdomega), _stream(stream)), h)
 
 
+def cmlbm_kinetic_energy_sum(h, f_pre, stream=None):
+    out = ctypes.c_double(0.0)
+    _check(load_library().cmlbm_kinetic_energy_sum(h, _ptr(f_pre), ctypes.byref(out), _stream(stream)), h)
+    return out.value
+
+
+def cmlbm_kinetic_energy_seed(h, f_pre, scale, lam, dLdF, stream=None):
+    _check(load_library().cmlbm_kinetic_energy_seed(h, _ptr(f_pre), float(scale), _ptr(lam), _ptr(dLdF),
+                                                     _stream(stream)), h)
+
+
+def cmlbm_init_adjoint(h, u0, lam0, dLdF, stream=None):
+    _check(load_library().cmlbm_init_adjoint(h, _ptr(u0), _ptr(lam0), _ptr(dLdF), _stream(stream)), h)
+
+
 def cmlbm_version():
     return load_library().cmlbm_version().decode()
 
@@ -279,3 +298,12 @@ class Sim:
 
     def adjoint_step(self, f_post_prev, lam_next, lam, dLdF, dLdomega, stream=None):
         cmlbm_adjoint_step(self.h, f_post_prev, lam_next, lam, dLdF, dLdomega, stream)
+
+    def kinetic_energy_sum(self, f_pre, stream=None):
+        return cmlbm_kinetic_energy_sum(self.h, f_pre, stream)
+
+    def kinetic_energy_seed(self, f_pre, scale, lam, dLdF, stream=None):
+        cmlbm_kinetic_energy_seed(self.h, f_pre, scale, lam, dLdF, stream)
+
+    def init_adjoint(self, u0, lam0, dLdF, stream=None):
+        cmlbm_init_adjoint(self.h, u0, lam0, dLdF, stream)

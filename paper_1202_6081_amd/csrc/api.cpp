@@ -137,7 +137,7 @@ cmlbm_status cmlbm_create(int q, int nx, int ny, int nz, int precision, cmlbm_si
   cmlbm_sim* s = new cmlbm_sim();
   s->q = q;
   s->prec = precision;
-  hipGetDevice(&s->device);
+  (void)hipGetDevice(&s->device);
   s->g.nx = nx;
   s->g.ny = ny;
   s->g.nz = nz;
@@ -156,9 +156,9 @@ cmlbm_status cmlbm_create(int q, int nx, int ny, int nz, int precision, cmlbm_si
 
 void cmlbm_destroy(cmlbm_sim* sim) {
   if (!sim) return;
-  if (sim->totals_partials) hipFree(sim->totals_partials);
-  if (sim->totals_out) hipFree(sim->totals_out);
-  if (sim->adj_partials) hipFree(sim->adj_partials);
+  if (sim->totals_partials) (void)hipFree(sim->totals_partials);
+  if (sim->totals_out) (void)hipFree(sim->totals_out);
+  if (sim->adj_partials) (void)hipFree(sim->adj_partials);
   delete sim;
 }
 
@@ -293,7 +293,7 @@ cmlbm_status cmlbm_adjoint_step(cmlbm_sim* s, const void* f_post_prev, const voi
     return fail(s, CMLBM_EINVAL, "lam, lam_next and f_post_prev must differ");
   const int nblk = cmlbm::adjoint_blocks(s->g);
   if (nblk > s->adj_nblk) {
-    if (s->adj_partials) hipFree(s->adj_partials);
+    if (s->adj_partials) (void)hipFree(s->adj_partials);
     s->adj_partials = nullptr;
     s->adj_nblk = 0;
     if (hipMalloc(&s->adj_partials, sizeof(double) * 26 * size_t(nblk)) != hipSuccess)
@@ -325,6 +325,40 @@ cmlbm_status cmlbm_adjoint_step(cmlbm_sim* s, const void* f_post_prev, const voi
   hipError_t e = cmlbm::launch_adjoint(s->prec, a64, a32, s->adj_partials, nblk, dLdomega_dev, dLdF_uniform,
                                        static_cast<hipStream_t>(stream));
   return check_hip(s, e, "adjoint_step");
+}
+
+cmlbm_status cmlbm_kinetic_energy_sum(cmlbm_sim* s, const void* f_pre, double* out, void* stream) {
+  if (!s) return CMLBM_EINVAL;
+  if (!f_pre || !out) return fail(s, CMLBM_EINVAL, "NULL buffer");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = cmlbm::launch_ke_sum(s->q, s->prec, s->g, f_pre, s->mask, make_force<double>(s), make_force<float>(s),
+                                      s->totals_partials, cmlbm::kTotalsBlocks, s->totals_out, st);
+  if (e != hipSuccess) return check_hip(s, e, "kinetic_energy_sum");
+  e = hipMemcpyAsync(out, s->totals_out, sizeof(double), hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess) return check_hip(s, e, "kinetic_energy_sum copy");
+  return check_hip(s, hipStreamSynchronize(st), "kinetic_energy_sum sync");
+}
+
+cmlbm_status cmlbm_kinetic_energy_seed(cmlbm_sim* s, const void* f_pre, double scale, void* lam, double* dLdF_dev,
+                                       void* stream) {
+  if (!s) return CMLBM_EINVAL;
+  if (!f_pre || !lam || !dLdF_dev) return fail(s, CMLBM_EINVAL, "NULL buffer");
+  if (f_pre == lam) return fail(s, CMLBM_EINVAL, "f_pre and lam must differ");
+  hipError_t e = cmlbm::launch_ke_seed(s->q, s->prec, s->g, f_pre, s->mask, make_force<double>(s),
+                                       make_force<float>(s), scale, lam, dLdF_dev, s->totals_partials,
+                                       cmlbm::kTotalsBlocks, static_cast<hipStream_t>(stream));
+  return check_hip(s, e, "kinetic_energy_seed");
+}
+
+cmlbm_status cmlbm_init_adjoint(cmlbm_sim* s, const void* u0_dev, const void* lam0_dev, double* dLdF_dev,
+                                void* stream) {
+  if (!s) return CMLBM_EINVAL;
+  if (s->q != 27) return fail(s, CMLBM_EUNSUPPORTED, "the initial-condition adjoint is provided for D3Q27");
+  if (!u0_dev || !lam0_dev || !dLdF_dev) return fail(s, CMLBM_EINVAL, "NULL buffer");
+  hipError_t e = cmlbm::launch_init_adjoint(s->prec, s->g, u0_dev, lam0_dev, s->mask, make_force<double>(s),
+                                            make_force<float>(s), dLdF_dev, s->totals_partials,
+                                            cmlbm::kTotalsBlocks, static_cast<hipStream_t>(stream));
+  return check_hip(s, e, "init_adjoint");
 }
 
 }  // extern "C"

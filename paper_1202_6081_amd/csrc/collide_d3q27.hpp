@@ -239,12 +239,43 @@ CMLBM_HD void relax27(R (&m)[27], R rho, R Fx, R Fy, R Fz, const Rates<R>& p) {
   m[K3(2, 2, 2)] = p.wc[26] * m[K3(2, 2, 2)] + p.w[26] * (kxx * kyy * kzz);
 }
 
+// First pass along z fused with the density and velocity sums: raw z-moments
+// (s0, s1, s2) = (a+b+c, c-a, c+a) of each line give rho and j, then the shift
+// to central moments about u_z is the same arithmetic as fwd_line.
+template <typename R>
+CMLBM_HD void first_pass27(R (&m)[27], R Fx, R Fy, R Fz, R& rho, R& ux, R& uy, R& uz) {
+  R s0[9], s1[9];
+#pragma unroll
+  for (int l = 0; l < 9; ++l) {
+    const int o = line_base<2>(l);
+    s0[l] = m[o] + m[o + 1] + m[o + 2];
+    s1[l] = m[o + 2] - m[o];
+  }
+  // lines l = ix*3 + iy
+  rho = ((s0[0] + s0[1] + s0[2]) + (s0[3] + s0[4] + s0[5])) + (s0[6] + s0[7] + s0[8]);
+  const R jx = (s0[6] + s0[7] + s0[8]) - (s0[0] + s0[1] + s0[2]);
+  const R jy = (s0[2] + s0[5] + s0[8]) - (s0[0] + s0[3] + s0[6]);
+  const R jz = ((s1[0] + s1[1] + s1[2]) + (s1[3] + s1[4] + s1[5])) + (s1[6] + s1[7] + s1[8]);
+  const R inv = R(1) / rho;
+  ux = (jx + R(0.5) * Fx) * inv;
+  uy = (jy + R(0.5) * Fy) * inv;
+  uz = (jz + R(0.5) * Fz) * inv;
+#pragma unroll
+  for (int l = 0; l < 9; ++l) {
+    const int o = line_base<2>(l);
+    const R k1 = s1[l] - uz * s0[l];
+    const R k2 = (m[o + 2] + m[o]) - uz * (s1[l] + k1);
+    m[o] = s0[l];
+    m[o + 1] = k1;
+    m[o + 2] = k2;
+  }
+}
+
 // Full collision: cube-ordered pre-collision populations in, post-collision out.
 template <typename R>
 CMLBM_HD void collide27(R (&m)[27], R Fx, R Fy, R Fz, const Rates<R>& p) {
   R rho, ux, uy, uz;
-  moments0_27(m, Fx, Fy, Fz, rho, ux, uy, uz);
-  fwd_pass<2>(m, uz);
+  first_pass27(m, Fx, Fy, Fz, rho, ux, uy, uz);
   fwd_pass<1>(m, uy);
   fwd_pass<0>(m, ux);
   relax27(m, rho, Fx, Fy, Fz, p);

@@ -122,6 +122,43 @@ __device__ __forceinline__ void pull(const typename ST::T* __restrict__ fin, uin
   }
 }
 
+// Element idx of an array whose byte size fits in 32 bits: a uniform base
+// pointer plus a 32-bit byte offset, which maps onto the scalar-base form of
+// the global load/store instructions.
+template <typename T>
+__device__ __forceinline__ T ld32(const T* base, uint32_t idx) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + idx * uint32_t(sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ T* at32(T* base, uint32_t idx) {
+  return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + idx * uint32_t(sizeof(T)));
+}
+
+// pull() for the step kernel: WIDE selects 64-bit indexing for arrays of 4 GiB
+// and more.
+template <int Q, class ST, bool MASK, bool WIDE>
+__device__ __forceinline__ void pull_step(const typename ST::T* __restrict__ fin, uint64_t N, const uint8_t* mask,
+                                          const Neigh& nb, uint32_t node, typename ST::R (&f)[Q]) {
+  if constexpr (WIDE) {
+    pull<Q, ST, MASK>(fin, N, mask, nb, node, f);
+  } else {
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      const uint32_t src = nb.at(Lattice<Q>::e(a));
+      typename ST::T v;
+      if constexpr (MASK) {
+        if (mask[src])
+          v = ld32(fin + uint64_t(opposite<Q>(a)) * N, node);
+        else
+          v = ld32(fin + uint64_t(a) * N, src);
+      } else {
+        v = ld32(fin + uint64_t(a) * N, src);
+      }
+      f[a] = decode<ST, Q>(v, a);
+    }
+  }
+}
+
 template <typename R, typename FT>
 __device__ __forceinline__ void force_at(const ForceArgs<FT>& F, uint64_t N, uint32_t node, R& Fx, R& Fy, R& Fz) {
   if (F.field) {
@@ -152,27 +189,107 @@ __device__ __forceinline__ void collide(R (&f)[Q], R Fx, R Fy, R Fz, const Rates
 // ---------------------------------------------------------------------------
 // The fused pull-stream + collide + force step
 // ---------------------------------------------------------------------------
-template <int Q, class ST, bool MASK>
-__global__ __launch_bounds__(256) void k_step(StepArgs<typename ST::R> args) {
+// Launch shape of the step kernel: one block covers CMLBM_STEP_BLOCK
+// consecutive x of one row (y, z).  Hardware hands consecutive block ids to
+// the eight XCDs in turn; with CMLBM_XCD_REMAP the block id is permuted so that
+// each XCD receives a contiguous run of rows, keeping the two x-segments of a
+// row and the row's halo cache lines in one XCD's L2.
+#ifndef CMLBM_STEP_BLOCK
+#define CMLBM_STEP_BLOCK 256
+#endif
+#ifndef CMLBM_XCD_REMAP
+#define CMLBM_XCD_REMAP 1
+#endif
+#ifndef CMLBM_NT_STORE
+#define CMLBM_NT_STORE 1
+#endif
+
+__device__ __forceinline__ uint32_t step_block_id() {
+  uint32_t L = blockIdx.x;
+#if CMLBM_XCD_REMAP
+  const uint32_t G = gridDim.x, per = G >> 3;
+  if (L < (per << 3)) L = (L & 7u) * per + (L >> 3);
+#endif
+  return L;
+}
+
+template <typename T>
+__device__ __forceinline__ void store_stream(T* p, T v) {
+#if CMLBM_NT_STORE
+  __builtin_nontemporal_store(v, p);
+#else
+  *p = v;
+#endif
+}
+
+// Raw buffer store: per-array resource (base in SGPRs, size bound) plus a
+// 32-bit byte offset shared by all directions.  Stores past the bound are
+// dropped by the hardware.  Word 3 = 0x00020000 is the raw-buffer descriptor
+// of the gfx9 family.
+constexpr int kStoreAux = CMLBM_NT_STORE ? 2 : 0;   // 2: nontemporal (streaming) store
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t array_rsrc(void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, int(bytes), 0x00020000);
+}
+
+template <typename T>
+__device__ __forceinline__ void buf_store(T v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+  if constexpr (sizeof(T) == 4) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, kStoreAux);
+  } else if constexpr (sizeof(T) == 8) {
+    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, kStoreAux);
+  } else {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, off, 0, kStoreAux);
+  }
+}
+
+template <int Q, class ST, bool MASK, bool WIDE>
+__global__ __launch_bounds__(CMLBM_STEP_BLOCK) void k_step(StepArgs<typename ST::R> args) {
   using R = typename ST::R;
   using T = typename ST::T;
   const Geom g = args.g;
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t nseg = (uint32_t(g.nx) + blockDim.x - 1) / blockDim.x;
+  const uint32_t L = step_block_id();
+  const uint32_t row = L / nseg;                  // row = z * ny + y
+  const int x = int((L - row * nseg) * blockDim.x + threadIdx.x);
   if (x >= g.nx) return;
-  const Coord c{x, int(blockIdx.y), int(blockIdx.z)};
-  const uint32_t node = (uint32_t(c.z) * uint32_t(g.ny) + uint32_t(c.y)) * uint32_t(g.nx) + uint32_t(x);
+  const Coord c{x, int(row % uint32_t(g.ny)), int(row / uint32_t(g.ny))};
+  const uint32_t node = row * uint32_t(g.nx) + uint32_t(x);
   if constexpr (MASK) {
     if (args.mask[node]) return;
   }
   const Neigh nb(g, c, +1);
   R f[Q];
-  pull<Q, ST, MASK>(static_cast<const T*>(args.fin), g.N, args.mask, nb, node, f);
+  pull_step<Q, ST, MASK, WIDE>(static_cast<const T*>(args.fin), g.N, args.mask, nb, node, f);
   R Fx, Fy, Fz;
-  force_at(args.force, g.N, node, Fx, Fy, Fz);
+  if (args.force.field) {
+    const R* Ff = args.force.field;
+    const R sc = R(args.force.scale);
+    if constexpr (WIDE) {
+      Fx = sc * Ff[node];
+      Fy = sc * Ff[g.N + node];
+      Fz = sc * Ff[2 * g.N + node];
+    } else {
+      Fx = sc * ld32(Ff, node);
+      Fy = sc * ld32(Ff + g.N, node);
+      Fz = sc * ld32(Ff + 2 * g.N, node);
+    }
+  } else {
+    Fx = R(args.force.uni[0]);
+    Fy = R(args.force.uni[1]);
+    Fz = R(args.force.uni[2]);
+  }
   collide<Q>(f, Fx, Fy, Fz, args.rates);
   T* __restrict__ fout = static_cast<T*>(args.fout);
+  if constexpr (WIDE) {
 #pragma unroll
-  for (int a = 0; a < Q; ++a) fout[uint64_t(a) * g.N + node] = encode<ST, Q>(f[a], a);
+    for (int a = 0; a < Q; ++a) store_stream(&fout[uint64_t(a) * g.N + node], encode<ST, Q>(f[a], a));
+  } else {
+    const uint32_t bytes = uint32_t(g.N * sizeof(T)), off = node * uint32_t(sizeof(T));
+#pragma unroll
+    for (int a = 0; a < Q; ++a) buf_store(encode<ST, Q>(f[a], a), array_rsrc(fout + uint64_t(a) * g.N, bytes), off);
+  }
 }
 
 // Observable pre-collision state fbar(x) (full populations, compute type).
@@ -456,6 +573,128 @@ __global__ __launch_bounds__(256) void k_adjoint27(AdjArgs<typename ST::R> args,
 }
 
 // ---------------------------------------------------------------------------
+// Kinetic-energy loss and its seed: E = sum over fluid x of |j|^2 / (2 rho),
+// j = sum fbar e + F/2, on pre-collision populations (compute type).
+// dE/dfbar_a = u.e_a - |u|^2/2, dE/dF = u/2 (times the force scale).
+// ---------------------------------------------------------------------------
+template <int Q, typename R>
+__device__ __forceinline__ void node_moments(const R* fpre, uint64_t N, uint32_t n, R Fx, R Fy, R Fz, R& rho,
+                                             R& ux, R& uy, R& uz) {
+  R jx = R(0), jy = R(0), jz = R(0);
+  rho = R(0);
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    const Vel e = Lattice<Q>::e(a);
+    const R v = fpre[uint64_t(a) * N + n];
+    rho += v;
+    jx += R(e.x) * v;
+    jy += R(e.y) * v;
+    jz += R(e.z) * v;
+  }
+  const R inv = R(1) / rho;
+  ux = (jx + R(0.5) * Fx) * inv;
+  uy = (jy + R(0.5) * Fy) * inv;
+  uz = (jz + R(0.5) * Fz) * inv;
+}
+
+template <int Q, typename R>
+__global__ __launch_bounds__(256) void k_ke_sum(Geom g, const R* fpre, const uint8_t* mask, ForceArgs<R> force,
+                                                double* partials) {
+  double acc[1] = {0};
+  for (uint32_t n = blockIdx.x * blockDim.x + threadIdx.x; n < g.N; n += gridDim.x * blockDim.x) {
+    if (mask && mask[n]) continue;
+    R Fx, Fy, Fz;
+    force_at(force, g.N, n, Fx, Fy, Fz);
+    R rho, ux, uy, uz;
+    node_moments<Q>(fpre, g.N, n, Fx, Fy, Fz, rho, ux, uy, uz);
+    acc[0] += 0.5 * double(rho) * (double(ux) * ux + double(uy) * uy + double(uz) * uz);
+  }
+  __shared__ double sh[8];
+  block_sum<1>(acc, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = acc[0];
+}
+
+template <int Q, typename R>
+__global__ __launch_bounds__(256) void k_ke_seed(Geom g, const R* fpre, const uint8_t* mask, ForceArgs<R> force,
+                                                 double scale, R* lam, double* dLdF, double* partials) {
+  double acc[3] = {0, 0, 0};
+  for (uint32_t n = blockIdx.x * blockDim.x + threadIdx.x; n < g.N; n += gridDim.x * blockDim.x) {
+    if (mask && mask[n]) {
+#pragma unroll
+      for (int a = 0; a < Q; ++a) lam[uint64_t(a) * g.N + n] = R(0);
+      continue;
+    }
+    R Fx, Fy, Fz;
+    force_at(force, g.N, n, Fx, Fy, Fz);
+    R rho, ux, uy, uz;
+    node_moments<Q>(fpre, g.N, n, Fx, Fy, Fz, rho, ux, uy, uz);
+    const R half_u2 = R(0.5) * (ux * ux + uy * uy + uz * uz);
+    const R sc = R(scale);
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      const Vel e = Lattice<Q>::e(a);
+      lam[uint64_t(a) * g.N + n] = sc * (R(e.x) * ux + R(e.y) * uy + R(e.z) * uz - half_u2);
+    }
+    const double c = 0.5 * scale * double(force.scale);
+    if (force.field) {
+      dLdF[n] += c * double(ux);
+      dLdF[g.N + n] += c * double(uy);
+      dLdF[2 * g.N + n] += c * double(uz);
+    } else {
+      acc[0] += c * double(ux);
+      acc[1] += c * double(uy);
+      acc[2] += c * double(uz);
+    }
+  }
+  __shared__ double sh[3 * 8];
+  block_sum<3>(acc, sh);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) partials[uint64_t(blockIdx.x) * 3 + i] = acc[i];
+  }
+}
+
+// Adjoint of the initial condition fbar(x, 0) = f^eq(rho0, u0) - S(F, u0)/2
+// with respect to F (D3Q27): S is the inverse-pass image of the central moments
+// (0; F; 0, ...), so dL/dF = -(scale/2) (first-order rows of P(u0)^T lam0).
+template <typename R>
+__global__ __launch_bounds__(256) void k_init_adjoint27(Geom g, const R* u0, const R* lam0, const uint8_t* mask,
+                                                        ForceArgs<R> force, double* dLdF, double* partials) {
+  double acc[3] = {0, 0, 0};
+  for (uint32_t n = blockIdx.x * blockDim.x + threadIdx.x; n < g.N; n += gridDim.x * blockDim.x) {
+    if (mask && mask[n]) continue;
+    const R ux = u0[n], uy = u0[g.N + n], uz = u0[2 * g.N + n];
+    R gm[27], zero[27];
+#pragma unroll
+    for (int a = 0; a < 27; ++a) {
+      gm[cube27(a)] = lam0[uint64_t(a) * g.N + n];
+      zero[a] = R(0);
+    }
+    R gu = R(0);
+    inv_pass_adj<2>(zero, uz, gm, gu);
+    inv_pass_adj<1>(zero, uy, gm, gu);
+    inv_pass_adj<0>(zero, ux, gm, gu);
+    const double c = -0.5 * double(force.scale);
+    const double gx = c * double(gm[K3(1, 0, 0)]), gy = c * double(gm[K3(0, 1, 0)]), gz = c * double(gm[K3(0, 0, 1)]);
+    if (force.field) {
+      dLdF[n] += gx;
+      dLdF[g.N + n] += gy;
+      dLdF[2 * g.N + n] += gz;
+    } else {
+      acc[0] += gx;
+      acc[1] += gy;
+      acc[2] += gz;
+    }
+  }
+  __shared__ double sh[3 * 8];
+  block_sum<3>(acc, sh);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) partials[uint64_t(blockIdx.x) * 3 + i] = acc[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Host-side launchers
 // ---------------------------------------------------------------------------
 namespace {
@@ -465,28 +704,41 @@ struct StorageFor;
 
 constexpr int kBlock = 256;
 
-inline dim3 step_grid(const Geom& g, int bx) {
-  return dim3((g.nx + bx - 1) / bx, g.ny, g.nz);
-}
-
 inline int step_block(const Geom& g) {
-  int bx = kBlock;
-  if (g.nx < kBlock) bx = ((g.nx + 63) / 64) * 64;
+  int bx = CMLBM_STEP_BLOCK;
+  if (g.nx < bx) bx = ((g.nx + 63) / 64) * 64;
   return bx;
 }
+
+inline dim3 step_grid(const Geom& g, int bx) {
+  return dim3(unsigned((g.nx + bx - 1) / bx) * unsigned(g.ny) * unsigned(g.nz));
+}
+
+inline int adjoint_block(const Geom& g) { return g.nx < 256 ? ((g.nx + 63) / 64) * 64 : 256; }
 
 inline unsigned aux_grid(const Geom& g) {
   const uint64_t need = (g.N + kBlock - 1) / kBlock;
   return unsigned(need < 8192 ? (need == 0 ? 1 : need) : 8192);
 }
 
+// Arrays of 4 GiB or more need 64-bit element offsets.
+inline bool wide(const Geom& g, size_t elem) { return g.N * elem >= (uint64_t(1) << 32); }
+
 template <int Q, class ST>
 hipError_t step_impl(const StepArgs<typename ST::R>& a, hipStream_t st) {
   const int bx = step_block(a.g);
-  if (a.mask)
-    hipLaunchKernelGGL((k_step<Q, ST, true>), step_grid(a.g, bx), dim3(bx), 0, st, a);
-  else
-    hipLaunchKernelGGL((k_step<Q, ST, false>), step_grid(a.g, bx), dim3(bx), 0, st, a);
+  const bool w = wide(a.g, sizeof(typename ST::R));
+  if (a.mask) {
+    if (w)
+      hipLaunchKernelGGL((k_step<Q, ST, true, true>), step_grid(a.g, bx), dim3(bx), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_step<Q, ST, true, false>), step_grid(a.g, bx), dim3(bx), 0, st, a);
+  } else {
+    if (w)
+      hipLaunchKernelGGL((k_step<Q, ST, false, true>), step_grid(a.g, bx), dim3(bx), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_step<Q, ST, false, false>), step_grid(a.g, bx), dim3(bx), 0, st, a);
+  }
   return hipGetLastError();
 }
 
@@ -538,9 +790,9 @@ template <class ST>
 hipError_t adjoint_impl(const AdjArgs<typename ST::R>& a, double* partials, int nblk, double* dLdomega,
                         double* dLdF_uniform, hipStream_t st) {
   if (a.mask)
-    hipLaunchKernelGGL((k_adjoint27<ST, true>), dim3(nblk), dim3(step_block(a.g)), 0, st, a, partials);
+    hipLaunchKernelGGL((k_adjoint27<ST, true>), dim3(nblk), dim3(adjoint_block(a.g)), 0, st, a, partials);
   else
-    hipLaunchKernelGGL((k_adjoint27<ST, false>), dim3(nblk), dim3(step_block(a.g)), 0, st, a, partials);
+    hipLaunchKernelGGL((k_adjoint27<ST, false>), dim3(nblk), dim3(adjoint_block(a.g)), 0, st, a, partials);
   hipLaunchKernelGGL(k_reduce_rows, dim3(23), dim3(kBlock), 0, st, partials, nblk, 26, dLdomega, 1);
   if (dLdF_uniform)
     hipLaunchKernelGGL(k_reduce_rows, dim3(3), dim3(kBlock), 0, st, partials + 23, nblk, 26, dLdF_uniform, 1);
@@ -622,5 +874,60 @@ hipError_t launch_adjoint(int prec, const AdjArgs<double>& a64, const AdjArgs<fl
 }
 
 #undef CMLBM_DISPATCH
+
+namespace {
+template <int Q, typename R>
+hipError_t ke_sum_impl(const Geom& g, const void* fpre, const uint8_t* mask, const ForceArgs<R>& f, double* partials,
+                       int nblk, double* out, hipStream_t st) {
+  hipLaunchKernelGGL((k_ke_sum<Q, R>), dim3(nblk), dim3(kBlock), 0, st, g, static_cast<const R*>(fpre), mask, f,
+                     partials);
+  hipLaunchKernelGGL(k_reduce_rows, dim3(1), dim3(kBlock), 0, st, partials, nblk, 1, out, 0);
+  return hipGetLastError();
+}
+template <int Q, typename R>
+hipError_t ke_seed_impl(const Geom& g, const void* fpre, const uint8_t* mask, const ForceArgs<R>& f, double scale,
+                        void* lam, double* dLdF, double* partials, int nblk, hipStream_t st) {
+  hipLaunchKernelGGL((k_ke_seed<Q, R>), dim3(nblk), dim3(kBlock), 0, st, g, static_cast<const R*>(fpre), mask, f,
+                     scale, static_cast<R*>(lam), dLdF, partials);
+  if (!f.field) hipLaunchKernelGGL(k_reduce_rows, dim3(3), dim3(kBlock), 0, st, partials, nblk, 3, dLdF, 1);
+  return hipGetLastError();
+}
+template <typename R>
+hipError_t init_adj_impl(const Geom& g, const void* u0, const void* lam0, const uint8_t* mask, const ForceArgs<R>& f,
+                         double* dLdF, double* partials, int nblk, hipStream_t st) {
+  hipLaunchKernelGGL((k_init_adjoint27<R>), dim3(nblk), dim3(kBlock), 0, st, g, static_cast<const R*>(u0),
+                     static_cast<const R*>(lam0), mask, f, dLdF, partials);
+  if (!f.field) hipLaunchKernelGGL(k_reduce_rows, dim3(3), dim3(kBlock), 0, st, partials, nblk, 3, dLdF, 1);
+  return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_ke_sum(int q, int prec, const Geom& g, const void* fpre, const uint8_t* mask,
+                         const ForceArgs<double>& f64, const ForceArgs<float>& f32, double* partials, int nblk,
+                         double* out, hipStream_t st) {
+  if (prec == 0)
+    return q == 27 ? ke_sum_impl<27>(g, fpre, mask, f64, partials, nblk, out, st)
+                   : ke_sum_impl<15>(g, fpre, mask, f64, partials, nblk, out, st);
+  return q == 27 ? ke_sum_impl<27>(g, fpre, mask, f32, partials, nblk, out, st)
+                 : ke_sum_impl<15>(g, fpre, mask, f32, partials, nblk, out, st);
+}
+
+hipError_t launch_ke_seed(int q, int prec, const Geom& g, const void* fpre, const uint8_t* mask,
+                          const ForceArgs<double>& f64, const ForceArgs<float>& f32, double scale, void* lam,
+                          double* dLdF, double* partials, int nblk, hipStream_t st) {
+  if (prec == 0)
+    return q == 27 ? ke_seed_impl<27>(g, fpre, mask, f64, scale, lam, dLdF, partials, nblk, st)
+                   : ke_seed_impl<15>(g, fpre, mask, f64, scale, lam, dLdF, partials, nblk, st);
+  return q == 27 ? ke_seed_impl<27>(g, fpre, mask, f32, scale, lam, dLdF, partials, nblk, st)
+                 : ke_seed_impl<15>(g, fpre, mask, f32, scale, lam, dLdF, partials, nblk, st);
+}
+
+hipError_t launch_init_adjoint(int prec, const Geom& g, const void* u0, const void* lam0, const uint8_t* mask,
+                               const ForceArgs<double>& f64, const ForceArgs<float>& f32, double* dLdF,
+                               double* partials, int nblk, hipStream_t st) {
+  if (prec == 0) return init_adj_impl<double>(g, u0, lam0, mask, f64, dLdF, partials, nblk, st);
+  return init_adj_impl<float>(g, u0, lam0, mask, f32, dLdF, partials, nblk, st);
+}
+
 
 }  // namespace cmlbm

@@ -67,6 +67,16 @@ hipError_t launch_init(int q, int prec, const Geom& g, const void* rho0, const v
 hipError_t launch_adjoint(int prec, const AdjArgs<double>& a64, const AdjArgs<float>& a32, double* partials,
                           int nblk, double* dLdomega, double* dLdF_uniform, hipStream_t st);
 
+hipError_t launch_ke_sum(int q, int prec, const Geom& g, const void* fpre, const uint8_t* mask,
+                         const ForceArgs<double>& f64, const ForceArgs<float>& f32, double* partials, int nblk,
+                         double* out, hipStream_t st);
+hipError_t launch_ke_seed(int q, int prec, const Geom& g, const void* fpre, const uint8_t* mask,
+                          const ForceArgs<double>& f64, const ForceArgs<float>& f32, double scale, void* lam,
+                          double* dLdF, double* partials, int nblk, hipStream_t st);
+hipError_t launch_init_adjoint(int prec, const Geom& g, const void* u0, const void* lam0, const uint8_t* mask,
+                               const ForceArgs<double>& f64, const ForceArgs<float>& f32, double* dLdF,
+                               double* partials, int nblk, hipStream_t st);
+
 // Blocks of the grid-stride adjoint launch (each thread visits at most 8 nodes).
 inline int adjoint_blocks(const Geom& g) {
   const int bx = g.nx < 256 ? ((g.nx + 63) / 64) * 64 : 256;

@@ -1,0 +1,72 @@
+"""Host logic of the checkpoint-and-recompute sweeps (no GPU): a fake
+simulator whose states are step counters checks that every adjoint step sees
+the right forward state, in reverse order, with the predicted number of
+recomputed steps and a bounded number of live buffers."""
+import pytest
+
+from paper_1202_6081_amd import autograd as ag
+
+
+class _State:
+    def __init__(self):
+        self.t = None
+
+
+class FakeSim:
+    def __init__(self):
+        self.steps = 0
+        self.seen = []
+
+    def populations(self):
+        return _State()
+
+    def step(self, src, dst):
+        assert src is not dst and src.t is not None
+        dst.t = src.t + 1
+        self.steps += 1
+
+    def adjoint_step(self, x, lam, lam_tmp, dLdF, dLdw):
+        self.seen.append(x.t)
+
+
+def _run(nsteps, every=None, snapshots=None):
+    sim = FakeSim()
+    pool = ag._Pool(sim)
+    x0 = pool.get()
+    x0.t = 0
+    stored, last = ag.forward_sweep(sim, pool, x0, nsteps, ag.keep_positions(nsteps, every, snapshots))
+    assert last.t == nsteps and sim.steps == nsteps
+    if not any(last is v for v in stored.values()):
+        pool.put(last)
+    sim.steps = 0
+    sw = ag._Sweep(sim, pool, None, None, None, None)
+    ag.backward_sweep(sw, stored, nsteps, every, snapshots)
+    assert sim.seen == list(range(nsteps - 1, -1, -1))
+    return sim, sw, pool, stored
+
+
+@pytest.mark.parametrize("nsteps,every", [(200, 20), (37, 5), (10, 10), (7, 1), (1, 3)])
+def test_uniform_checkpoints(nsteps, every):
+    sim, sw, pool, stored = _run(nsteps, every=every)
+    assert sw.recomputed == sim.steps
+    # each segment of length L replays L - 1 steps
+    nseg = -(-nsteps // every)
+    assert sw.recomputed == nsteps - nseg
+
+
+@pytest.mark.parametrize("nsteps,s", [(100, 10), (100, 4), (50, 1), (30, 0), (12, 20), (1, 2), (2, 1)])
+def test_binomial_schedule(nsteps, s):
+    sim, sw, pool, stored = _run(nsteps, snapshots=s)
+    assert sw.recomputed == sim.steps == ag.recompute_steps(nsteps, s)
+    # live buffers: x0, at most s snapshots, two work buffers
+    assert pool.allocated <= s + 3
+
+
+def test_binomial_cost_closed_cases():
+    assert ag._cost(1, 3)[0] == 0
+    assert ag._cost(10, 0)[0] == 45
+    assert ag._cost(10, 9)[0] == 9            # enough slots: one pass storing everything
+    # more slots never cost more
+    for n in (20, 60, 100):
+        costs = [ag._cost(n, s)[0] for s in range(0, 12)]
+        assert all(a >= b for a, b in zip(costs, costs[1:]))

@@ -1,0 +1,171 @@
+"""GPU parity of the D3Q27 adjoint (through the C ABI) against derivatives of the
+FP64 oracle taken by the complex step (exact to rounding: every operation of
+the step is analytic).
+
+* one adjoint step: <lam, v> = d/de <mu, step(fbar + e v)> for random v, and the
+  same for the force field and the 23 rates;
+* a whole differentiable run (checkpointed, both schedules): dL/dF and
+  dL/domega of the mean kinetic energy after N steps;
+* the 64^3, 200-step, checkpoint-every-20 configuration: FP32 gradient against
+  the FP64 GPU gradient, and the FP64 GPU gradient against central finite
+  differences of the FP64 GPU forward run.
+"""
+import numpy as np
+import pytest
+import torch
+
+import lbm_inputs as inp
+from gpu_helpers import gpu_setup, shear_rates
+from oracle import lbm
+from oracle.lattice import D3Q27
+
+pytestmark = pytest.mark.gpu
+
+F64, F32 = 0, 1
+H = 1e-30            # complex-step size
+
+
+def _walls(shape):
+    solid = np.zeros(shape, dtype=bool)
+    solid[0] = True
+    solid[shape[0] // 2, shape[1] // 2, shape[2] // 3] = True
+    return solid
+
+
+@pytest.mark.parametrize("force_kind", ["field", "uniform"])
+@pytest.mark.parametrize("masked", [False, True])
+def test_single_adjoint_step(force_kind, masked):
+    print(f"case adjoint-step {force_kind} masked={masked}", flush=True)
+    shape = (5, 6, 67)
+    rng = np.random.default_rng(21)
+    om = list(rng.uniform(0.7, 1.9, 23))
+    F = inp.gaussian_force(shape, 1e-4, 4) if force_kind == "field" else np.array([2e-4, -1e-4, 3e-5])
+    solid = _walls(shape) if masked else None
+    fluid = np.ones(shape, bool) if solid is None else ~solid
+    sim = gpu_setup(27, shape, F64, om, F, solid)
+    rho0 = 1 + 0.01 * rng.standard_normal(shape)
+    u0 = 0.05 * rng.uniform(-1, 1, (3,) + shape)
+    x, _ = sim.init_equilibrium(torch.from_numpy(rho0).cuda(), torch.from_numpy(u0).cuda())
+    x = sim.run(x, sim.populations(), 2)
+    f_pre = sim.gather(x).cpu().numpy()
+    mu = rng.standard_normal((27,) + shape)
+    mu[:, ~fluid] = 0.0
+    lam = torch.zeros((27,) + shape, dtype=torch.float64, device="cuda")
+    dLdF = torch.zeros(F.shape, dtype=torch.float64, device="cuda")
+    dLdw = torch.zeros(23, dtype=torch.float64, device="cuda")
+    sim.adjoint_step(x, torch.from_numpy(mu).cuda(), lam, dLdF, dLdw)
+    lam = lam.cpu().numpy()
+    lam[:, ~fluid] = 0.0
+    dLdF = dLdF.cpu().numpy()
+    dLdw = dLdw.cpu().numpy()
+
+    def L(f, Fv, w):
+        return np.sum(mu * lbm.step(D3Q27, f, Fv, w, solid))
+
+    for k in range(3):
+        v = rng.standard_normal(f_pre.shape)
+        v[:, ~fluid] = 0.0
+        ref = L(f_pre + 1j * H * v, F.astype(complex), np.array(om, dtype=complex)).imag / H
+        assert abs(np.sum(lam * v) - ref) <= 1e-10 * abs(ref) + 1e-14, (k, np.sum(lam * v), ref)
+        vF = rng.standard_normal(F.shape)
+        if F.ndim > 1:
+            vF[:, ~fluid] = 0.0
+        ref = L(f_pre.astype(complex), F + 1j * H * vF, np.array(om, dtype=complex)).imag / H
+        assert abs(np.sum(dLdF * vF) - ref) <= 1e-9 * abs(ref) + 1e-14, (k, np.sum(dLdF * vF), ref)
+    for b in range(23):
+        w = np.array(om, dtype=complex)
+        w[b] += 1j * H
+        ref = L(f_pre.astype(complex), F.astype(complex), w).imag / H
+        assert abs(dLdw[b] - ref) <= 1e-9 * abs(ref) + 1e-13, (b, dLdw[b], ref)
+
+
+def _oracle_loss(rho0, u0, F, om, nsteps, solid):
+    f = lbm.initial_state(D3Q27, rho0, u0, F, solid)
+    f = lbm.run(D3Q27, f, F, om, nsteps, solid)
+    return lbm.kinetic_energy(D3Q27, f, F, solid)
+
+
+@pytest.mark.parametrize("schedule", [{"every": 2}, {"snapshots": 2}, {"snapshots": 0}])
+@pytest.mark.parametrize("masked", [False, True])
+def test_whole_run_gradient_fp64(schedule, masked):
+    from paper_1202_6081_amd import autograd as ag
+    print(f"case run-grad {schedule} masked={masked}", flush=True)
+    shape = (4, 5, 66)
+    nsteps = 6
+    rng = np.random.default_rng(31)
+    om = np.array(rng.uniform(0.8, 1.9, 23))
+    F = inp.gaussian_force(shape, 1e-4, 8)
+    solid = _walls(shape) if masked else None
+    fluid = np.ones(shape, bool) if solid is None else ~solid
+    rho0 = 1 + 0.01 * rng.standard_normal(shape)
+    u0 = 0.05 * rng.uniform(-1, 1, (3,) + shape)
+    sim = gpu_setup(27, shape, F64, list(om), None, solid)
+    Ft = torch.from_numpy(F).cuda().requires_grad_(True)
+    wt = torch.from_numpy(om.copy()).requires_grad_(True)
+    out = ag.run(sim, torch.from_numpy(rho0).cuda(), torch.from_numpy(u0).cuda(), Ft, wt, nsteps, **schedule)
+    loss = ag.kinetic_energy(sim, out, Ft, n_fluid=int(fluid.sum()))
+    loss.backward()
+    ref_loss = _oracle_loss(rho0, u0, F, om, nsteps, solid)
+    assert abs(float(loss) - ref_loss) <= 1e-12 * abs(ref_loss)
+    gF = Ft.grad.cpu().numpy()
+    gw = wt.grad.numpy()
+    for k in range(3):
+        v = rng.standard_normal(F.shape)
+        v[:, ~fluid] = 0.0
+        ref = _oracle_loss(rho0, u0, F + 1j * H * v, om.astype(complex), nsteps, solid).imag / H
+        assert abs(np.sum(gF * v) - ref) <= 1e-9 * abs(ref), (k, np.sum(gF * v), ref)
+    for vw in (np.r_[np.ones(5), np.zeros(18)], rng.standard_normal(23)):
+        ref = _oracle_loss(rho0, u0, F.astype(complex), om + 1j * H * vw, nsteps, solid).imag / H
+        assert abs(np.sum(gw * vw) - ref) <= 1e-9 * abs(ref), (np.sum(gw * vw), ref)
+
+
+def _config4(prec, F=None, om_shear=1.6, nsteps=200, every=20, n=64, want_grad=True):
+    from paper_1202_6081_amd import autograd as ag
+    from paper_1202_6081_amd import cmlbm
+    sim = cmlbm.Sim(27, n, n, n, prec)
+    u0 = torch.from_numpy(inp.taylor_green(n, 0.02)).cuda()
+    rho0 = torch.ones((n, n, n), dtype=torch.float64, device="cuda")
+    Ft = torch.from_numpy(F).cuda().requires_grad_(want_grad)
+    wt = torch.tensor([om_shear] * 5 + [1.0] * 18, dtype=torch.float64, requires_grad=want_grad)
+    out = ag.run(sim, rho0, u0, Ft, wt, nsteps, every=every)
+    loss = ag.kinetic_energy(sim, out, Ft)
+    if not want_grad:
+        return float(loss)
+    loss.backward()
+    st = ag.last_backward_stats()
+    return float(loss), st["dLdF_fp64"].cpu().numpy(), st["dLdomega_fp64"].cpu().numpy()
+
+
+def test_config_64cubed_200_steps():
+    # Taylor-Green (k0 = 2 pi/64, u0 = 0.02), F ~ N(0, (1e-6)^2) per node and
+    # component (seed 2024), shear 1.6, loss = mean KE after 200 steps,
+    # checkpoints every 20 steps.
+    print("case config4 64^3", flush=True)
+    n = 64
+    F = inp.gaussian_force((n, n, n), 1e-6, 2024)
+    L64, gF64, gw64 = _config4(F64, F)
+    L32, gF32, gw32 = _config4(F32, F)
+    rel = np.linalg.norm(gF32 - gF64) / np.linalg.norm(gF64)
+    relw = abs(gw32[:5].sum() - gw64[:5].sum()) / abs(gw64[:5].sum())
+    print(f"config4: loss {L64:.10e}  |dL/dF| {np.linalg.norm(gF64):.4e}  dL/dw_shear {gw64[:5].sum():.6e}  "
+          f"FP32 vs FP64: dL/dF rel L2 {rel:.3e}, dL/dw_shear rel {relw:.3e}", flush=True)
+    assert abs(L32 - L64) <= 1e-5 * abs(L64)
+    assert rel < 2e-3 and relw < 2e-3
+    # central finite differences of the FP64 GPU forward run along random directions
+    rng = np.random.default_rng(5)
+    for k in range(2):
+        v = rng.standard_normal(F.shape)
+        v /= np.linalg.norm(v)
+        h = 1e-5
+        Lp = _config4(F64, F + h * v, want_grad=False)
+        Lm = _config4(F64, F - h * v, want_grad=False)
+        fd = (Lp - Lm) / (2 * h)
+        an = float(np.sum(gF64 * v))
+        print(f"config4 FD dir {k}: fd {fd:.8e} adjoint {an:.8e}", flush=True)
+        assert abs(fd - an) <= 1e-5 * abs(an)
+    hw = 1e-5
+    Lp = _config4(F64, F, om_shear=1.6 + hw, want_grad=False)
+    Lm = _config4(F64, F, om_shear=1.6 - hw, want_grad=False)
+    fd = (Lp - Lm) / (2 * hw)
+    print(f"config4 FD shear: fd {fd:.8e} adjoint {gw64[:5].sum():.8e}", flush=True)
+    assert abs(fd - gw64[:5].sum()) <= 1e-5 * abs(fd)

@@ -91,7 +91,7 @@ def test_forward_matches_oracle(case):
         if prec == F64:
             assert rel_err(got, states[0], fluid) < tol
         else:
-            assert _absdiff(got, states[0], fluid) < 2e-7
+            assert _absdiff(got, states[0], fluid) < 5e-7      # FP32 rounding of the init
     other = sim.populations()
     for n in range(1, steps + 1):
         sim.step(f_post, other)
