@@ -21,11 +21,20 @@
  * Streams:    `stream` is a hipStream_t (NULL = the default stream).  Work is
  *             enqueued asynchronously; only cmlbm_totals synchronizes.
  * Threads:    a handle must not be used by two host threads at once.
- * Layout:     structure of arrays, x fastest.  Populations f[a][nz][ny][nx]
- *             with directions a in the paper's order (Eq. velocityd3qq27 and
- *             Appendix A for D3Q27; Appendix G for D3Q15).  Vector fields
- *             (velocity, force, force gradient) are [3][nz][ny][nx].
- *             Scalars are [nz][ny][nx].
+ * Layout:     fields are structure of arrays, x fastest: vector fields
+ *             (velocity, force, force gradient) [3][nz][ny][nx], scalars
+ *             [nz][ny][nx], and "SoA populations" f[a][nz][ny][nx] with
+ *             directions a in the paper's order (Eq. velocityd3qq27 and
+ *             Appendix A for D3Q27; Appendix G for D3Q15).
+ *             The population *buffers* of cmlbm_step / cmlbm_run (q * nx * ny *
+ *             nz values of the storage type) use a blocked row layout: row
+ *             r = z*ny + y holds q*nx values; inside a row x is cut into blocks
+ *             of 64 consecutive nodes (the last may be shorter) and a block
+ *             stores its q directions one after the other:
+ *               index(a, r, x) = r*nx*q + b*64*q + a*len + (x - 64*b),
+ *               b = x / 64, len = min(64, nx - 64*b).
+ *             cmlbm_export_populations / cmlbm_import_populations convert to
+ *             and from SoA populations.
  * State:      the population buffers passed to cmlbm_step / cmlbm_run hold the
  *             post-collision, not yet streamed populations fbar~ (Eq.
  *             cascadedcollision1).  The paper's state, the pre-collision
@@ -121,6 +130,15 @@ cmlbm_status cmlbm_step(cmlbm_sim *sim, const void *f_in, void *f_out, void *str
 /* nsteps >= 0 steps ping-ponging between f_a and f_b, starting from f_a.
  * *result_in_b (may be NULL) is set to 1 when the last state is in f_b. */
 cmlbm_status cmlbm_run(cmlbm_sim *sim, void *f_a, void *f_b, int nsteps, void *stream, int *result_in_b);
+
+/* Copy a population buffer (blocked layout, storage type) into SoA
+ * populations of "real" type [q][nz][ny][nx], decoding the 16-bit deviation
+ * formats (the post-collision values themselves, not streamed).  f_buf != f_soa. */
+cmlbm_status cmlbm_export_populations(cmlbm_sim *sim, const void *f_buf, void *f_soa, void *stream);
+
+/* The inverse: SoA "real" populations into a population buffer (16-bit
+ * formats store the rounded deviation from w_a). */
+cmlbm_status cmlbm_import_populations(cmlbm_sim *sim, const void *f_soa, void *f_buf, void *stream);
 
 /* The paper's state: pre-collision fbar(x, t) pulled from the post-collision
  * buffer f_post, as full "real" populations [q][nz][ny][nx] (zeros at solid

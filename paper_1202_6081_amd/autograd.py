@@ -206,6 +206,7 @@ class _Run(torch.autograd.Function):
         ctx.sim, ctx.pool, ctx.stored = sim, pool, stored
         ctx.u0, ctx.nsteps, ctx.every, ctx.snapshots = u0r, nsteps, every, snapshots
         ctx.F_dtype, ctx.w_dtype, ctx.F_shape = F.dtype, omega.dtype, F.shape
+        ctx.F_device, ctx.w_device = F.device, omega.device
         ctx.Fr = Fr
         return pre
 
@@ -224,7 +225,8 @@ class _Run(torch.autograd.Function):
         _last_stats.update(ctx.stats)
         _last_stats["dLdF_fp64"] = dLdF
         _last_stats["dLdomega_fp64"] = dLdw
-        return (dLdF.to(ctx.F_dtype), dLdw.to(ctx.w_dtype), None, None, None, None, None, None)
+        return (dLdF.to(device=ctx.F_device, dtype=ctx.F_dtype), dLdw.to(device=ctx.w_device, dtype=ctx.w_dtype),
+                None, None, None, None, None, None)
 
 
 _last_stats = {}
@@ -315,6 +317,7 @@ def benchmark_adjoint_ratio(sim, nsteps, forward_ms_per_step, budget_gib=200.0):
     fwd_ms = (t1 - t0) * 1e3
     bwd_ms = (t2 - t1) * 1e3
     dLdw_shear = float(st["dLdomega_fp64"][:5].sum())
+    recomputed, adj_steps = st["recomputed"], st["adjoint_steps"]
     del out, loss, st
     _last_stats.clear()
     # average duration of the adjoint step kernel alone (events on the launch stream)
@@ -339,7 +342,7 @@ def benchmark_adjoint_ratio(sim, nsteps, forward_ms_per_step, budget_gib=200.0):
     return {
         "steps": nsteps, "snapshots": snaps, "budget_gib": budget_gib,
         "peak_alloc_gib": round(peak / 2**30, 1),
-        "recomputed_steps": st["recomputed"], "adjoint_steps": st["adjoint_steps"],
+        "recomputed_steps": recomputed, "adjoint_steps": adj_steps,
         "forward_pass_ms": round(fwd_ms, 1), "backward_ms": round(bwd_ms, 1),
         "ratio_backward_over_forward_steps": round(bwd_ms / (nsteps * forward_ms_per_step), 3),
         "adjoint_step_ms": round(adj_ms, 3),

@@ -48,6 +48,8 @@ def load_library():
         "cmlbm_step": (i, [vp, vp, vp, vp]),
         "cmlbm_run": (i, [vp, vp, vp, i, vp, ctypes.POINTER(i)]),
         "cmlbm_gather_precollision": (i, [vp, vp, vp, vp]),
+        "cmlbm_export_populations": (i, [vp, vp, vp, vp]),
+        "cmlbm_import_populations": (i, [vp, vp, vp, vp]),
         "cmlbm_macroscopic": (i, [vp, vp, vp, vp, vp]),
         "cmlbm_totals": (i, [vp, vp, ctypes.POINTER(d), vp]),
         "cmlbm_adjoint_step": (i, [vp, vp, vp, vp, vp, vp, vp]),
@@ -69,7 +71,8 @@ def load_library():
 def exported_symbols():
     return ["cmlbm_create", "cmlbm_destroy", "cmlbm_set_rates", "cmlbm_set_force_uniform",
             "cmlbm_set_force_field", "cmlbm_set_force_scale", "cmlbm_set_mask", "cmlbm_init_equilibrium",
-            "cmlbm_step", "cmlbm_run", "cmlbm_gather_precollision", "cmlbm_macroscopic", "cmlbm_totals",
+            "cmlbm_step", "cmlbm_run", "cmlbm_gather_precollision", "cmlbm_export_populations",
+            "cmlbm_import_populations", "cmlbm_macroscopic", "cmlbm_totals",
             "cmlbm_adjoint_step", "cmlbm_kinetic_energy_sum", "cmlbm_kinetic_energy_seed", "cmlbm_init_adjoint",
             "cmlbm_status_string", "cmlbm_last_error", "cmlbm_version"]
 
@@ -169,6 +172,14 @@ def cmlbm_run(h, f_a, f_b, nsteps, stream=None):
 
 def cmlbm_gather_precollision(h, f_post, f_pre, stream=None):
     _check(load_library().cmlbm_gather_precollision(h, _ptr(f_post), _ptr(f_pre), _stream(stream)), h)
+
+
+def cmlbm_export_populations(h, f_buf, f_soa, stream=None):
+    _check(load_library().cmlbm_export_populations(h, _ptr(f_buf), _ptr(f_soa), _stream(stream)), h)
+
+
+def cmlbm_import_populations(h, f_soa, f_buf, stream=None):
+    _check(load_library().cmlbm_import_populations(h, _ptr(f_soa), _ptr(f_buf), _stream(stream)), h)
 
 
 def cmlbm_macroscopic(h, f_post, rho, u, stream=None):
@@ -286,6 +297,16 @@ class Sim:
         out = self.real_populations() if out is None else out
         cmlbm_gather_precollision(self.h, f_post, out, stream)
         return out
+
+    def export_populations(self, f_buf, out=None, stream=None):
+        out = self.real_populations() if out is None else out
+        cmlbm_export_populations(self.h, f_buf, out, stream)
+        return out
+
+    def import_populations(self, f_soa, f_buf=None, stream=None):
+        f_buf = self.populations() if f_buf is None else f_buf
+        cmlbm_import_populations(self.h, f_soa.to(device=self.device, dtype=self.real).contiguous(), f_buf, stream)
+        return f_buf
 
     def macroscopic(self, f_post, stream=None):
         rho = torch.empty((self.nz, self.ny, self.nx), dtype=self.real, device=self.device)

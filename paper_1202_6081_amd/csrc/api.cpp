@@ -263,6 +263,22 @@ cmlbm_status cmlbm_gather_precollision(cmlbm_sim* s, const void* f_post, void* f
   return check_hip(s, e, "gather_precollision");
 }
 
+cmlbm_status cmlbm_export_populations(cmlbm_sim* s, const void* f_buf, void* f_soa, void* stream) {
+  if (!s) return CMLBM_EINVAL;
+  if (!f_buf || !f_soa) return fail(s, CMLBM_EINVAL, "NULL buffer");
+  if (f_buf == f_soa) return fail(s, CMLBM_EINVAL, "f_buf and f_soa must differ");
+  hipError_t e = cmlbm::launch_convert(s->q, s->prec, s->g, f_buf, f_soa, true, static_cast<hipStream_t>(stream));
+  return check_hip(s, e, "export_populations");
+}
+
+cmlbm_status cmlbm_import_populations(cmlbm_sim* s, const void* f_soa, void* f_buf, void* stream) {
+  if (!s) return CMLBM_EINVAL;
+  if (!f_buf || !f_soa) return fail(s, CMLBM_EINVAL, "NULL buffer");
+  if (f_buf == f_soa) return fail(s, CMLBM_EINVAL, "f_buf and f_soa must differ");
+  hipError_t e = cmlbm::launch_convert(s->q, s->prec, s->g, f_soa, f_buf, false, static_cast<hipStream_t>(stream));
+  return check_hip(s, e, "import_populations");
+}
+
 cmlbm_status cmlbm_macroscopic(cmlbm_sim* s, const void* f_post, void* rho, void* u, void* stream) {
   if (!s) return CMLBM_EINVAL;
   if (!f_post || !rho || !u) return fail(s, CMLBM_EINVAL, "NULL buffer");

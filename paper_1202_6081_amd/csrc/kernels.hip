@@ -1,14 +1,22 @@
 // HIP kernels of the central-moment LBM step for CDNA4 (gfx950).
 //
-// Data layout in HBM: populations as structure of arrays f[a][z][y][x]
-// (x fastest), directions a in the paper's order (Eq. velocityd3qq27 /
-// Appendix G).  The stored state is the post-collision, not yet streamed
-// fbar~; a step pulls fbar_a(x) = fbar~_a(x - e_a) (Eq. cascadedstreaming1 read
-// backwards), with half-way bounce-back fbar_a(x) = fbar~_abar(x) when x - e_a is
-// a solid node, collides in registers and writes fbar~(x) at x.  Each wavefront
-// covers 64 consecutive x of one row, so every load and store of one direction
-// is a contiguous 256 B (FP32) stream; the +-1 shifts in x only straddle one
-// extra cache line that the neighbouring wave also touches.
+// Population buffers (the post-collision, not yet streamed fbar~ of Eq.
+// cascadedcollision1) use a blocked row layout.  Row r = z*ny + y holds Q*nx
+// values; inside a row, x is cut into blocks of 64 consecutive nodes (the last
+// block may be shorter) and each block stores its Q directions one after the
+// other, 64 values each:
+//     element(a, r, x) = r*nx*Q + b*64*Q + a*len(b) + (x - 64 b),  b = x/64,
+//     len(b) = min(64, nx - 64 b).
+// A wavefront covers one block, so the 27 direction streams of one wavefront's
+// stores fall in one contiguous 27*256 B (FP32) region and its loads in nine
+// such regions (one per source row), which keeps DRAM page locality with 55
+// concurrent streams.  Directions are in the paper's order (Eq.
+// velocityd3qq27 / Appendix G).  Fields (force, velocity, mask, adjoints) stay
+// structure of arrays [c][z][y][x].
+//
+// A step pulls fbar_a(x) = fbar~_a(x - e_a) (Eq. cascadedstreaming1 read
+// backwards), with half-way bounce-back fbar_a(x) = fbar~_abar(x) when x - e_a
+// is a solid node, collides in registers and writes fbar~(x).
 //
 // Storage variants: FP64, FP32, and FP32 compute with the deviation
 // fbar - w_a stored as FP16 or BF16 (round to nearest even).
@@ -64,32 +72,19 @@ __device__ __forceinline__ typename ST::T encode(typename ST::R v, int a) {
     return v;
 }
 
+// Element idx of an array whose byte size fits in 32 bits: a uniform base
+// pointer plus a 32-bit byte offset, which maps onto the scalar-base form of
+// the global load instructions.
+template <typename T>
+__device__ __forceinline__ T ld32(const T* base, uint32_t idx) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + idx * uint32_t(sizeof(T)));
+}
+
 // ---------------------------------------------------------------------------
-// Geometry helpers
+// Geometry
 // ---------------------------------------------------------------------------
 struct Coord {
   int x, y, z;
-};
-
-// Node index of (x - s*ex, y - s*ey, z - s*ez) with periodic wrap, s = +-1.
-struct Neigh {
-  int xs[3];       // x - s*e for e = -1, 0, +1
-  uint32_t row[3][3];   // ((z - s*ez) * ny + (y - s*ey)) * nx for ey, ez = -1, 0, +1
-  __device__ __forceinline__ Neigh(const Geom& g, Coord c, int s) {
-    const int xm = c.x == 0 ? g.nx - 1 : c.x - 1, xp = c.x == g.nx - 1 ? 0 : c.x + 1;
-    const int ym = c.y == 0 ? g.ny - 1 : c.y - 1, yp = c.y == g.ny - 1 ? 0 : c.y + 1;
-    const int zm = c.z == 0 ? g.nz - 1 : c.z - 1, zp = c.z == g.nz - 1 ? 0 : c.z + 1;
-    const int X[3] = {s > 0 ? xp : xm, c.x, s > 0 ? xm : xp};
-    const int Y[3] = {s > 0 ? yp : ym, c.y, s > 0 ? ym : yp};
-    const int Z[3] = {s > 0 ? zp : zm, c.z, s > 0 ? zm : zp};
-#pragma unroll
-    for (int i = 0; i < 3; ++i) xs[i] = X[i];
-#pragma unroll
-    for (int j = 0; j < 3; ++j)
-#pragma unroll
-      for (int k = 0; k < 3; ++k) row[j][k] = (uint32_t(Z[k]) * uint32_t(g.ny) + uint32_t(Y[j])) * uint32_t(g.nx);
-  }
-  __device__ __forceinline__ uint32_t at(Vel e) const { return row[e.y + 1][e.z + 1] + uint32_t(xs[e.x + 1]); }
 };
 
 __device__ __forceinline__ Coord coord_of(const Geom& g, uint32_t n) {
@@ -99,63 +94,60 @@ __device__ __forceinline__ Coord coord_of(const Geom& g, uint32_t n) {
   return {int(r - y * uint32_t(g.nx)), int(y), int(z)};
 }
 
-// Pull the pre-collision populations of node `node` from the post-collision
-// array `fin` (s = +1: from x - e_a).  With MASK, a link whose source is solid
-// is replaced by the node's own reversed population (half-way bounce-back).
+// Offset of (a, x) inside a row of the blocked population layout.
+template <int Q>
+__device__ __forceinline__ uint32_t in_row(uint32_t nx, int a, uint32_t x) {
+  const uint32_t b0 = x & ~63u;
+  const uint32_t len = min(64u, nx - b0);
+  return b0 * uint32_t(Q) + uint32_t(a) * len + (x - b0);
+}
+
+// Source rows and x positions of the pull (s = +1: x - e) or of the reverse
+// gather (s = -1: x + e), periodic.
+struct Stencil {
+  uint32_t row[3][3];   // row index (z - s*ez)*ny + (y - s*ey), indexed [ey+1][ez+1]
+  uint32_t xs[3];       // x - s*ex, indexed [ex+1]
+  __device__ __forceinline__ Stencil(const Geom& g, Coord c, int s) {
+    const int xm = c.x == 0 ? g.nx - 1 : c.x - 1, xp = c.x == g.nx - 1 ? 0 : c.x + 1;
+    const int ym = c.y == 0 ? g.ny - 1 : c.y - 1, yp = c.y == g.ny - 1 ? 0 : c.y + 1;
+    const int zm = c.z == 0 ? g.nz - 1 : c.z - 1, zp = c.z == g.nz - 1 ? 0 : c.z + 1;
+    const int X[3] = {s > 0 ? xp : xm, c.x, s > 0 ? xm : xp};
+    const int Y[3] = {s > 0 ? yp : ym, c.y, s > 0 ? ym : yp};
+    const int Z[3] = {s > 0 ? zp : zm, c.z, s > 0 ? zm : zp};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) xs[i] = uint32_t(X[i]);
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) row[j][k] = uint32_t(Z[k]) * uint32_t(g.ny) + uint32_t(Y[j]);
+  }
+  __device__ __forceinline__ uint32_t node(Vel e, uint32_t nx) const {
+    return row[e.y + 1][e.z + 1] * nx + xs[e.x + 1];
+  }
+};
+
+// Pull the pre-collision populations of node (row0, x) from the blocked
+// post-collision buffer `fin`.  With MASK, a link whose source is solid takes
+// the node's own reversed population (half-way bounce-back).
 template <int Q, class ST, bool MASK>
-__device__ __forceinline__ void pull(const typename ST::T* __restrict__ fin, uint64_t N, const uint8_t* mask,
-                                     const Neigh& nb, uint32_t node, typename ST::R (&f)[Q]) {
+__device__ __forceinline__ void pull(const typename ST::T* __restrict__ fin, const Geom& g, const uint8_t* mask,
+                                     const Stencil& st, uint32_t row0, uint32_t x, typename ST::R (&f)[Q]) {
+  using T = typename ST::T;
+  const uint64_t rowQ = uint64_t(g.nx) * Q;
 #pragma unroll
   for (int a = 0; a < Q; ++a) {
     const Vel e = Lattice<Q>::e(a);
-    const uint32_t src = nb.at(e);
-    typename ST::T v;
+    const T* rp = fin + uint64_t(st.row[e.y + 1][e.z + 1]) * rowQ;
+    T v;
     if constexpr (MASK) {
-      if (mask[src])
-        v = fin[uint64_t(opposite<Q>(a)) * N + node];
+      if (mask[st.node(e, uint32_t(g.nx))])
+        v = ld32(fin + uint64_t(row0) * rowQ, in_row<Q>(uint32_t(g.nx), opposite<Q>(a), x));
       else
-        v = fin[uint64_t(a) * N + src];
+        v = ld32(rp, in_row<Q>(uint32_t(g.nx), a, st.xs[e.x + 1]));
     } else {
-      v = fin[uint64_t(a) * N + src];
+      v = ld32(rp, in_row<Q>(uint32_t(g.nx), a, st.xs[e.x + 1]));
     }
     f[a] = decode<ST, Q>(v, a);
-  }
-}
-
-// Element idx of an array whose byte size fits in 32 bits: a uniform base
-// pointer plus a 32-bit byte offset, which maps onto the scalar-base form of
-// the global load/store instructions.
-template <typename T>
-__device__ __forceinline__ T ld32(const T* base, uint32_t idx) {
-  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + idx * uint32_t(sizeof(T)));
-}
-template <typename T>
-__device__ __forceinline__ T* at32(T* base, uint32_t idx) {
-  return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + idx * uint32_t(sizeof(T)));
-}
-
-// pull() for the step kernel: WIDE selects 64-bit indexing for arrays of 4 GiB
-// and more.
-template <int Q, class ST, bool MASK, bool WIDE>
-__device__ __forceinline__ void pull_step(const typename ST::T* __restrict__ fin, uint64_t N, const uint8_t* mask,
-                                          const Neigh& nb, uint32_t node, typename ST::R (&f)[Q]) {
-  if constexpr (WIDE) {
-    pull<Q, ST, MASK>(fin, N, mask, nb, node, f);
-  } else {
-#pragma unroll
-    for (int a = 0; a < Q; ++a) {
-      const uint32_t src = nb.at(Lattice<Q>::e(a));
-      typename ST::T v;
-      if constexpr (MASK) {
-        if (mask[src])
-          v = ld32(fin + uint64_t(opposite<Q>(a)) * N, node);
-        else
-          v = ld32(fin + uint64_t(a) * N, src);
-      } else {
-        v = ld32(fin + uint64_t(a) * N, src);
-      }
-      f[a] = decode<ST, Q>(v, a);
-    }
   }
 }
 
@@ -189,11 +181,11 @@ __device__ __forceinline__ void collide(R (&f)[Q], R Fx, R Fy, R Fz, const Rates
 // ---------------------------------------------------------------------------
 // The fused pull-stream + collide + force step
 // ---------------------------------------------------------------------------
-// Launch shape of the step kernel: one block covers CMLBM_STEP_BLOCK
-// consecutive x of one row (y, z).  Hardware hands consecutive block ids to
-// the eight XCDs in turn; with CMLBM_XCD_REMAP the block id is permuted so that
-// each XCD receives a contiguous run of rows, keeping the two x-segments of a
-// row and the row's halo cache lines in one XCD's L2.
+// Launch shape: one block covers CMLBM_STEP_BLOCK consecutive x of one row, so
+// every row base is uniform across the block.  Hardware hands consecutive
+// block ids to the eight XCDs in turn; with CMLBM_XCD_REMAP the block id is
+// permuted so that each XCD receives a contiguous run of rows, keeping a row's
+// segments and their shared edge cache lines in one XCD's L2.
 #ifndef CMLBM_STEP_BLOCK
 #define CMLBM_STEP_BLOCK 256
 #endif
@@ -213,19 +205,9 @@ __device__ __forceinline__ uint32_t step_block_id() {
   return L;
 }
 
-template <typename T>
-__device__ __forceinline__ void store_stream(T* p, T v) {
-#if CMLBM_NT_STORE
-  __builtin_nontemporal_store(v, p);
-#else
-  *p = v;
-#endif
-}
-
-// Raw buffer store: per-array resource (base in SGPRs, size bound) plus a
-// 32-bit byte offset shared by all directions.  Stores past the bound are
-// dropped by the hardware.  Word 3 = 0x00020000 is the raw-buffer descriptor
-// of the gfx9 family.
+// Raw buffer store: a resource over one row (base in SGPRs, size bound) plus a
+// 32-bit byte offset.  Stores past the bound are dropped by the hardware.
+// Word 3 = 0x00020000 is the raw-buffer descriptor of the gfx9 family.
 constexpr int kStoreAux = CMLBM_NT_STORE ? 2 : 0;   // 2: nontemporal (streaming) store
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t array_rsrc(void* base, uint32_t bytes) {
@@ -244,71 +226,88 @@ __device__ __forceinline__ void buf_store(T v, __amdgpu_buffer_rsrc_t r, uint32_
   }
 }
 
-template <int Q, class ST, bool MASK, bool WIDE>
+template <int Q, class ST, bool MASK>
 __global__ __launch_bounds__(CMLBM_STEP_BLOCK) void k_step(StepArgs<typename ST::R> args) {
   using R = typename ST::R;
   using T = typename ST::T;
   const Geom g = args.g;
   const uint32_t nseg = (uint32_t(g.nx) + blockDim.x - 1) / blockDim.x;
   const uint32_t L = step_block_id();
-  const uint32_t row = L / nseg;                  // row = z * ny + y
-  const int x = int((L - row * nseg) * blockDim.x + threadIdx.x);
-  if (x >= g.nx) return;
-  const Coord c{x, int(row % uint32_t(g.ny)), int(row / uint32_t(g.ny))};
-  const uint32_t node = row * uint32_t(g.nx) + uint32_t(x);
+  const uint32_t row = L / nseg;                  // row = z * ny + y, uniform over the block
+  const uint32_t x = (L - row * nseg) * blockDim.x + threadIdx.x;
+  if (x >= uint32_t(g.nx)) return;
+  const Coord c{int(x), int(row % uint32_t(g.ny)), int(row / uint32_t(g.ny))};
+  const uint32_t node = row * uint32_t(g.nx) + x;
   if constexpr (MASK) {
     if (args.mask[node]) return;
   }
-  const Neigh nb(g, c, +1);
+  const Stencil st(g, c, +1);
   R f[Q];
-  pull_step<Q, ST, MASK, WIDE>(static_cast<const T*>(args.fin), g.N, args.mask, nb, node, f);
+  pull<Q, ST, MASK>(static_cast<const T*>(args.fin), g, args.mask, st, row, x, f);
   R Fx, Fy, Fz;
   if (args.force.field) {
-    const R* Ff = args.force.field;
+    const R* Ff = args.force.field + uint64_t(row) * uint32_t(g.nx);
     const R sc = R(args.force.scale);
-    if constexpr (WIDE) {
-      Fx = sc * Ff[node];
-      Fy = sc * Ff[g.N + node];
-      Fz = sc * Ff[2 * g.N + node];
-    } else {
-      Fx = sc * ld32(Ff, node);
-      Fy = sc * ld32(Ff + g.N, node);
-      Fz = sc * ld32(Ff + 2 * g.N, node);
-    }
+    Fx = sc * ld32(Ff, x);
+    Fy = sc * ld32(Ff + g.N, x);
+    Fz = sc * ld32(Ff + 2 * g.N, x);
   } else {
     Fx = R(args.force.uni[0]);
     Fy = R(args.force.uni[1]);
     Fz = R(args.force.uni[2]);
   }
   collide<Q>(f, Fx, Fy, Fz, args.rates);
-  T* __restrict__ fout = static_cast<T*>(args.fout);
-  if constexpr (WIDE) {
+  const uint32_t rowQ = uint32_t(g.nx) * uint32_t(Q);
+  const __amdgpu_buffer_rsrc_t rs =
+      array_rsrc(static_cast<T*>(args.fout) + uint64_t(row) * rowQ, rowQ * uint32_t(sizeof(T)));
 #pragma unroll
-    for (int a = 0; a < Q; ++a) store_stream(&fout[uint64_t(a) * g.N + node], encode<ST, Q>(f[a], a));
-  } else {
-    const uint32_t bytes = uint32_t(g.N * sizeof(T)), off = node * uint32_t(sizeof(T));
-#pragma unroll
-    for (int a = 0; a < Q; ++a) buf_store(encode<ST, Q>(f[a], a), array_rsrc(fout + uint64_t(a) * g.N, bytes), off);
-  }
+  for (int a = 0; a < Q; ++a)
+    buf_store(encode<ST, Q>(f[a], a), rs, in_row<Q>(uint32_t(g.nx), a, x) * uint32_t(sizeof(T)));
 }
 
-// Observable pre-collision state fbar(x) (full populations, compute type).
+// ---------------------------------------------------------------------------
+// Read-out kernels (grid-stride over nodes)
+// ---------------------------------------------------------------------------
+// Observable pre-collision state fbar(x): full populations, compute type,
+// structure of arrays [Q][N].
 template <int Q, class ST, bool MASK>
 __global__ __launch_bounds__(256) void k_gather(AuxArgs<typename ST::R> args) {
   using R = typename ST::R;
   const Geom g = args.g;
+  R* out = static_cast<R*>(args.out0);
   for (uint32_t n = blockIdx.x * blockDim.x + threadIdx.x; n < g.N; n += gridDim.x * blockDim.x) {
-    R* out = static_cast<R*>(args.out0);
     if (MASK && args.mask[n]) {
 #pragma unroll
       for (int a = 0; a < Q; ++a) out[uint64_t(a) * g.N + n] = R(0);
       continue;
     }
-    const Neigh nb(g, coord_of(g, n), +1);
+    const Coord c = coord_of(g, n);
+    const Stencil st(g, c, +1);
     R f[Q];
-    pull<Q, ST, MASK>(static_cast<const typename ST::T*>(args.in0), g.N, args.mask, nb, n, f);
+    pull<Q, ST, MASK>(static_cast<const typename ST::T*>(args.in0), g, args.mask, st,
+                      n / uint32_t(g.nx), uint32_t(c.x), f);
 #pragma unroll
     for (int a = 0; a < Q; ++a) out[uint64_t(a) * g.N + n] = f[a];
+  }
+}
+
+// Population buffer (blocked layout, storage type) <-> full populations in
+// compute type, structure of arrays [Q][N].  EXPORT: buffer -> SoA.
+template <int Q, class ST, bool EXPORT>
+__global__ __launch_bounds__(256) void k_convert(Geom g, const void* in, void* out) {
+  using R = typename ST::R;
+  using T = typename ST::T;
+  const uint64_t rowQ = uint64_t(g.nx) * Q;
+  for (uint32_t n = blockIdx.x * blockDim.x + threadIdx.x; n < g.N; n += gridDim.x * blockDim.x) {
+    const uint32_t row = n / uint32_t(g.nx), x = n - row * uint32_t(g.nx);
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      const uint64_t blk = uint64_t(row) * rowQ + in_row<Q>(uint32_t(g.nx), a, x);
+      if constexpr (EXPORT)
+        static_cast<R*>(out)[uint64_t(a) * g.N + n] = decode<ST, Q>(static_cast<const T*>(in)[blk], a);
+      else
+        static_cast<T*>(out)[blk] = encode<ST, Q>(static_cast<const R*>(in)[uint64_t(a) * g.N + n], a);
+    }
   }
 }
 
@@ -325,9 +324,11 @@ __global__ __launch_bounds__(256) void k_macro(AuxArgs<typename ST::R> args) {
       u_out[n] = u_out[g.N + n] = u_out[2 * g.N + n] = R(0);
       continue;
     }
-    const Neigh nb(g, coord_of(g, n), +1);
+    const Coord c = coord_of(g, n);
+    const Stencil st(g, c, +1);
     R f[Q];
-    pull<Q, ST, MASK>(static_cast<const typename ST::T*>(args.in0), g.N, args.mask, nb, n, f);
+    pull<Q, ST, MASK>(static_cast<const typename ST::T*>(args.in0), g, args.mask, st, n / uint32_t(g.nx),
+                      uint32_t(c.x), f);
     R Fx, Fy, Fz;
     force_at(args.force, g.N, n, Fx, Fy, Fz);
     R rho = R(0), jx = R(0), jy = R(0), jz = R(0);
@@ -379,9 +380,11 @@ __global__ __launch_bounds__(256) void k_totals(AuxArgs<typename ST::R> args, do
   double acc[4] = {0, 0, 0, 0};
   for (uint32_t n = blockIdx.x * blockDim.x + threadIdx.x; n < g.N; n += gridDim.x * blockDim.x) {
     if (MASK && args.mask[n]) continue;
-    const Neigh nb(g, coord_of(g, n), +1);
+    const Coord c = coord_of(g, n);
+    const Stencil st(g, c, +1);
     R f[Q];
-    pull<Q, ST, MASK>(static_cast<const typename ST::T*>(args.in0), g.N, args.mask, nb, n, f);
+    pull<Q, ST, MASK>(static_cast<const typename ST::T*>(args.in0), g, args.mask, st, n / uint32_t(g.nx),
+                      uint32_t(c.x), f);
     R Fx, Fy, Fz;
     force_at(args.force, g.N, n, Fx, Fy, Fz);
 #pragma unroll
@@ -419,7 +422,7 @@ __global__ __launch_bounds__(256) void k_reduce_rows(const double* partials, int
 
 // ---------------------------------------------------------------------------
 // Initial condition: fbar(x, 0) = f^eq(rho0, u0) - S/2, then the inverse pull
-// into the post-collision array so that the first step's pull reproduces it.
+// into the post-collision buffer so that the first step's pull reproduces it.
 // ---------------------------------------------------------------------------
 template <int Q, typename R, typename FT>
 __global__ __launch_bounds__(256) void k_initial_pre(Geom g, const R* rho0, const R* u0, ForceArgs<FT> force,
@@ -461,27 +464,31 @@ __global__ __launch_bounds__(256) void k_initial_pre(Geom g, const R* rho0, cons
   }
 }
 
-// fbar~(y)_a = fbar(y + e_a)_a if y + e_a is fluid, else fbar(y)_abar.
+// fbar~(y)_a = fbar(y + e_a)_a if y + e_a is fluid, else fbar(y)_abar; fpre is
+// structure of arrays, fpost the blocked population buffer.
 template <int Q, class ST, bool MASK>
 __global__ __launch_bounds__(256) void k_scatter_post(Geom g, const typename ST::R* fpre, const uint8_t* mask,
                                                       typename ST::T* fpost) {
   using R = typename ST::R;
+  const uint64_t rowQ = uint64_t(g.nx) * Q;
   for (uint32_t n = blockIdx.x * blockDim.x + threadIdx.x; n < g.N; n += gridDim.x * blockDim.x) {
+    const Coord c = coord_of(g, n);
+    const uint64_t base = uint64_t(n / uint32_t(g.nx)) * rowQ;
     if (MASK && mask[n]) {
 #pragma unroll
-      for (int a = 0; a < Q; ++a) fpost[uint64_t(a) * g.N + n] = typename ST::T(0);
+      for (int a = 0; a < Q; ++a) fpost[base + in_row<Q>(uint32_t(g.nx), a, uint32_t(c.x))] = typename ST::T(0);
       continue;
     }
-    const Neigh nb(g, coord_of(g, n), -1);    // x + e_a
+    const Stencil st(g, c, -1);    // x + e_a
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
-      const uint32_t dst = nb.at(Lattice<Q>::e(a));
+      const uint32_t dst = st.node(Lattice<Q>::e(a), uint32_t(g.nx));
       R v;
       if (MASK && mask[dst])
         v = fpre[uint64_t(opposite<Q>(a)) * g.N + n];
       else
         v = fpre[uint64_t(a) * g.N + dst];
-      fpost[uint64_t(a) * g.N + n] = encode<ST, Q>(v, a);
+      fpost[base + in_row<Q>(uint32_t(g.nx), a, uint32_t(c.x))] = encode<ST, Q>(v, a);
     }
   }
 }
@@ -490,9 +497,10 @@ __global__ __launch_bounds__(256) void k_scatter_post(Geom g, const typename ST:
 // Adjoint step (D3Q27).  Forward step n maps the pre-collision state
 // fbar^n(x) (pulled from f_post_prev) to fbar~(x) = C(fbar^n(x)), and
 // fbar^{n+1}(x)_a = fbar~(x - e_a)_a (or bounce-back).  Given
-// lam_next = dL/dfbar^{n+1}, the adjoint of the stored fbar~(x)_a is
-// mu_a = lam_next(x + e_a)_a, or lam_next(x)_abar when x + e_a is solid, and
-// lam(x) = J_C(fbar^n(x))^T mu.  dL/dF(x) and dL/domega accumulate in FP64.
+// lam_next = dL/dfbar^{n+1} (structure of arrays), the adjoint of the stored
+// fbar~(x)_a is mu_a = lam_next(x + e_a)_a, or lam_next(x)_abar when x + e_a is
+// solid, and lam(x) = J_C(fbar^n(x))^T mu.  dL/dF(x) and dL/domega accumulate
+// in FP64.
 // ---------------------------------------------------------------------------
 template <class ST, bool MASK>
 __global__ __launch_bounds__(256) void k_adjoint27(AdjArgs<typename ST::R> args, double* partials) {
@@ -509,28 +517,28 @@ __global__ __launch_bounds__(256) void k_adjoint27(AdjArgs<typename ST::R> args,
   const uint32_t items = nseg * uint32_t(g.ny) * uint32_t(g.nz);
   for (uint32_t it = blockIdx.x; it < items; it += gridDim.x) {
     const uint32_t row = it / nseg;
-    const int x = int((it - row * nseg) * blockDim.x + threadIdx.x);
-    if (x >= g.nx) continue;
-    const Coord c{x, int(row % uint32_t(g.ny)), int(row / uint32_t(g.ny))};
-    const uint32_t node = row * uint32_t(g.nx) + uint32_t(x);
+    const uint32_t x = (it - row * nseg) * blockDim.x + threadIdx.x;
+    if (x >= uint32_t(g.nx)) continue;
+    const Coord c{int(x), int(row % uint32_t(g.ny)), int(row / uint32_t(g.ny))};
+    const uint32_t node = row * uint32_t(g.nx) + x;
     if (MASK && args.mask[node]) continue;
     // forward pre-collision populations
     R f[27];
     {
-      const Neigh nb(g, c, +1);
+      const Stencil st(g, c, +1);
       R fa[27];
-      pull<27, ST, MASK>(static_cast<const T*>(args.fpost), g.N, args.mask, nb, node, fa);
+      pull<27, ST, MASK>(static_cast<const T*>(args.fpost), g, args.mask, st, row, x, fa);
 #pragma unroll
       for (int a = 0; a < 27; ++a) f[cube27(a)] = fa[a];
     }
     // adjoint of this node's post-collision populations (reverse streaming)
     R gm[27];
     {
-      const Neigh nb(g, c, -1);
+      const Stencil st(g, c, -1);
       const R* lam = args.lam_next;
 #pragma unroll
       for (int a = 0; a < 27; ++a) {
-        const uint32_t dst = nb.at(kE27[a]);
+        const uint32_t dst = st.node(kE27[a], uint32_t(g.nx));
         R v;
         if (MASK && args.mask[dst])
           v = lam[uint64_t(opposite<27>(a)) * g.N + node];
@@ -699,9 +707,6 @@ __global__ __launch_bounds__(256) void k_init_adjoint27(Geom g, const R* u0, con
 // ---------------------------------------------------------------------------
 namespace {
 
-template <class ST>
-struct StorageFor;
-
 constexpr int kBlock = 256;
 
 inline int step_block(const Geom& g) {
@@ -721,24 +726,13 @@ inline unsigned aux_grid(const Geom& g) {
   return unsigned(need < 8192 ? (need == 0 ? 1 : need) : 8192);
 }
 
-// Arrays of 4 GiB or more need 64-bit element offsets.
-inline bool wide(const Geom& g, size_t elem) { return g.N * elem >= (uint64_t(1) << 32); }
-
 template <int Q, class ST>
 hipError_t step_impl(const StepArgs<typename ST::R>& a, hipStream_t st) {
   const int bx = step_block(a.g);
-  const bool w = wide(a.g, sizeof(typename ST::R));
-  if (a.mask) {
-    if (w)
-      hipLaunchKernelGGL((k_step<Q, ST, true, true>), step_grid(a.g, bx), dim3(bx), 0, st, a);
-    else
-      hipLaunchKernelGGL((k_step<Q, ST, true, false>), step_grid(a.g, bx), dim3(bx), 0, st, a);
-  } else {
-    if (w)
-      hipLaunchKernelGGL((k_step<Q, ST, false, true>), step_grid(a.g, bx), dim3(bx), 0, st, a);
-    else
-      hipLaunchKernelGGL((k_step<Q, ST, false, false>), step_grid(a.g, bx), dim3(bx), 0, st, a);
-  }
+  if (a.mask)
+    hipLaunchKernelGGL((k_step<Q, ST, true>), step_grid(a.g, bx), dim3(bx), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_step<Q, ST, false>), step_grid(a.g, bx), dim3(bx), 0, st, a);
   return hipGetLastError();
 }
 
@@ -748,6 +742,15 @@ hipError_t gather_impl(const AuxArgs<typename ST::R>& a, hipStream_t st) {
     hipLaunchKernelGGL((k_gather<Q, ST, true>), dim3(aux_grid(a.g)), dim3(kBlock), 0, st, a);
   else
     hipLaunchKernelGGL((k_gather<Q, ST, false>), dim3(aux_grid(a.g)), dim3(kBlock), 0, st, a);
+  return hipGetLastError();
+}
+
+template <int Q, class ST>
+hipError_t convert_impl(const Geom& g, const void* in, void* out, bool to_soa, hipStream_t st) {
+  if (to_soa)
+    hipLaunchKernelGGL((k_convert<Q, ST, true>), dim3(aux_grid(g)), dim3(kBlock), 0, st, g, in, out);
+  else
+    hipLaunchKernelGGL((k_convert<Q, ST, false>), dim3(aux_grid(g)), dim3(kBlock), 0, st, g, in, out);
   return hipGetLastError();
 }
 
@@ -802,50 +805,63 @@ hipError_t adjoint_impl(const AdjArgs<typename ST::R>& a, double* partials, int 
 }  // namespace
 
 // Dispatch on (Q, precision).
-#define CMLBM_DISPATCH(Q, PREC, CALL_F64, CALL_F32, CALL_F16, CALL_BF16) \
-  switch (PREC) {                                                        \
-    case 0: return CALL_F64;                                             \
-    case 1: return CALL_F32;                                             \
-    case 2: return CALL_F16;                                             \
-    default: return CALL_BF16;                                           \
+#define CMLBM_DISPATCH(PREC, CALL_F64, CALL_F32, CALL_F16, CALL_BF16) \
+  switch (PREC) {                                                     \
+    case 0: return CALL_F64;                                          \
+    case 1: return CALL_F32;                                          \
+    case 2: return CALL_F16;                                          \
+    default: return CALL_BF16;                                        \
   }
 
 hipError_t launch_step(int q, int prec, const StepArgs<double>& a64, const StepArgs<float>& a32, hipStream_t st) {
   if (q == 27) {
-    CMLBM_DISPATCH(q, prec, (step_impl<27, StF64>(a64, st)), (step_impl<27, StF32>(a32, st)),
+    CMLBM_DISPATCH(prec, (step_impl<27, StF64>(a64, st)), (step_impl<27, StF32>(a32, st)),
                    (step_impl<27, StF16>(a32, st)), (step_impl<27, StBF16>(a32, st)))
   }
-  CMLBM_DISPATCH(q, prec, (step_impl<15, StF64>(a64, st)), (step_impl<15, StF32>(a32, st)),
+  CMLBM_DISPATCH(prec, (step_impl<15, StF64>(a64, st)), (step_impl<15, StF32>(a32, st)),
                  (step_impl<15, StF16>(a32, st)), (step_impl<15, StBF16>(a32, st)))
 }
 
 hipError_t launch_gather(int q, int prec, const AuxArgs<double>& a64, const AuxArgs<float>& a32, hipStream_t st) {
   if (q == 27) {
-    CMLBM_DISPATCH(q, prec, (gather_impl<27, StF64>(a64, st)), (gather_impl<27, StF32>(a32, st)),
+    CMLBM_DISPATCH(prec, (gather_impl<27, StF64>(a64, st)), (gather_impl<27, StF32>(a32, st)),
                    (gather_impl<27, StF16>(a32, st)), (gather_impl<27, StBF16>(a32, st)))
   }
-  CMLBM_DISPATCH(q, prec, (gather_impl<15, StF64>(a64, st)), (gather_impl<15, StF32>(a32, st)),
+  CMLBM_DISPATCH(prec, (gather_impl<15, StF64>(a64, st)), (gather_impl<15, StF32>(a32, st)),
                  (gather_impl<15, StF16>(a32, st)), (gather_impl<15, StBF16>(a32, st)))
+}
+
+hipError_t launch_convert(int q, int prec, const Geom& g, const void* in, void* out, bool to_soa, hipStream_t st) {
+  if (q == 27) {
+    CMLBM_DISPATCH(prec, (convert_impl<27, StF64>(g, in, out, to_soa, st)),
+                   (convert_impl<27, StF32>(g, in, out, to_soa, st)),
+                   (convert_impl<27, StF16>(g, in, out, to_soa, st)),
+                   (convert_impl<27, StBF16>(g, in, out, to_soa, st)))
+  }
+  CMLBM_DISPATCH(prec, (convert_impl<15, StF64>(g, in, out, to_soa, st)),
+                 (convert_impl<15, StF32>(g, in, out, to_soa, st)),
+                 (convert_impl<15, StF16>(g, in, out, to_soa, st)),
+                 (convert_impl<15, StBF16>(g, in, out, to_soa, st)))
 }
 
 hipError_t launch_macro(int q, int prec, const AuxArgs<double>& a64, const AuxArgs<float>& a32, hipStream_t st) {
   if (q == 27) {
-    CMLBM_DISPATCH(q, prec, (macro_impl<27, StF64>(a64, st)), (macro_impl<27, StF32>(a32, st)),
+    CMLBM_DISPATCH(prec, (macro_impl<27, StF64>(a64, st)), (macro_impl<27, StF32>(a32, st)),
                    (macro_impl<27, StF16>(a32, st)), (macro_impl<27, StBF16>(a32, st)))
   }
-  CMLBM_DISPATCH(q, prec, (macro_impl<15, StF64>(a64, st)), (macro_impl<15, StF32>(a32, st)),
+  CMLBM_DISPATCH(prec, (macro_impl<15, StF64>(a64, st)), (macro_impl<15, StF32>(a32, st)),
                  (macro_impl<15, StF16>(a32, st)), (macro_impl<15, StBF16>(a32, st)))
 }
 
 hipError_t launch_totals(int q, int prec, const AuxArgs<double>& a64, const AuxArgs<float>& a32, double* partials,
                          int nblk, double* out4, hipStream_t st) {
   if (q == 27) {
-    CMLBM_DISPATCH(q, prec, (totals_impl<27, StF64>(a64, partials, nblk, out4, st)),
+    CMLBM_DISPATCH(prec, (totals_impl<27, StF64>(a64, partials, nblk, out4, st)),
                    (totals_impl<27, StF32>(a32, partials, nblk, out4, st)),
                    (totals_impl<27, StF16>(a32, partials, nblk, out4, st)),
                    (totals_impl<27, StBF16>(a32, partials, nblk, out4, st)))
   }
-  CMLBM_DISPATCH(q, prec, (totals_impl<15, StF64>(a64, partials, nblk, out4, st)),
+  CMLBM_DISPATCH(prec, (totals_impl<15, StF64>(a64, partials, nblk, out4, st)),
                  (totals_impl<15, StF32>(a32, partials, nblk, out4, st)),
                  (totals_impl<15, StF16>(a32, partials, nblk, out4, st)),
                  (totals_impl<15, StBF16>(a32, partials, nblk, out4, st)))
@@ -854,12 +870,12 @@ hipError_t launch_totals(int q, int prec, const AuxArgs<double>& a64, const AuxA
 hipError_t launch_init(int q, int prec, const Geom& g, const void* rho0, const void* u0, const ForceArgs<double>& f64,
                        const ForceArgs<float>& f32, const uint8_t* mask, void* fpre, void* fpost, hipStream_t st) {
   if (q == 27) {
-    CMLBM_DISPATCH(q, prec, (init_impl<27, StF64>(g, rho0, u0, f64, mask, fpre, fpost, st)),
+    CMLBM_DISPATCH(prec, (init_impl<27, StF64>(g, rho0, u0, f64, mask, fpre, fpost, st)),
                    (init_impl<27, StF32>(g, rho0, u0, f32, mask, fpre, fpost, st)),
                    (init_impl<27, StF16>(g, rho0, u0, f32, mask, fpre, fpost, st)),
                    (init_impl<27, StBF16>(g, rho0, u0, f32, mask, fpre, fpost, st)))
   }
-  CMLBM_DISPATCH(q, prec, (init_impl<15, StF64>(g, rho0, u0, f64, mask, fpre, fpost, st)),
+  CMLBM_DISPATCH(prec, (init_impl<15, StF64>(g, rho0, u0, f64, mask, fpre, fpost, st)),
                  (init_impl<15, StF32>(g, rho0, u0, f32, mask, fpre, fpost, st)),
                  (init_impl<15, StF16>(g, rho0, u0, f32, mask, fpre, fpost, st)),
                  (init_impl<15, StBF16>(g, rho0, u0, f32, mask, fpre, fpost, st)))
@@ -867,7 +883,7 @@ hipError_t launch_init(int q, int prec, const Geom& g, const void* rho0, const v
 
 hipError_t launch_adjoint(int prec, const AdjArgs<double>& a64, const AdjArgs<float>& a32, double* partials,
                           int nblk, double* dLdomega, double* dLdF_uniform, hipStream_t st) {
-  CMLBM_DISPATCH(27, prec, (adjoint_impl<StF64>(a64, partials, nblk, dLdomega, dLdF_uniform, st)),
+  CMLBM_DISPATCH(prec, (adjoint_impl<StF64>(a64, partials, nblk, dLdomega, dLdF_uniform, st)),
                  (adjoint_impl<StF32>(a32, partials, nblk, dLdomega, dLdF_uniform, st)),
                  (adjoint_impl<StF16>(a32, partials, nblk, dLdomega, dLdF_uniform, st)),
                  (adjoint_impl<StBF16>(a32, partials, nblk, dLdomega, dLdF_uniform, st)))

@@ -59,6 +59,9 @@ struct AdjArgs {
 // prec: 0 FP64, 1 FP32, 2 FP32 compute / FP16 deviation storage, 3 BF16 deviations.
 hipError_t launch_step(int q, int prec, const StepArgs<double>& a64, const StepArgs<float>& a32, hipStream_t st);
 hipError_t launch_gather(int q, int prec, const AuxArgs<double>& a64, const AuxArgs<float>& a32, hipStream_t st);
+// Population buffer (blocked layout) <-> full populations in compute type,
+// structure of arrays [Q][N]; to_soa selects the direction.
+hipError_t launch_convert(int q, int prec, const Geom& g, const void* in, void* out, bool to_soa, hipStream_t st);
 hipError_t launch_macro(int q, int prec, const AuxArgs<double>& a64, const AuxArgs<float>& a32, hipStream_t st);
 hipError_t launch_totals(int q, int prec, const AuxArgs<double>& a64, const AuxArgs<float>& a32, double* partials,
                          int nblk, double* out4, hipStream_t st);

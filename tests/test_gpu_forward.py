@@ -219,7 +219,8 @@ def test_full_size_sampled_nodes(q):
     idx[:4] = [0, n - 1, n * n - 1, n**3 - 1]          # corners of the periodic box
     idx_t = torch.from_numpy(idx).to("cuda")
     f_in = pre.reshape(q, -1)[:, idx_t].double().cpu().numpy().T
-    f_gpu = out.reshape(q, -1)[:, idx_t].double().cpu().numpy().T
+    post = sim.export_populations(out, out=f_pre)          # pre no longer needed past this point
+    f_gpu = post.reshape(q, -1)[:, idx_t].double().cpu().numpy().T
     Fs = F.reshape(3, -1)[:, idx_t].double().cpu().numpy().T
     want = collision.collide(LATTICES[q], f_in, Fs, shear_rates(q, 1.9))
     assert np.abs(f_gpu - want).max() < 2e-6
@@ -244,3 +245,30 @@ def test_duct_128_transient_closed_form():
     err = np.linalg.norm(ux - ua) / np.linalg.norm(ua)
     print(f"duct128 relative L2 {err:.3e}  center {ux[62, 62]:.6e} vs {ua[62, 62]:.6e}", flush=True)
     assert err < 1e-2
+
+
+@pytest.mark.parametrize("prec", [F64, F32, F16, BF16])
+@pytest.mark.parametrize("q,nx", [(27, 130), (15, 64), (27, 5)])
+def test_population_buffer_layout(prec, q, nx):
+    # The documented blocked layout: index(a, r, x) = r*nx*q + b*64*q + a*len + (x - 64 b),
+    # b = x // 64, len = min(64, nx - 64 b); export/import round trip.
+    print(f"case layout q{q} nx{nx} p{prec}", flush=True)
+    cm = lib()
+    ny, nz = 3, 2
+    sim = cm.Sim(q, nx, ny, nz, prec)
+    rng = np.random.default_rng(1)
+    lat = LATTICES[q]
+    w = collision.equilibrium(lat, np.array(1.0), np.zeros(3))
+    soa = w[:, None, None, None] + 0.01 * rng.standard_normal((q, nz, ny, nx))
+    buf = sim.import_populations(torch.from_numpy(soa))
+    raw = buf.reshape(-1).double().cpu().numpy()
+    for a, z, y, x in [(0, 0, 0, 0), (q - 1, 1, 2, nx - 1), (q // 2, 1, 0, min(70, nx - 1)), (3, 0, 1, nx // 2)]:
+        r = z * ny + y
+        b = x // 64
+        ln = min(64, nx - 64 * b)
+        idx = r * nx * q + b * 64 * q + a * ln + (x - 64 * b)
+        stored = raw[idx] + (w[a] if prec in (F16, BF16) else 0.0)
+        assert abs(stored - soa[a, z, y, x]) <= (1e-15 if prec == F64 else 2e-7 if prec == F32 else 1e-4)
+    back = sim.export_populations(buf).double().cpu().numpy()
+    tol = {F64: 0.0, F32: 1e-7, F16: 1e-5, BF16: 1e-4}[prec]
+    assert np.abs(back - soa).max() <= tol
