@@ -282,20 +282,28 @@ def binomial_snapshots_for_budget(state_bytes, budget_bytes, fixed_bytes):
     return max(0, int((budget_bytes - fixed_bytes) // state_bytes))
 
 
-def benchmark_adjoint_ratio(sim, nsteps, forward_ms_per_step, budget_gib=200.0):
+def benchmark_adjoint_ratio(sim, nsteps, forward_ms_per_step, budget_gib=None):
     """Time a checkpointed D3Q27 adjoint of `nsteps` steps on sim's lattice
     under a device memory budget and return the adjoint/forward time ratio.
 
-    Loss: mean kinetic energy of fbar(N).  Fixed memory: two forward work
-    buffers, two adjoint buffers, the pre-collision output, the force field,
-    the FP64 force gradient; the rest of the budget holds snapshots."""
+    Loss: mean kinetic energy of fbar(N).  Fixed memory: x(0) and two work
+    buffers (storage precision); the pre-collision output, the incoming
+    gradient, the two adjoint buffers (arithmetic precision); the force field,
+    its FP64 accumulator and FP32 gradient, u0 and rho0.  What is already
+    allocated on the device counts against the budget too; the rest holds
+    snapshots.  The default budget is 80% of the device memory.  The returned
+    peak is torch's own allocator high-water mark over the run."""
     dev = sim.device
     n = sim.nx * sim.ny * sim.nz
     state = n * 27 * torch.tensor([], dtype=sim.store).element_size()
     real_state = n * 27 * torch.tensor([], dtype=sim.real).element_size()
-    fixed = 2 * state + 3 * real_state + 3 * n * (8 + torch.tensor([], dtype=sim.real).element_size())
+    fixed = 3 * state + 4 * real_state + n * (3 * (8 + 4 * 4) + 4)
+    if budget_gib is None:
+        budget_gib = 0.8 * torch.cuda.get_device_properties(dev).total_memory / 2**30
     budget = budget_gib * 2**30
-    snaps = binomial_snapshots_for_budget(state, budget, fixed)
+    torch.cuda.reset_peak_memory_stats(dev)
+    base = torch.cuda.memory_allocated(dev)
+    snaps = binomial_snapshots_for_budget(state, budget - base, fixed)
     snaps = max(1, min(snaps, nsteps - 1))
     import lbm_inputs as inp   # Kolmogorov field of the benchmark workload
     F = torch.from_numpy(inp.kolmogorov_force(sim.nx, amplitude=1e-6, waves=4, nz=sim.nz, ny=sim.ny,
@@ -318,6 +326,7 @@ def benchmark_adjoint_ratio(sim, nsteps, forward_ms_per_step, budget_gib=200.0):
     bwd_ms = (t2 - t1) * 1e3
     dLdw_shear = float(st["dLdomega_fp64"][:5].sum())
     recomputed, adj_steps = st["recomputed"], st["adjoint_steps"]
+    loss_value = float(loss)
     del out, loss, st
     _last_stats.clear()
     # average duration of the adjoint step kernel alone (events on the launch stream)
@@ -340,7 +349,7 @@ def benchmark_adjoint_ratio(sim, nsteps, forward_ms_per_step, budget_gib=200.0):
     adj_ms = e0.elapsed_time(e1) / k
     del x, lam_a, lam_b, dLdF
     return {
-        "steps": nsteps, "snapshots": snaps, "budget_gib": budget_gib,
+        "steps": nsteps, "snapshots": snaps, "budget_gib": round(budget_gib, 1),
         "peak_alloc_gib": round(peak / 2**30, 1),
         "recomputed_steps": recomputed, "adjoint_steps": adj_steps,
         "forward_pass_ms": round(fwd_ms, 1), "backward_ms": round(bwd_ms, 1),
@@ -349,5 +358,5 @@ def benchmark_adjoint_ratio(sim, nsteps, forward_ms_per_step, budget_gib=200.0):
         "adjoint_step_bytes_per_node": 27 * 4 * 3 + 12 + 48,
         "adjoint_step_GBs": round((27 * 4 * 3 + 12 + 48) * n / (adj_ms * 1e-3) / 1e9, 1),
         "dLdomega_shear": dLdw_shear,
-        "loss": float(loss),
+        "loss": loss_value,
     }
