@@ -16,8 +16,9 @@
  *             fields, mask, gradients).  The library borrows a pointer for the
  *             duration of a call, except the force field and the mask, which
  *             are borrowed until replaced or until cmlbm_destroy.  The library
- *             owns only the opaque handle and a few kilobytes of device scratch
- *             for reductions.  Device pointers must be 256-byte aligned.
+ *             owns only the opaque handle and device scratch for reductions
+ *             (about nx*ny*nz/8 bytes plus 64 KiB, allocated by cmlbm_create).
+ *             Device pointers must be 256-byte aligned.
  * Streams:    `stream` is a hipStream_t (NULL = the default stream).  Work is
  *             enqueued asynchronously; only cmlbm_totals synchronizes.
  * Threads:    a handle must not be used by two host threads at once.
@@ -92,6 +93,17 @@ void cmlbm_destroy(cmlbm_sim *sim);
  * copied.  Errors: EINVAL (n, NULL, a rate outside (0, 2)). */
 cmlbm_status cmlbm_set_rates(cmlbm_sim *sim, const double *omega, int n);
 
+/* Form of the factorized attractors of the fourth- and sixth-order central
+ * moments (Sec. 3, the list after Eq. centralmomentfdefinitionpostcollision;
+ * Eq. transformedcentralmomentattractors).  per_mass = 0 (the default): the
+ * literal products of the post-collision second moments, kxx~ kyy~ and
+ * kxx~ kyy~ kzz~, as printed.  per_mass = 1: the same factorization per unit
+ * mass, rho (kxx~/rho)(kyy~/rho) and rho (kxx~/rho)(kyy~/rho)(kzz~/rho), for
+ * which the equilibrium is a fixed point at every density.  The two agree at
+ * rho = 1.  Applies to the step and to the adjoint.  Errors: EINVAL unless
+ * per_mass is 0 or 1. */
+cmlbm_status cmlbm_set_attractor_per_mass(cmlbm_sim *sim, int per_mass);
+
 /* Uniform body force F (force per unit volume, Sec. 3 Eq. forcingaliased).
  * Replaces any force field. */
 cmlbm_status cmlbm_set_force_uniform(cmlbm_sim *sim, double fx, double fy, double fz);
@@ -127,6 +139,16 @@ cmlbm_status cmlbm_init_equilibrium(cmlbm_sim *sim, const void *rho_dev, const v
  * post-collision populations of step t into f_out.  f_in != f_out. */
 cmlbm_status cmlbm_step(cmlbm_sim *sim, const void *f_in, void *f_out, void *stream);
 
+/* One step exactly as cmlbm_step, which also reduces the FP64 totals of the
+ * state it steps from (the pre-collision fbar(x, t) it pulls) inside the same
+ * pass: totals_dev[0..3] = (sum rho, sum rho u_x, sum rho u_y, sum rho u_z)
+ * over fluid nodes, rho u including F/2 (Eqs. densitycalculation,
+ * velocitycalculation); the same quantities as cmlbm_totals(f_in), without a
+ * second read of the populations.  totals_dev: 4 doubles of device memory,
+ * overwritten, written asynchronously on `stream` (no host synchronization).
+ * Errors: as cmlbm_step; EINVAL if totals_dev is NULL. */
+cmlbm_status cmlbm_step_totals(cmlbm_sim *sim, const void *f_in, void *f_out, double *totals_dev, void *stream);
+
 /* nsteps >= 0 steps ping-ponging between f_a and f_b, starting from f_a.
  * *result_in_b (may be NULL) is set to 1 when the last state is in f_b. */
 cmlbm_status cmlbm_run(cmlbm_sim *sim, void *f_a, void *f_b, int nsteps, void *stream, int *result_in_b);
@@ -155,16 +177,17 @@ cmlbm_status cmlbm_macroscopic(cmlbm_sim *sim, const void *f_post, void *rho, vo
  * output; synchronizes `stream`. */
 cmlbm_status cmlbm_totals(cmlbm_sim *sim, const void *f_post, double out4[4], void *stream);
 
-/* Adjoint of one D3Q27 step (reverse streaming plus the transposed Jacobian
- * of the central-moment collision and force terms).  Forward step n maps the
- * pre-collision state fbar^n, pulled from f_post_prev, to fbar^(n+1).  Given
- * lam_next = dL/dfbar^(n+1) ("real" [27][nz][ny][nx]), writes
- * lam = dL/dfbar^n and accumulates (adds) into
+/* Adjoint of one step, D3Q27 or D3Q15 (reverse streaming plus the transposed
+ * Jacobian of the central-moment collision and force terms of Sec. 7 and
+ * Appendix G).  Forward step n maps the pre-collision state fbar^n, pulled
+ * from f_post_prev, to fbar^(n+1).  Given lam_next = dL/dfbar^(n+1) ("real"
+ * SoA populations [q][nz][ny][nx]), writes lam = dL/dfbar^n and accumulates
+ * (adds) into
  *   dLdF_dev:     FP64 [3][nz][ny][nx] when a force field is set, or FP64 [3]
  *                 (dL/dF of the uniform force) otherwise;
- *   dLdomega_dev: FP64 [23], dL/domega_4 .. dL/domega_26.
- * The force and rates must be those of the forward step.  lam, lam_next and
- * f_post_prev must not overlap.  Errors: EUNSUPPORTED for q = 15. */
+ *   dLdomega_dev: FP64 [q-4], dL/domega_4 .. dL/domega_(q-1).
+ * The force, rates and attractor form must be those of the forward step.
+ * lam, lam_next and f_post_prev must not overlap. */
 cmlbm_status cmlbm_adjoint_step(cmlbm_sim *sim, const void *f_post_prev, const void *lam_next, void *lam,
                                 double *dLdF_dev, double *dLdomega_dev, void *stream);
 
@@ -185,8 +208,8 @@ cmlbm_status cmlbm_kinetic_energy_seed(cmlbm_sim *sim, const void *f_pre, double
 /* Adjoint of the initial state of cmlbm_init_equilibrium with respect to the
  * force: fbar(x, 0) = f^eq(rho, u0) - S(F, u0)/2 depends on F through S (Sec. 5
  * matching principle).  Accumulates -(1/2) (dS/dF)^T lam0 into dLdF_dev (same
- * layout as above).  u0_dev: "real" [3][nz][ny][nx]; lam0_dev = dL/dfbar(0).
- * D3Q27 only (EUNSUPPORTED otherwise). */
+ * layout as above).  u0_dev: "real" [3][nz][ny][nx]; lam0_dev = dL/dfbar(0)
+ * ("real" SoA populations). */
 cmlbm_status cmlbm_init_adjoint(cmlbm_sim *sim, const void *u0_dev, const void *lam0_dev, double *dLdF_dev,
                                 void *stream);
 

@@ -155,9 +155,15 @@ def source(lat, F, u):
     return (m * inv_d) @ K.T
 
 
-def attractors(lat, rho, kt_diag):
+def attractors(lat, rho, kt_diag, per_mass=False):
     """Attractor of every central monomial (order >= 2) given the
-    post-collision diagonal second moments kt_diag[..., 0:3] = (kxx, kyy, kzz)."""
+    post-collision diagonal second moments kt_diag[..., 0:3] = (kxx, kyy, kzz).
+
+    The factorized attractors (Sec. 3, the list after Eq.
+    centralmomentfdefinitionpostcollision; Eq. transformedcentralmomentattractors)
+    are the literal products kxx kyy, kxx kyy kzz by default.  per_mass=True
+    factorizes the moments per unit mass instead: rho (kxx/rho)(kyy/rho) and
+    rho (kxx/rho)(kyy/rho)(kzz/rho)."""
     like = rho
     zero = rho * 0
     cs2 = _num(CS2, like)
@@ -172,6 +178,8 @@ def attractors(lat, rho, kt_diag):
             val = kt_diag[..., spec[0]]
             for axis in spec[1:]:
                 val = val * kt_diag[..., axis]
+                if per_mass:
+                    val = val / rho
             out.append(val)
     return np.stack(out, axis=-1)
 
@@ -188,10 +196,11 @@ def _rates_vector(lat, omega, like):
 # ----------------------------------------------------------------------------
 # The collision
 # ----------------------------------------------------------------------------
-def collide(lat, fbar, F, omega):
+def collide(lat, fbar, F, omega, per_mass=False):
     """Post-collision transformed populations fbar~ = fbar + Omega + S (Eq.
     cascadedcollision1), for pre-collision fbar[..., Q], force F[..., 3] and
-    rates omega = (omega_4, ..., omega_(Q-1))."""
+    rates omega = (omega_4, ..., omega_(Q-1)); per_mass selects the
+    per-unit-mass factorized attractors (see attractors)."""
     exact = _is_exact(fbar)
     Phi = lat.Phi.astype(object) if exact else lat.Phi
     rho, u = macroscopic(lat, fbar, F)
@@ -214,7 +223,7 @@ def collide(lat, fbar, F, omega):
 
     # Orders three and up, toward the factorized attractors.
     higher = lat.order >= 3
-    A = attractors(lat, rho, kt_diag) @ Phi.T
+    A = attractors(lat, rho, kt_diag, per_mass) @ Phi.T
     Ct[..., higher] = C[..., higher] + w[higher] * (A[..., higher] - C[..., higher])
 
     PM = Phi @ M

@@ -37,14 +37,14 @@ def fluid_mask(solid, shape):
     return ~np.asarray(solid, dtype=bool)
 
 
-def collide_field(lat, f, F, omega, solid=None):
+def collide_field(lat, f, F, omega, solid=None, per_mass=False):
     """Post-collision populations at every fluid node (solid entries 0)."""
     shape = f.shape[1:]
     fluid = fluid_mask(solid, shape)
     fn = _nodes_last(f)
     Fn = _force_field(F, shape)
     post = np.zeros(fn.shape, dtype=np.result_type(fn, Fn, np.asarray(omega)))
-    post[fluid] = collision.collide(lat, fn[fluid], Fn[fluid], omega)
+    post[fluid] = collision.collide(lat, fn[fluid], Fn[fluid], omega, per_mass)
     return np.moveaxis(post, -1, 0)
 
 
@@ -65,14 +65,15 @@ def stream(lat, post, solid=None):
     return out
 
 
-def step(lat, f, F, omega, solid=None):
-    """One collide-and-stream step of the pre-collision state."""
-    return stream(lat, collide_field(lat, f, F, omega, solid), solid)
+def step(lat, f, F, omega, solid=None, per_mass=False):
+    """One collide-and-stream step of the pre-collision state (per_mass: the
+    attractor form, see collision.attractors)."""
+    return stream(lat, collide_field(lat, f, F, omega, solid, per_mass), solid)
 
 
-def run(lat, f, F, omega, nsteps, solid=None, callback=None):
+def run(lat, f, F, omega, nsteps, solid=None, callback=None, per_mass=False):
     for n in range(nsteps):
-        f = step(lat, f, F, omega, solid)
+        f = step(lat, f, F, omega, solid, per_mass)
         if callback is not None:
             callback(n + 1, f)
     return f

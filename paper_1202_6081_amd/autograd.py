@@ -1,4 +1,4 @@
-"""Differentiable D3Q27 runs: torch.autograd.Function over the HIP adjoint step,
+"""Differentiable D3Q27 / D3Q15 runs: torch.autograd.Function over the HIP adjoint step,
 with checkpoint-and-recompute over time.
 
 Forward: fbar(0) = f^eq(rho0, u0) - S/2 (cmlbm_init_equilibrium), N steps of
@@ -217,7 +217,7 @@ class _Run(torch.autograd.Function):
         lam = g.detach().to(dtype=sim.real).contiguous().clone()
         lam_tmp = sim.real_populations()
         dLdF = torch.zeros(ctx.F_shape, dtype=torch.float64, device=sim.device)
-        dLdw = torch.zeros(23, dtype=torch.float64, device=sim.device)
+        dLdw = torch.zeros(sim.q - 4, dtype=torch.float64, device=sim.device)
         sw = _Sweep(sim, pool, lam, lam_tmp, dLdF, dLdw)
         backward_sweep(sw, stored, ctx.nsteps, ctx.every, ctx.snapshots)
         sim.init_adjoint(ctx.u0, sw.lam, dLdF)
@@ -238,13 +238,14 @@ def last_backward_stats():
 
 
 def run(sim, rho0, u0, F, omega, nsteps, every=None, snapshots=None):
-    """Differentiable D3Q27 run: returns the pre-collision populations fbar(N)
+    """Differentiable run: returns the pre-collision populations fbar(N)
     (Q, nz, ny, nx), differentiable with respect to the force field F
-    (3, nz, ny, nx) and the rates omega (23,).  Exactly one of `every`
-    (uniform checkpoint interval) or `snapshots` (binomial schedule with that
-    many stored states besides x(0)) must be given."""
-    if sim.q != 27:
-        raise cmlbm.CmlbmError(-2, "the adjoint is provided for D3Q27")
+    (3, nz, ny, nx) or uniform force F (3,), and the rates omega (Q - 4,).
+    Exactly one of `every` (uniform checkpoint interval) or `snapshots`
+    (binomial schedule with that many stored states besides x(0)) must be
+    given."""
+    if len(omega) != sim.q - 4:
+        raise ValueError(f"expected {sim.q - 4} rates")
     if (every is None) == (snapshots is None):
         raise ValueError("give exactly one of every= or snapshots=")
     return _Run.apply(F, omega, sim, rho0, u0, int(nsteps), int(every or 0), int(snapshots or 0))

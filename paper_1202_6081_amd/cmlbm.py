@@ -43,9 +43,11 @@ def load_library():
         "cmlbm_set_force_uniform": (i, [vp, d, d, d]),
         "cmlbm_set_force_field": (i, [vp, vp]),
         "cmlbm_set_force_scale": (i, [vp, d]),
+        "cmlbm_set_attractor_per_mass": (i, [vp, i]),
         "cmlbm_set_mask": (i, [vp, vp]),
         "cmlbm_init_equilibrium": (i, [vp, vp, vp, vp, vp, vp]),
         "cmlbm_step": (i, [vp, vp, vp, vp]),
+        "cmlbm_step_totals": (i, [vp, vp, vp, vp, vp]),
         "cmlbm_run": (i, [vp, vp, vp, i, vp, ctypes.POINTER(i)]),
         "cmlbm_gather_precollision": (i, [vp, vp, vp, vp]),
         "cmlbm_export_populations": (i, [vp, vp, vp, vp]),
@@ -70,9 +72,9 @@ def load_library():
 
 def exported_symbols():
     return ["cmlbm_create", "cmlbm_destroy", "cmlbm_set_rates", "cmlbm_set_force_uniform",
-            "cmlbm_set_force_field", "cmlbm_set_force_scale", "cmlbm_set_mask", "cmlbm_init_equilibrium",
-            "cmlbm_step", "cmlbm_run", "cmlbm_gather_precollision", "cmlbm_export_populations",
-            "cmlbm_import_populations", "cmlbm_macroscopic", "cmlbm_totals",
+            "cmlbm_set_force_field", "cmlbm_set_force_scale", "cmlbm_set_attractor_per_mass", "cmlbm_set_mask",
+            "cmlbm_init_equilibrium", "cmlbm_step", "cmlbm_step_totals", "cmlbm_run", "cmlbm_gather_precollision",
+            "cmlbm_export_populations", "cmlbm_import_populations", "cmlbm_macroscopic", "cmlbm_totals",
             "cmlbm_adjoint_step", "cmlbm_kinetic_energy_sum", "cmlbm_kinetic_energy_seed", "cmlbm_init_adjoint",
             "cmlbm_status_string", "cmlbm_last_error", "cmlbm_version"]
 
@@ -151,6 +153,10 @@ def cmlbm_set_force_scale(h, scale):
     _check(load_library().cmlbm_set_force_scale(h, float(scale)), h)
 
 
+def cmlbm_set_attractor_per_mass(h, per_mass):
+    _check(load_library().cmlbm_set_attractor_per_mass(h, int(bool(per_mass))), h)
+
+
 def cmlbm_set_mask(h, mask):
     _check(load_library().cmlbm_set_mask(h, _ptr(mask)), h)
 
@@ -162,6 +168,12 @@ def cmlbm_init_equilibrium(h, rho, u, f_pre, f_post, stream=None):
 
 def cmlbm_step(h, f_in, f_out, stream=None):
     _check(load_library().cmlbm_step(h, _ptr(f_in), _ptr(f_out), _stream(stream)), h)
+
+
+def cmlbm_step_totals(h, f_in, f_out, totals, stream=None):
+    if totals.dtype != torch.float64 or totals.numel() < 4:
+        raise CmlbmError(-1, "totals must be a device tensor of at least 4 float64")
+    _check(load_library().cmlbm_step_totals(h, _ptr(f_in), _ptr(f_out), _ptr(totals), _stream(stream)), h)
 
 
 def cmlbm_run(h, f_a, f_b, nsteps, stream=None):
@@ -268,6 +280,9 @@ class Sim:
     def set_force_scale(self, scale):
         cmlbm_set_force_scale(self.h, scale)
 
+    def set_attractor_per_mass(self, per_mass=True):
+        cmlbm_set_attractor_per_mass(self.h, per_mass)
+
     def set_mask(self, solid):
         if solid is None:
             self._keep.pop("mask", None)
@@ -286,8 +301,13 @@ class Sim:
         cmlbm_init_equilibrium(self.h, rho, u, f_pre, f_post, stream)
         return f_post, f_pre
 
-    def step(self, f_in, f_out, stream=None):
-        cmlbm_step(self.h, f_in, f_out, stream)
+    def step(self, f_in, f_out, stream=None, totals=None):
+        """One step f_in -> f_out.  With `totals` (4 float64 on the device), the
+        same pass also writes the FP64 (mass, momentum) of f_in's state."""
+        if totals is None:
+            cmlbm_step(self.h, f_in, f_out, stream)
+        else:
+            cmlbm_step_totals(self.h, f_in, f_out, totals, stream)
 
     def run(self, f_a, f_b, nsteps, stream=None):
         """Returns the buffer holding the last state."""

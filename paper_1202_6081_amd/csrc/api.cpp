@@ -20,11 +20,13 @@ struct cmlbm_sim {
   double F[3] = {0, 0, 0};
   const void* Ffield = nullptr;
   double fscale = 1.0;
+  int per_mass = 0;
   const uint8_t* mask = nullptr;
   double* totals_partials = nullptr;   // [kTotalsBlocks][4]
   double* totals_out = nullptr;        // [4]
   double* adj_partials = nullptr;      // [adj_nblk][26]
   int adj_nblk = 0;
+  double* step_partials = nullptr;     // [step_blocks][4] + [kReduceChunks][4], fused step totals
   std::string err;
 };
 
@@ -58,6 +60,7 @@ cmlbm::Rates<R> make_rates(const cmlbm_sim* s) {
     r.w[b] = R(s->omega[b - 4]);
     r.wc[b] = R(1.0 - s->omega[b - 4]);
   }
+  r.per_mass = s->per_mass;
   return r;
 }
 
@@ -144,8 +147,10 @@ cmlbm_status cmlbm_create(int q, int nx, int ny, int nz, int precision, cmlbm_si
   s->g.nxy = uint32_t(nx) * uint32_t(ny);
   s->g.N = N;
   for (double& w : s->omega) w = 1.0;
+  const uint64_t step_rows = cmlbm::step_blocks(s->g) + cmlbm::kReduceChunks;
   if (hipMalloc(&s->totals_partials, sizeof(double) * 4 * cmlbm::kTotalsBlocks) != hipSuccess ||
-      hipMalloc(&s->totals_out, sizeof(double) * 4) != hipSuccess) {
+      hipMalloc(&s->totals_out, sizeof(double) * 4) != hipSuccess ||
+      hipMalloc(&s->step_partials, sizeof(double) * 4 * step_rows) != hipSuccess) {
     g_create_error = "device scratch allocation failed";
     cmlbm_destroy(s);
     return CMLBM_ENOMEM;
@@ -159,6 +164,7 @@ void cmlbm_destroy(cmlbm_sim* sim) {
   if (sim->totals_partials) (void)hipFree(sim->totals_partials);
   if (sim->totals_out) (void)hipFree(sim->totals_out);
   if (sim->adj_partials) (void)hipFree(sim->adj_partials);
+  if (sim->step_partials) (void)hipFree(sim->step_partials);
   delete sim;
 }
 
@@ -192,6 +198,13 @@ cmlbm_status cmlbm_set_force_field(cmlbm_sim* s, const void* F_dev) {
   return ok(s);
 }
 
+cmlbm_status cmlbm_set_attractor_per_mass(cmlbm_sim* s, int per_mass) {
+  if (!s) return CMLBM_EINVAL;
+  if (per_mass != 0 && per_mass != 1) return fail(s, CMLBM_EINVAL, "per_mass must be 0 or 1");
+  s->per_mass = per_mass;
+  return ok(s);
+}
+
 cmlbm_status cmlbm_set_force_scale(cmlbm_sim* s, double scale) {
   if (!s) return CMLBM_EINVAL;
   if (!std::isfinite(scale)) return fail(s, CMLBM_EINVAL, "scale must be finite");
@@ -216,10 +229,17 @@ cmlbm_status cmlbm_init_equilibrium(cmlbm_sim* s, const void* rho_dev, const voi
   return check_hip(s, e, "init_equilibrium");
 }
 
-cmlbm_status cmlbm_step(cmlbm_sim* s, const void* f_in, void* f_out, void* stream) {
-  if (!s) return CMLBM_EINVAL;
+namespace {
+
+cmlbm_status step_common(cmlbm_sim* s, const void* f_in, void* f_out, double* totals_dev, void* stream) {
   if (!f_in || !f_out) return fail(s, CMLBM_EINVAL, "NULL population buffer");
   if (f_in == f_out) return fail(s, CMLBM_EINVAL, "f_in and f_out must differ (pull streaming)");
+  double* partials = nullptr;
+  double* stage = nullptr;
+  if (totals_dev) {
+    partials = s->step_partials;
+    stage = s->step_partials + 4 * cmlbm::step_blocks(s->g);
+  }
   cmlbm::StepArgs<double> a64{};
   cmlbm::StepArgs<float> a32{};
   if (s->prec == CMLBM_F64) {
@@ -229,6 +249,9 @@ cmlbm_status cmlbm_step(cmlbm_sim* s, const void* f_in, void* f_out, void* strea
     a64.mask = s->mask;
     a64.force = make_force<double>(s);
     a64.rates = make_rates<double>(s);
+    a64.partials = partials;
+    a64.stage = stage;
+    a64.totals = totals_dev;
   } else {
     a32.g = s->g;
     a32.fin = f_in;
@@ -236,8 +259,24 @@ cmlbm_status cmlbm_step(cmlbm_sim* s, const void* f_in, void* f_out, void* strea
     a32.mask = s->mask;
     a32.force = make_force<float>(s);
     a32.rates = make_rates<float>(s);
+    a32.partials = partials;
+    a32.stage = stage;
+    a32.totals = totals_dev;
   }
   return check_hip(s, cmlbm::launch_step(s->q, s->prec, a64, a32, static_cast<hipStream_t>(stream)), "step");
+}
+
+}  // namespace
+
+cmlbm_status cmlbm_step(cmlbm_sim* s, const void* f_in, void* f_out, void* stream) {
+  if (!s) return CMLBM_EINVAL;
+  return step_common(s, f_in, f_out, nullptr, stream);
+}
+
+cmlbm_status cmlbm_step_totals(cmlbm_sim* s, const void* f_in, void* f_out, double* totals_dev, void* stream) {
+  if (!s) return CMLBM_EINVAL;
+  if (!totals_dev) return fail(s, CMLBM_EINVAL, "totals_dev is NULL");
+  return step_common(s, f_in, f_out, totals_dev, stream);
 }
 
 cmlbm_status cmlbm_run(cmlbm_sim* s, void* f_a, void* f_b, int nsteps, void* stream, int* result_in_b) {
@@ -303,7 +342,6 @@ cmlbm_status cmlbm_totals(cmlbm_sim* s, const void* f_post, double out4[4], void
 cmlbm_status cmlbm_adjoint_step(cmlbm_sim* s, const void* f_post_prev, const void* lam_next, void* lam,
                                 double* dLdF_dev, double* dLdomega_dev, void* stream) {
   if (!s) return CMLBM_EINVAL;
-  if (s->q != 27) return fail(s, CMLBM_EUNSUPPORTED, "the adjoint step is provided for D3Q27");
   if (!f_post_prev || !lam_next || !lam || !dLdF_dev || !dLdomega_dev) return fail(s, CMLBM_EINVAL, "NULL buffer");
   if (lam == lam_next || lam == f_post_prev || lam_next == f_post_prev)
     return fail(s, CMLBM_EINVAL, "lam, lam_next and f_post_prev must differ");
@@ -338,7 +376,7 @@ cmlbm_status cmlbm_adjoint_step(cmlbm_sim* s, const void* f_post_prev, const voi
     a32.rates = make_rates<float>(s);
   }
   double* dLdF_uniform = s->Ffield ? nullptr : dLdF_dev;
-  hipError_t e = cmlbm::launch_adjoint(s->prec, a64, a32, s->adj_partials, nblk, dLdomega_dev, dLdF_uniform,
+  hipError_t e = cmlbm::launch_adjoint(s->q, s->prec, a64, a32, s->adj_partials, nblk, dLdomega_dev, dLdF_uniform,
                                        static_cast<hipStream_t>(stream));
   return check_hip(s, e, "adjoint_step");
 }
@@ -369,9 +407,8 @@ cmlbm_status cmlbm_kinetic_energy_seed(cmlbm_sim* s, const void* f_pre, double s
 cmlbm_status cmlbm_init_adjoint(cmlbm_sim* s, const void* u0_dev, const void* lam0_dev, double* dLdF_dev,
                                 void* stream) {
   if (!s) return CMLBM_EINVAL;
-  if (s->q != 27) return fail(s, CMLBM_EUNSUPPORTED, "the initial-condition adjoint is provided for D3Q27");
   if (!u0_dev || !lam0_dev || !dLdF_dev) return fail(s, CMLBM_EINVAL, "NULL buffer");
-  hipError_t e = cmlbm::launch_init_adjoint(s->prec, s->g, u0_dev, lam0_dev, s->mask, make_force<double>(s),
+  hipError_t e = cmlbm::launch_init_adjoint(s->q, s->prec, s->g, u0_dev, lam0_dev, s->mask, make_force<double>(s),
                                             make_force<float>(s), dLdF_dev, s->totals_partials,
                                             cmlbm::kTotalsBlocks, static_cast<hipStream_t>(stream));
   return check_hip(s, e, "init_adjoint");

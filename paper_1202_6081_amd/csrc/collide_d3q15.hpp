@@ -195,7 +195,7 @@ CMLBM_HD void collide15(R (&f)[15], R Fx, R Fy, R Fz, const Rates<R>& p) {
   const R tzz = (t9 - d2) * R(1.0 / 3.0);
   populations15(rho, ux, uy, uz, R(0.5) * Fx, R(0.5) * Fy, R(0.5) * Fz, p.wc[4] * cxy, p.wc[5] * cxz,
                 p.wc[6] * cyz, txx, tyy, tzz, p.wc[10] * cxyy, p.wc[11] * cxxy, p.wc[12] * cxxz, p.wc[13] * cxyz,
-                p.wc[14] * cxxyy + p.w[14] * (txx * tyy), f);
+                p.wc[14] * cxxyy + p.w[14] * (txx * tyy * (p.per_mass ? R(1) / rho : R(1))), f);
 }
 
 // Initial transformed populations fbar = f^eq(rho, u) - S/2: f^eq has the
@@ -209,6 +209,351 @@ CMLBM_HD void initial15(R rho, R ux, R uy, R uz, R Fx, R Fy, R Fz, R (&f)[15]) {
   source15(Fx, Fy, Fz, ux, uy, uz, S);
 #pragma unroll
   for (int a = 0; a < 15; ++a) f[a] -= R(0.5) * S[a];
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint of collide15.
+//
+// The fifteen moments are indexed 1, x, y, z, xy, xz, yz, xx, yy, zz, xyy, xxy,
+// xxz, xyz, xxyy.  The binomial shift between raw and central moments factors
+// into one shift per axis, because this set is closed under lowering any one
+// exponent: along an axis the moments form triples (exponent 0, 1, 2), pairs
+// (0, 1) and singles, and a triple (m0, m1, m2) shifts by u as
+// (m0, m1 - u m0, m2 - 2 u m1 + u^2 m0) (raw to central) or
+// (m0, m1 + u m0, m2 + 2 u m1 + u^2 m0) (central to raw).
+// ---------------------------------------------------------------------------
+struct Groups15 {
+  int t[4][3];   // triples
+  int nt;
+  int p[4][2];   // pairs
+  int np;
+};
+
+template <int AX>
+CMLBM_HDC Groups15 groups15() {
+  if constexpr (AX == 0)
+    return {{{0, 1, 7}, {2, 4, 11}, {3, 5, 12}, {8, 10, 14}}, 4, {{6, 13}, {0, 0}, {0, 0}, {0, 0}}, 1};
+  else if constexpr (AX == 1)
+    return {{{0, 2, 8}, {1, 4, 10}, {7, 11, 14}, {0, 0, 0}}, 3, {{3, 6}, {5, 13}, {0, 0}, {0, 0}}, 2};
+  else
+    return {{{0, 3, 9}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, 1, {{1, 5}, {2, 6}, {4, 13}, {7, 12}}, 4};
+}
+
+// Exponents (x, y, z) of moment m.
+CMLBM_HDC Vel mono15(int m) {
+  constexpr Vel t[15] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1}, {2, 0, 0},
+                         {0, 2, 0}, {0, 0, 2}, {1, 2, 0}, {2, 1, 0}, {2, 0, 1}, {1, 1, 1}, {2, 2, 0}};
+  return t[m];
+}
+
+CMLBM_HDC int ipow(int v, int n) { return n == 0 ? 1 : (n == 1 ? v : v * v); }
+
+// Shift of moments m by u along axis AX (sg = -1: raw to central, +1: back).
+template <int AX, typename R>
+CMLBM_HD void shift15(R (&m)[15], R u, R sg) {
+  constexpr Groups15 G = groups15<AX>();
+  const R v = sg * u;
+#pragma unroll
+  for (int i = 0; i < G.nt; ++i) {
+    const int a = G.t[i][0], b = G.t[i][1], c = G.t[i][2];
+    m[c] = m[c] + v * (R(2) * m[b] + v * m[a]);
+    m[b] = m[b] + v * m[a];
+  }
+#pragma unroll
+  for (int i = 0; i < G.np; ++i) m[G.p[i][1]] += v * m[G.p[i][0]];
+}
+
+// Adjoint of shift15: m = its input, g = adjoint of its output (in place ->
+// adjoint of its input); adds d/du to gu.
+template <int AX, typename R>
+CMLBM_HD void shift15_adj(const R (&m)[15], R u, R sg, R (&g)[15], R& gu) {
+  constexpr Groups15 G = groups15<AX>();
+  const R v = sg * u;
+  R gv = R(0);
+#pragma unroll
+  for (int i = 0; i < G.nt; ++i) {
+    const int a = G.t[i][0], b = G.t[i][1], c = G.t[i][2];
+    const R g1 = g[b], g2 = g[c];
+    gv += g1 * m[a] + g2 * R(2) * (m[b] + v * m[a]);
+    g[a] += v * g1 + v * v * g2;
+    g[b] = g1 + R(2) * v * g2;
+  }
+#pragma unroll
+  for (int i = 0; i < G.np; ++i) {
+    const int a = G.p[i][0], b = G.p[i][1];
+    gv += g[b] * m[a];
+    g[a] += v * g[b];
+  }
+  gu += sg * gv;
+}
+
+// Raw moments of h, and the transpose (adjoint) of that linear map.
+template <typename R>
+CMLBM_HD void raw15(const R (&h)[15], R (&r)[15]) {
+#pragma unroll
+  for (int m = 0; m < 15; ++m) {
+    const Vel e = mono15(m);
+    R acc = R(0);
+#pragma unroll
+    for (int a = 0; a < 15; ++a) {
+      const int k = ipow(kE15[a].x, e.x) * ipow(kE15[a].y, e.y) * ipow(kE15[a].z, e.z);
+      if (k == 1) acc += h[a];
+      if (k == -1) acc -= h[a];
+    }
+    r[m] = acc;
+  }
+}
+
+template <typename R>
+CMLBM_HD void raw15_adj(const R (&gr)[15], R (&gh)[15]) {
+#pragma unroll
+  for (int a = 0; a < 15; ++a) {
+    R acc = R(0);
+#pragma unroll
+    for (int m = 0; m < 15; ++m) {
+      const Vel e = mono15(m);
+      const int k = ipow(kE15[a].x, e.x) * ipow(kE15[a].y, e.y) * ipow(kE15[a].z, e.z);
+      if (k == 1) acc += gr[m];
+      if (k == -1) acc -= gr[m];
+    }
+    gh[a] = acc;
+  }
+}
+
+// Transpose of the raw-moment inversion at the end of populations15:
+// gs = (d f / d s)^T g.
+template <typename R>
+CMLBM_HD void inverse15_adj(const R (&g)[15], R (&gs)[15]) {
+  R c = R(0), cx = R(0), cy = R(0), cz = R(0), cxy = R(0), cxz = R(0), cyz = R(0), cxyz = R(0);
+#pragma unroll
+  for (int a = 7; a < 15; ++a) {
+    const int x = kE15[a].x, y = kE15[a].y, z = kE15[a].z;
+    c += g[a];
+    cx += R(x) * g[a];
+    cy += R(y) * g[a];
+    cz += R(z) * g[a];
+    cxy += R(x * y) * g[a];
+    cxz += R(x * z) * g[a];
+    cyz += R(y * z) * g[a];
+    cxyz += R(x * y * z) * g[a];
+  }
+  const R p1 = R(0.5) * (g[1] + g[2]), m1 = R(0.5) * (g[1] - g[2]);
+  const R p2 = R(0.5) * (g[3] + g[4]), m2 = R(0.5) * (g[3] - g[4]);
+  const R p3 = R(0.5) * (g[5] + g[6]), m3 = R(0.5) * (g[5] - g[6]);
+  gs[0] = g[0];
+  gs[1] = m1;
+  gs[2] = m2;
+  gs[3] = m3;
+  gs[4] = R(0.125) * cxy;
+  gs[5] = R(0.125) * cxz;
+  gs[6] = R(0.125) * cyz;
+  gs[7] = p1 - g[0];
+  gs[8] = p2 - g[0];
+  gs[9] = p3 - g[0];
+  gs[10] = R(0.125) * cx - m1;
+  gs[11] = R(0.125) * cy - m2;
+  gs[12] = R(0.125) * cz - m3;
+  gs[13] = R(0.125) * cxyz;
+  gs[14] = R(0.125) * c - (p1 + p2 + p3) + R(2) * g[0];
+}
+
+// Adjoint of source15 with respect to F and u: gS = adjoint of S.
+template <typename R>
+CMLBM_HD void source15_adj(R Fx, R Fy, R Fz, R ux, R uy, R uz, const R (&gS)[15], R& gFx, R& gFy, R& gFz,
+                           R& gux, R& guy, R& guz) {
+  R G[15];
+#pragma unroll
+  for (int b = 1; b < 15; ++b) {
+    R acc = R(0);
+#pragma unroll
+    for (int a = 0; a < 15; ++a) {
+      const int k = k15_basis(b, kE15[a]);
+      if (k != 0) acc += R(k) * gS[a];
+    }
+    G[b] = acc * R(1.0 / k15_norm(b));
+  }
+  const R ux2 = ux * ux, uy2 = uy * uy, uz2 = uz * uz;
+  gFx += G[1];
+  gFy += G[2];
+  gFz += G[3];
+  // ms4..ms6
+  gFx += uy * G[4] + uz * G[5];
+  gFy += ux * G[4] + uz * G[6];
+  gFz += ux * G[5] + uy * G[6];
+  gux += Fy * G[4] + Fz * G[5];
+  guy += Fx * G[4] + Fz * G[6];
+  guz += Fx * G[5] + Fy * G[6];
+  // ms7..ms9
+  gFx += R(2) * ux * (G[7] + G[8] + G[9]);
+  gFy += R(2) * uy * (-G[7] + G[8] + G[9]);
+  gFz += R(2) * uz * (G[9] - R(2) * G[8]);
+  gux += R(2) * Fx * (G[7] + G[8] + G[9]);
+  guy += R(2) * Fy * (-G[7] + G[8] + G[9]);
+  guz += R(2) * Fz * (G[9] - R(2) * G[8]);
+  // ms10..ms12
+  gFx += (R(5) * (R(3) * ux2 + uy2 + uz2) - R(13)) * G[10] + R(10) * ux * (uy * G[11] + uz * G[12]);
+  gFy += (R(5) * (ux2 + R(3) * uy2 + uz2) - R(13)) * G[11] + R(10) * uy * (ux * G[10] + uz * G[12]);
+  gFz += (R(5) * (ux2 + uy2 + R(3) * uz2) - R(13)) * G[12] + R(10) * uz * (ux * G[10] + uy * G[11]);
+  gux += (R(30) * Fx * ux + R(10) * (Fy * uy + Fz * uz)) * G[10] + R(10) * (Fy * ux + Fx * uy) * G[11] +
+         R(10) * (Fz * ux + Fx * uz) * G[12];
+  guy += R(10) * (Fx * uy + Fy * ux) * G[10] + (R(30) * Fy * uy + R(10) * (Fx * ux + Fz * uz)) * G[11] +
+         R(10) * (Fz * uy + Fy * uz) * G[12];
+  guz += R(10) * (Fx * uz + Fz * ux) * G[10] + R(10) * (Fy * uz + Fz * uy) * G[11] +
+         (R(30) * Fz * uz + R(10) * (Fx * ux + Fy * uy)) * G[12];
+  // ms13
+  gFx += uy * uz * G[13];
+  gFy += ux * uz * G[13];
+  gFz += ux * uy * G[13];
+  gux += (Fy * uz + Fz * uy) * G[13];
+  guy += (Fx * uz + Fz * ux) * G[13];
+  guz += (Fx * uy + Fy * ux) * G[13];
+  // ms14
+  const R ax = R(3) * (uy2 + uz2) - R(4), ay = R(3) * (ux2 + uz2) - R(4), az = R(3) * (ux2 + uy2) - R(4);
+  gFx += R(20) * ux * ax * G[14];
+  gFy += R(20) * uy * ay * G[14];
+  gFz += R(20) * uz * az * G[14];
+  gux += R(20) * (Fx * ax + R(6) * ux * (Fy * uy + Fz * uz)) * G[14];
+  guy += R(20) * (Fy * ay + R(6) * uy * (Fx * ux + Fz * uz)) * G[14];
+  guz += R(20) * (Fz * az + R(6) * uz * (Fx * ux + Fy * uy)) * G[14];
+}
+
+// Adjoint of collide15.  f: pre-collision populations.  g: on entry the
+// adjoint of the post-collision populations, on exit the adjoint of f.  Adds
+// the force adjoint and gw[b] (adjoint of omega_b, b = 4..14).
+template <typename R, typename W>
+CMLBM_HD void collide15_adj(const R (&f)[15], R Fx, R Fy, R Fz, const Rates<R>& p, R (&g)[15], R& gFx, R& gFy,
+                            R& gFz, W& gw) {
+  R rho, ux, uy, uz;
+  moments0_15(f, Fx, Fy, Fz, rho, ux, uy, uz);
+  R gux = R(0), guy = R(0), guz = R(0), grho = R(0);
+  const R sm = p.per_mass ? R(1) / rho : R(1);
+  const R dsm = p.per_mass ? -sm : R(0);
+
+  // forward: central moments c of h = f + S
+  R c[15];
+  {
+    R h[15];
+    source15(Fx, Fy, Fz, ux, uy, uz, h);
+#pragma unroll
+    for (int a = 0; a < 15; ++a) h[a] += f[a];
+    raw15(h, c);
+  }
+  shift15<0>(c, ux, R(-1));
+  shift15<1>(c, uy, R(-1));
+  shift15<2>(c, uz, R(-1));
+  // relaxed central moments t (conserved rows: rho and F/2)
+  const R d1 = p.wc[7] * (c[7] - c[8]);
+  const R d2 = p.wc[8] * (c[7] + c[8] - R(2) * c[9]);
+  const R t9 = p.wc[9] * (c[7] + c[8] + c[9]) + p.w[9] * rho;
+  const R txx = (R(2) * t9 + d2 + R(3) * d1) * R(1.0 / 6.0);
+  const R tyy = (R(2) * t9 + d2 - R(3) * d1) * R(1.0 / 6.0);
+  const R tzz = (t9 - d2) * R(1.0 / 3.0);
+  R t[15];
+  t[0] = rho;
+  t[1] = R(0.5) * Fx;
+  t[2] = R(0.5) * Fy;
+  t[3] = R(0.5) * Fz;
+#pragma unroll
+  for (int m = 4; m < 7; ++m) t[m] = p.wc[m] * c[m];
+  t[7] = txx;
+  t[8] = tyy;
+  t[9] = tzz;
+#pragma unroll
+  for (int m = 10; m < 14; ++m) t[m] = p.wc[m] * c[m];
+  t[14] = p.wc[14] * c[14] + p.w[14] * (txx * tyy * sm);
+
+  // back through the inversion and the shifts central -> raw (z, y, x order
+  // reversed: the forward applies z, then y, then x)
+  R gt[15];
+  inverse15_adj(g, gt);
+  {
+    R v[15];   // input of the x shift = t shifted along z and y
+#pragma unroll
+    for (int m = 0; m < 15; ++m) v[m] = t[m];
+    shift15<2>(v, uz, R(1));
+    shift15<1>(v, uy, R(1));
+    shift15_adj<0>(v, ux, R(1), gt, gux);
+    shift15<1>(v, uy, R(-1));   // undo: v = input of the y shift
+    shift15_adj<1>(v, uy, R(1), gt, guy);
+    shift15_adj<2>(t, uz, R(1), gt, guz);
+  }
+  // relaxation
+  grho += gt[0];
+  gFx += R(0.5) * gt[1];
+  gFy += R(0.5) * gt[2];
+  gFz += R(0.5) * gt[3];
+  R gc[15];
+  gc[0] = gc[1] = gc[2] = gc[3] = R(0);
+#pragma unroll
+  for (int m = 4; m < 7; ++m) {
+    gc[m] = p.wc[m] * gt[m];
+    gw[m] -= c[m] * gt[m];
+  }
+#pragma unroll
+  for (int m = 10; m < 14; ++m) {
+    gc[m] = p.wc[m] * gt[m];
+    gw[m] -= c[m] * gt[m];
+  }
+  R gtxx = gt[7], gtyy = gt[8];
+  const R gtzz = gt[9];
+  {
+    const R G = gt[14];
+    const R A = txx * tyy * sm;
+    gc[14] = p.wc[14] * G;
+    gw[14] += (A - c[14]) * G;
+    const R gA = p.w[14] * G;
+    grho += dsm * A * gA;
+    gtxx += gA * tyy * sm;
+    gtyy += gA * txx * sm;
+  }
+  {
+    const R gt9 = (gtxx + gtyy) * R(1.0 / 3.0) + gtzz * R(1.0 / 3.0);
+    const R gd2 = (gtxx + gtyy) * R(1.0 / 6.0) - gtzz * R(1.0 / 3.0);
+    const R gd1 = R(0.5) * (gtxx - gtyy);
+    gw[7] -= (c[7] - c[8]) * gd1;
+    gw[8] -= (c[7] + c[8] - R(2) * c[9]) * gd2;
+    gw[9] += (rho - (c[7] + c[8] + c[9])) * gt9;
+    grho += p.w[9] * gt9;
+    const R gD1 = p.wc[7] * gd1, gD2 = p.wc[8] * gd2, gT = p.wc[9] * gt9;
+    gc[7] = gD1 + gD2 + gT;
+    gc[8] = -gD1 + gD2 + gT;
+    gc[9] = R(-2) * gD2 + gT;
+  }
+  // back through the shifts raw -> central (forward order x, y, z)
+  {
+    R v[15];   // input of the z shift: c unshifted along z
+#pragma unroll
+    for (int m = 0; m < 15; ++m) v[m] = c[m];
+    shift15<2>(v, uz, R(1));
+    shift15_adj<2>(v, uz, R(-1), gc, guz);
+    shift15<1>(v, uy, R(1));   // input of the y shift
+    shift15_adj<1>(v, uy, R(-1), gc, guy);
+    shift15<0>(v, ux, R(1));   // raw moments of h
+    shift15_adj<0>(v, ux, R(-1), gc, gux);
+  }
+  // raw moments, source, density and velocity
+  R gh[15];
+  raw15_adj(gc, gh);
+  source15_adj(Fx, Fy, Fz, ux, uy, uz, gh, gFx, gFy, gFz, gux, guy, guz);
+  const R inv = R(1) / rho;
+  const R gjx = gux * inv, gjy = guy * inv, gjz = guz * inv;
+  grho -= (ux * gux + uy * guy + uz * guz) * inv;
+  gFx += R(0.5) * gjx;
+  gFy += R(0.5) * gjy;
+  gFz += R(0.5) * gjz;
+#pragma unroll
+  for (int a = 0; a < 15; ++a)
+    g[a] = gh[a] + grho + R(kE15[a].x) * gjx + R(kE15[a].y) * gjy + R(kE15[a].z) * gjz;
+}
+
+// Adjoint of the force dependence of initial15 (u0 fixed): fbar = f^eq - S/2.
+template <typename R>
+CMLBM_HD void initial15_adj_force(R ux, R uy, R uz, const R (&lam)[15], R& gFx, R& gFy, R& gFz) {
+  R gS[15];
+#pragma unroll
+  for (int a = 0; a < 15; ++a) gS[a] = R(-0.5) * lam[a];
+  R gux = R(0), guy = R(0), guz = R(0);
+  source15_adj(R(0), R(0), R(0), ux, uy, uz, gS, gFx, gFy, gFz, gux, guy, guz);
 }
 
 }  // namespace cmlbm

@@ -31,6 +31,10 @@ template <typename R>
 struct Rates {
   R w[27];
   R wc[27];
+  // 0: factorized attractors as the literal products of post-collision
+  // second moments (kxx kyy, kxx kyy kzz); 1: per unit mass, rho (kxx/rho)
+  // (kyy/rho) and rho (kxx/rho)(kyy/rho)(kzz/rho).
+  int per_mass;
 };
 
 // -- 3-point transforms along one axis --------------------------------------
@@ -217,8 +221,9 @@ CMLBM_HD void relax27(R (&m)[27], R rho, R Fx, R Fy, R Fz, const Rates<R>& p) {
   }
   m[K3(1, 1, 1)] *= p.wc[16];
   // fourth order, diagonal pairs (g17, g18, g19) toward the factorized attractors
+  const R sm = p.per_mass ? R(1) / rho : R(1);
   {
-    const R axy = kxx * kyy, axz = kxx * kzz, ayz = kyy * kzz;
+    const R axy = kxx * kyy * sm, axz = kxx * kzz * sm, ayz = kyy * kzz * sm;
     const R A = m[K3(2, 2, 0)], B = m[K3(2, 0, 2)], C = m[K3(0, 2, 2)];
     const R q1 = p.wc[17] * (A + B + C) + p.w[17] * (axy + axz + ayz);
     const R q2 = p.wc[18] * (A + B - R(2) * C) + p.w[18] * (axy + axz - R(2) * ayz);
@@ -236,7 +241,7 @@ CMLBM_HD void relax27(R (&m)[27], R rho, R Fx, R Fy, R Fz, const Rates<R>& p) {
   m[K3(2, 1, 2)] *= p.wc[24];
   m[K3(2, 2, 1)] *= p.wc[25];
   // sixth order toward kxx kyy kzz (g26)
-  m[K3(2, 2, 2)] = p.wc[26] * m[K3(2, 2, 2)] + p.w[26] * (kxx * kyy * kzz);
+  m[K3(2, 2, 2)] = p.wc[26] * m[K3(2, 2, 2)] + p.w[26] * (kxx * kyy * kzz * (sm * sm));
 }
 
 // First pass along z fused with the density and velocity sums: raw z-moments
@@ -286,10 +291,11 @@ CMLBM_HD void collide27(R (&m)[27], R Fx, R Fy, R Fz, const Rates<R>& p) {
 
 // Adjoint of relax27.  m: pre-relaxation central moments (unchanged).  g: on
 // entry the adjoint of the relaxed moments, on exit the adjoint of m.  Adds to
-// grho, gF*, gw[b] (adjoint of omega_b).
-template <typename R>
+// grho, gF*, gw[b] (adjoint of omega_b, b = 4..26; gw is an array or any
+// accumulator whose operator[] yields an R&).
+template <typename R, typename W>
 CMLBM_HD void relax27_adj(const R (&m)[27], R rho, const Rates<R>& p, R (&g)[27], R& grho,
-                                            R& gFx, R& gFy, R& gFz, R (&gw)[27]) {
+                                            R& gFx, R& gFy, R& gFz, W& gw) {
   // recompute the second-order post values and attractor inputs
   const R xx = m[K3(2, 0, 0)], yy = m[K3(0, 2, 0)], zz = m[K3(0, 0, 2)];
   const R D1 = xx - yy, D2 = xx + yy - R(2) * zz, T = xx + yy + zz;
@@ -298,16 +304,22 @@ CMLBM_HD void relax27_adj(const R (&m)[27], R rho, const Rates<R>& p, R (&g)[27]
   const R kyy = (R(2) * t + d2 - R(3) * d1) * R(1.0 / 6.0);
   const R kzz = (t - d2) * R(1.0 / 3.0);
   R gkxx = R(0), gkyy = R(0), gkzz = R(0);
+  // per-mass attractors: A = P sm^(k-1), dA/drho = -(k-1) A sm
+  const R sm = p.per_mass ? R(1) / rho : R(1);
+  const R dsm = p.per_mass ? -sm : R(0);
 
   // sixth order
   {
     const R G = g[K3(2, 2, 2)];
-    const R P = kxx * kyy * kzz;
+    const R s2 = sm * sm;
+    const R P = kxx * kyy * kzz * s2;
     gw[26] += (P - m[K3(2, 2, 2)]) * G;
     const R gP = p.w[26] * G;
-    gkxx += gP * kyy * kzz;
-    gkyy += gP * kxx * kzz;
-    gkzz += gP * kxx * kyy;
+    grho += R(2) * dsm * P * gP;
+    const R gPs = gP * s2;
+    gkxx += gPs * kyy * kzz;
+    gkyy += gPs * kxx * kzz;
+    gkzz += gPs * kxx * kyy;
     g[K3(2, 2, 2)] = p.wc[26] * G;
   }
   // fifth order and fourth-order off-diagonal: m~ = (1 - w) m
@@ -325,7 +337,7 @@ CMLBM_HD void relax27_adj(const R (&m)[27], R rho, const Rates<R>& p, R (&g)[27]
   CMLBM_SCALE_ADJ(K3(1, 1, 2), 22)
   // fourth order diagonal
   {
-    const R axy = kxx * kyy, axz = kxx * kzz, ayz = kyy * kzz;
+    const R axy = kxx * kyy * sm, axz = kxx * kzz * sm, ayz = kyy * kzz * sm;
     const R A = m[K3(2, 2, 0)], B = m[K3(2, 0, 2)], C = m[K3(0, 2, 2)];
     const R Q1 = A + B + C, Q2 = A + B - R(2) * C, Q3 = A - B;
     const R a1 = axy + axz + ayz, a2 = axy + axz - R(2) * ayz, a3 = axy - axz;
@@ -340,9 +352,10 @@ CMLBM_HD void relax27_adj(const R (&m)[27], R rho, const Rates<R>& p, R (&g)[27]
     const R ga1 = p.w[17] * gq1, ga2 = p.w[18] * gq2, ga3 = p.w[19] * gq3;
     const R gQ1 = p.wc[17] * gq1, gQ2 = p.wc[18] * gq2, gQ3 = p.wc[19] * gq3;
     const R gaxy = ga1 + ga2 + ga3, gaxz = ga1 + ga2 - ga3, gayz = ga1 - R(2) * ga2;
-    gkxx += gaxy * kyy + gaxz * kzz;
-    gkyy += gaxy * kxx + gayz * kzz;
-    gkzz += gaxz * kxx + gayz * kyy;
+    grho += dsm * (axy * gaxy + axz * gaxz + ayz * gayz);
+    gkxx += sm * (gaxy * kyy + gaxz * kzz);
+    gkyy += sm * (gaxy * kxx + gayz * kzz);
+    gkzz += sm * (gaxz * kxx + gayz * kyy);
     g[K3(2, 2, 0)] = gQ1 + gQ2 + gQ3;
     g[K3(2, 0, 2)] = gQ1 + gQ2 - gQ3;
     g[K3(0, 2, 2)] = gQ1 - R(2) * gQ2;
@@ -390,22 +403,25 @@ CMLBM_HD void relax27_adj(const R (&m)[27], R rho, const Rates<R>& p, R (&g)[27]
   g[K3(0, 0, 0)] = g[K3(1, 0, 0)] = g[K3(0, 1, 0)] = g[K3(0, 0, 1)] = R(0);
 }
 
-// Adjoint of collide27.  f: cube-ordered pre-collision populations.  g: on
-// entry the adjoint of the post-collision populations, on exit the adjoint of
-// f.  s: scratch.  Adds the force and rate adjoints.
-template <typename R>
-CMLBM_HD void collide27_adj(const R (&f)[27], R Fx, R Fy, R Fz, const Rates<R>& p, R (&g)[27],
-                                              R (&s)[27], R& gFx, R& gFy, R& gFz, R (&gw)[27]) {
+// Adjoint of collide27.  f: cube-ordered pre-collision populations on entry;
+// on exit it holds their central moments (pre-relaxation).  g: on entry the
+// adjoint of the post-collision populations, on exit the adjoint of f.  s:
+// scratch.  Adds the force and rate adjoints.  Only the central moments c are
+// kept: the input of each forward pass is recovered from c by the inverse
+// passes, which undo the forward ones exactly (up to rounding).
+template <typename R, typename W>
+CMLBM_HD void collide27_adj(R (&f)[27], R Fx, R Fy, R Fz, const Rates<R>& p, R (&g)[27], R (&s)[27],
+                                              R& gFx, R& gFy, R& gFz, W& gw) {
   R rho, ux, uy, uz;
-  moments0_27(f, Fx, Fy, Fz, rho, ux, uy, uz);
+  R(&cm)[27] = f;
+  first_pass27(cm, Fx, Fy, Fz, rho, ux, uy, uz);
+  fwd_pass<1>(cm, uy);
+  fwd_pass<0>(cm, ux);
   R gux = R(0), guy = R(0), guz = R(0), grho = R(0);
 
   // relaxed moments, then replay the inverse passes to get each pass's input
 #pragma unroll
-  for (int k = 0; k < 27; ++k) s[k] = f[k];
-  fwd_pass<2>(s, uz);
-  fwd_pass<1>(s, uy);
-  fwd_pass<0>(s, ux);
+  for (int k = 0; k < 27; ++k) s[k] = cm[k];
   relax27(s, rho, Fx, Fy, Fz, p);
   inv_pass<0>(s, ux);
   inv_pass<1>(s, uy);                        // s = input of the z inverse pass
@@ -415,25 +431,17 @@ CMLBM_HD void collide27_adj(const R (&f)[27], R Fx, R Fy, R Fz, const Rates<R>& 
   fwd_pass<0>(s, ux);                        // s = relaxed central moments
   inv_pass_adj<0>(s, ux, g, gux);
 
-  // relaxation (needs the pre-relaxation moments)
-#pragma unroll
-  for (int k = 0; k < 27; ++k) s[k] = f[k];
-  fwd_pass<2>(s, uz);
-  fwd_pass<1>(s, uy);
-  fwd_pass<0>(s, ux);
-  relax27_adj(s, rho, p, g, grho, gFx, gFy, gFz, gw);
+  relax27_adj(cm, rho, p, g, grho, gFx, gFy, gFz, gw);
 
-  // forward passes z, y, x in reverse order, recomputing each pass's input
+  // forward passes x, y, z in reverse order
 #pragma unroll
-  for (int k = 0; k < 27; ++k) s[k] = f[k];
-  fwd_pass<2>(s, uz);
-  fwd_pass<1>(s, uy);                        // s = input of the x pass
+  for (int k = 0; k < 27; ++k) s[k] = cm[k];
+  inv_pass<0>(s, ux);                        // s = input of the x forward pass
   fwd_pass_adj<0>(s, ux, g, gux);
-#pragma unroll
-  for (int k = 0; k < 27; ++k) s[k] = f[k];
-  fwd_pass<2>(s, uz);                        // s = input of the y pass
+  inv_pass<1>(s, uy);                        // s = input of the y forward pass
   fwd_pass_adj<1>(s, uy, g, guy);
-  fwd_pass_adj<2>(f, uz, g, guz);
+  inv_pass<2>(s, uz);                        // s = f
+  fwd_pass_adj<2>(s, uz, g, guz);
 
   // u = (sum f e + F/2) / rho, rho = sum f
   const R inv = R(1) / rho;

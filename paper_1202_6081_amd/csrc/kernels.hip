@@ -226,7 +226,35 @@ __device__ __forceinline__ void buf_store(T v, __amdgpu_buffer_rsrc_t r, uint32_
   }
 }
 
-template <int Q, class ST, bool MASK>
+// FP64 mass and momentum of one node's pre-collision populations, rho u
+// including F/2 (Eqs. densitycalculation, velocitycalculation).
+template <int Q, typename R>
+__device__ __forceinline__ void add_node_totals(const R (&f)[Q], R Fx, R Fy, R Fz, double (&acc)[4]) {
+  double rho = 0, jx = 0.5 * double(Fx), jy = 0.5 * double(Fy), jz = 0.5 * double(Fz);
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    const Vel e = Lattice<Q>::e(a);
+    const double v = double(f[a]);
+    rho += v;
+    if (e.x > 0) jx += v;
+    if (e.x < 0) jx -= v;
+    if (e.y > 0) jy += v;
+    if (e.y < 0) jy -= v;
+    if (e.z > 0) jz += v;
+    if (e.z < 0) jz -= v;
+  }
+  acc[0] += rho;
+  acc[1] += jx;
+  acc[2] += jy;
+  acc[3] += jz;
+}
+
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* sh /* [NV][8] */);
+
+// With TOT, the step also writes its block's FP64 totals of the input state to
+// args.partials[blockIdx.x][0..3].
+template <int Q, class ST, bool MASK, bool TOT>
 __global__ __launch_bounds__(CMLBM_STEP_BLOCK) void k_step(StepArgs<typename ST::R> args) {
   using R = typename ST::R;
   using T = typename ST::T;
@@ -235,34 +263,46 @@ __global__ __launch_bounds__(CMLBM_STEP_BLOCK) void k_step(StepArgs<typename ST:
   const uint32_t L = step_block_id();
   const uint32_t row = L / nseg;                  // row = z * ny + y, uniform over the block
   const uint32_t x = (L - row * nseg) * blockDim.x + threadIdx.x;
-  if (x >= uint32_t(g.nx)) return;
-  const Coord c{int(x), int(row % uint32_t(g.ny)), int(row / uint32_t(g.ny))};
   const uint32_t node = row * uint32_t(g.nx) + x;
-  if constexpr (MASK) {
-    if (args.mask[node]) return;
+  const bool active = x < uint32_t(g.nx) && !(MASK && args.mask[node]);
+  double acc[4] = {0, 0, 0, 0};
+  if constexpr (!TOT) {
+    if (!active) return;
   }
-  const Stencil st(g, c, +1);
-  R f[Q];
-  pull<Q, ST, MASK>(static_cast<const T*>(args.fin), g, args.mask, st, row, x, f);
-  R Fx, Fy, Fz;
-  if (args.force.field) {
-    const R* Ff = args.force.field + uint64_t(row) * uint32_t(g.nx);
-    const R sc = R(args.force.scale);
-    Fx = sc * ld32(Ff, x);
-    Fy = sc * ld32(Ff + g.N, x);
-    Fz = sc * ld32(Ff + 2 * g.N, x);
-  } else {
-    Fx = R(args.force.uni[0]);
-    Fy = R(args.force.uni[1]);
-    Fz = R(args.force.uni[2]);
-  }
-  collide<Q>(f, Fx, Fy, Fz, args.rates);
-  const uint32_t rowQ = uint32_t(g.nx) * uint32_t(Q);
-  const __amdgpu_buffer_rsrc_t rs =
-      array_rsrc(static_cast<T*>(args.fout) + uint64_t(row) * rowQ, rowQ * uint32_t(sizeof(T)));
+  if (active) {
+    const Coord c{int(x), int(row % uint32_t(g.ny)), int(row / uint32_t(g.ny))};
+    const Stencil st(g, c, +1);
+    R f[Q];
+    pull<Q, ST, MASK>(static_cast<const T*>(args.fin), g, args.mask, st, row, x, f);
+    R Fx, Fy, Fz;
+    if (args.force.field) {
+      const R* Ff = args.force.field + uint64_t(row) * uint32_t(g.nx);
+      const R sc = R(args.force.scale);
+      Fx = sc * ld32(Ff, x);
+      Fy = sc * ld32(Ff + g.N, x);
+      Fz = sc * ld32(Ff + 2 * g.N, x);
+    } else {
+      Fx = R(args.force.uni[0]);
+      Fy = R(args.force.uni[1]);
+      Fz = R(args.force.uni[2]);
+    }
+    if constexpr (TOT) add_node_totals<Q>(f, Fx, Fy, Fz, acc);
+    collide<Q>(f, Fx, Fy, Fz, args.rates);
+    const uint32_t rowQ = uint32_t(g.nx) * uint32_t(Q);
+    const __amdgpu_buffer_rsrc_t rs =
+        array_rsrc(static_cast<T*>(args.fout) + uint64_t(row) * rowQ, rowQ * uint32_t(sizeof(T)));
 #pragma unroll
-  for (int a = 0; a < Q; ++a)
-    buf_store(encode<ST, Q>(f[a], a), rs, in_row<Q>(uint32_t(g.nx), a, x) * uint32_t(sizeof(T)));
+    for (int a = 0; a < Q; ++a)
+      buf_store(encode<ST, Q>(f[a], a), rs, in_row<Q>(uint32_t(g.nx), a, x) * uint32_t(sizeof(T)));
+  }
+  if constexpr (TOT) {
+    __shared__ double sh[4 * 8];
+    block_sum<4>(acc, sh);
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) args.partials[uint64_t(blockIdx.x) * 4 + i] = acc[i];
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -420,6 +460,26 @@ __global__ __launch_bounds__(256) void k_reduce_rows(const double* partials, int
   if (threadIdx.x == 0) out[col] = accumulate ? out[col] + v[0] : v[0];
 }
 
+// First stage of a long reduction: block b sums rows [b*chunk, (b+1)*chunk) of
+// a [nrows][NV] array into stage[b][NV].
+template <int NV>
+__global__ __launch_bounds__(256) void k_reduce_chunks(const double* rows, uint64_t nrows, double* stage) {
+  const uint64_t chunk = (nrows + gridDim.x - 1) / gridDim.x;
+  const uint64_t r0 = uint64_t(blockIdx.x) * chunk;
+  const uint64_t r1 = r0 + chunk < nrows ? r0 + chunk : nrows;
+  double v[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = 0;
+  for (uint64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x)
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] += rows[r * NV + i];
+  __shared__ double sh[NV * 8];
+  block_sum<NV>(v, sh);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int i = 0; i < NV; ++i) stage[uint64_t(blockIdx.x) * NV + i] = v[i];
+}
+
 // ---------------------------------------------------------------------------
 // Initial condition: fbar(x, 0) = f^eq(rho0, u0) - S/2, then the inverse pull
 // into the post-collision buffer so that the first step's pull reproduces it.
@@ -494,7 +554,7 @@ __global__ __launch_bounds__(256) void k_scatter_post(Geom g, const typename ST:
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint step (D3Q27).  Forward step n maps the pre-collision state
+// Adjoint step (D3Q27 and D3Q15).  Forward step n maps the pre-collision state
 // fbar^n(x) (pulled from f_post_prev) to fbar~(x) = C(fbar^n(x)), and
 // fbar^{n+1}(x)_a = fbar~(x - e_a)_a (or bounce-back).  Given
 // lam_next = dL/dfbar^{n+1} (structure of arrays), the adjoint of the stored
@@ -502,64 +562,119 @@ __global__ __launch_bounds__(256) void k_scatter_post(Geom g, const typename ST:
 // solid, and lam(x) = J_C(fbar^n(x))^T mu.  dL/dF(x) and dL/domega accumulate
 // in FP64.
 // ---------------------------------------------------------------------------
-template <class ST, bool MASK>
-__global__ __launch_bounds__(256) void k_adjoint27(AdjArgs<typename ST::R> args, double* partials) {
+// Launch shape: a block walks a contiguous run of row segments (one segment =
+// blockDim.x consecutive x of one row), so row bases are uniform and the
+// neighbour rows that one segment gathers from are reused by the next ones
+// from the same XCD's L2; block ids are permuted per XCD as in the step.
+template <typename T>
+__device__ __forceinline__ void st32(T* base, uint32_t idx, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + idx * uint32_t(sizeof(T))) = v;
+}
+
+constexpr int kAdjBlock = 256;   // largest adjoint block (smaller for nx < 256)
+
+// Register slot of direction a in the adjoint's population vectors: cube
+// order for D3Q27 (the axis passes), the paper's order for D3Q15.
+template <int Q>
+__device__ __forceinline__ constexpr int slot(int a) {
+  if constexpr (Q == 27)
+    return cube27(a);
+  else
+    return a;
+}
+
+// Per-thread column of LDS: element b (4..26) at sh[(b - 4) * kAdjBlock + tid].
+template <typename R>
+struct LdsColumn {
+  R* p;
+  __device__ __forceinline__ R& operator[](int b) const { return p[(b - 4) * kAdjBlock]; }
+};
+
+// Waves per SIMD the adjoint is compiled for: three 27-vectors and the line
+// transforms fit 168 VGPRs in FP32 (3 waves); FP64 needs twice the registers.
+template <class ST>
+constexpr int adjoint_waves() {
+  return sizeof(typename ST::R) == 8 ? 1 : 3;
+}
+
+template <int Q, class ST, bool MASK>
+__global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(adjoint_waves<ST>()))) void k_adjoint(
+    AdjArgs<typename ST::R> args, double* partials) {
   using R = typename ST::R;
   using T = typename ST::T;
   const Geom g = args.g;
-  // Per-thread running sums over the (few) nodes this thread visits:
-  // wacc[b] = dL/domega_b for b = 4..26, uF = dL/dF for a uniform force.
-  R wacc[27];
+  const uint32_t nx = uint32_t(g.nx);
+  // Per-thread running sums over the (few) nodes this thread visits, in LDS to
+  // keep registers for the collision: dL/domega_b for b = 4..26; uF = dL/dF
+  // for a uniform force.
+  __shared__ R wsh[23 * kAdjBlock];
+  LdsColumn<R> wacc{wsh + threadIdx.x};
 #pragma unroll
-  for (int b = 0; b < 27; ++b) wacc[b] = R(0);
+  for (int b = 4; b < 27; ++b) wacc[b] = R(0);   // (b >= Q stays zero)
   R uF[3] = {R(0), R(0), R(0)};
-  const uint32_t nseg = (uint32_t(g.nx) + blockDim.x - 1) / blockDim.x;
+  const uint32_t nseg = (nx + blockDim.x - 1) / blockDim.x;
   const uint32_t items = nseg * uint32_t(g.ny) * uint32_t(g.nz);
-  for (uint32_t it = blockIdx.x; it < items; it += gridDim.x) {
+  const uint32_t per_block = (items + gridDim.x - 1) / gridDim.x;
+  const uint32_t it0 = step_block_id() * per_block;
+  const uint32_t it1 = min(items, it0 + per_block);
+  for (uint32_t it = it0; it < it1; ++it) {
     const uint32_t row = it / nseg;
     const uint32_t x = (it - row * nseg) * blockDim.x + threadIdx.x;
-    if (x >= uint32_t(g.nx)) continue;
+    if (x >= nx) continue;
     const Coord c{int(x), int(row % uint32_t(g.ny)), int(row / uint32_t(g.ny))};
-    const uint32_t node = row * uint32_t(g.nx) + x;
-    if (MASK && args.mask[node]) continue;
-    // forward pre-collision populations
-    R f[27];
+    if (MASK && args.mask[row * nx + x]) continue;
+    // forward pre-collision populations (D3Q27: in cube order)
+    R f[Q];
     {
       const Stencil st(g, c, +1);
-      R fa[27];
-      pull<27, ST, MASK>(static_cast<const T*>(args.fpost), g, args.mask, st, row, x, fa);
+      R fa[Q];
+      pull<Q, ST, MASK>(static_cast<const T*>(args.fpost), g, args.mask, st, row, x, fa);
 #pragma unroll
-      for (int a = 0; a < 27; ++a) f[cube27(a)] = fa[a];
+      for (int a = 0; a < Q; ++a) f[slot<Q>(a)] = fa[a];
     }
     // adjoint of this node's post-collision populations (reverse streaming)
-    R gm[27];
+    R gm[Q];
     {
       const Stencil st(g, c, -1);
-      const R* lam = args.lam_next;
 #pragma unroll
-      for (int a = 0; a < 27; ++a) {
-        const uint32_t dst = st.node(kE27[a], uint32_t(g.nx));
+      for (int a = 0; a < Q; ++a) {
+        const Vel e = Lattice<Q>::e(a);
         R v;
-        if (MASK && args.mask[dst])
-          v = lam[uint64_t(opposite<27>(a)) * g.N + node];
+        if (MASK && args.mask[st.node(e, nx)])
+          v = ld32(args.lam_next + uint64_t(opposite<Q>(a)) * g.N + uint64_t(row) * nx, x);
         else
-          v = lam[uint64_t(a) * g.N + dst];
-        gm[cube27(a)] = v;
+          v = ld32(args.lam_next + uint64_t(a) * g.N + uint64_t(st.row[e.y + 1][e.z + 1]) * nx,
+                   st.xs[e.x + 1]);
+        gm[slot<Q>(a)] = v;
       }
     }
     R Fx, Fy, Fz;
-    force_at(args.force, g.N, node, Fx, Fy, Fz);
-    R s[27];
+    if (args.force.field) {
+      const R* Ff = args.force.field + uint64_t(row) * nx;
+      const R sc = R(args.force.scale);
+      Fx = sc * ld32(Ff, x);
+      Fy = sc * ld32(Ff + g.N, x);
+      Fz = sc * ld32(Ff + 2 * g.N, x);
+    } else {
+      Fx = R(args.force.uni[0]);
+      Fy = R(args.force.uni[1]);
+      Fz = R(args.force.uni[2]);
+    }
     R gFx = R(0), gFy = R(0), gFz = R(0);
-    collide27_adj(f, Fx, Fy, Fz, args.rates, gm, s, gFx, gFy, gFz, wacc);
-    R* lam_out = args.lam;
+    if constexpr (Q == 27) {
+      R s[27];
+      collide27_adj(f, Fx, Fy, Fz, args.rates, gm, s, gFx, gFy, gFz, wacc);
+    } else {
+      collide15_adj(f, Fx, Fy, Fz, args.rates, gm, gFx, gFy, gFz, wacc);
+    }
 #pragma unroll
-    for (int a = 0; a < 27; ++a) lam_out[uint64_t(a) * g.N + node] = gm[cube27(a)];
+    for (int a = 0; a < Q; ++a) st32(args.lam + uint64_t(a) * g.N + uint64_t(row) * nx, x, gm[slot<Q>(a)]);
     if (args.force.field) {
       const double sc = double(args.force.scale);
-      args.dLdF[node] += sc * double(gFx);
-      args.dLdF[g.N + node] += sc * double(gFy);
-      args.dLdF[2 * g.N + node] += sc * double(gFz);
+      double* d = args.dLdF + uint64_t(row) * nx;
+      st32(d, x, ld32(d, x) + sc * double(gFx));
+      st32(d + g.N, x, ld32(d + g.N, x) + sc * double(gFy));
+      st32(d + 2 * g.N, x, ld32(d + 2 * g.N, x) + sc * double(gFz));
     } else {
       uF[0] += gFx;
       uF[1] += gFy;
@@ -568,7 +683,8 @@ __global__ __launch_bounds__(256) void k_adjoint27(AdjArgs<typename ST::R> args,
   }
   double v[26];
 #pragma unroll
-  for (int b = 4; b < 27; ++b) v[b - 4] = double(wacc[b]);
+  for (int b = 4; b < 27; ++b) v[b - 4] = b < Q ? double(wacc[b]) : 0.0;
+  __syncthreads();
   v[23] = double(uF[0]) * double(args.force.scale);
   v[24] = double(uF[1]) * double(args.force.scale);
   v[25] = double(uF[2]) * double(args.force.scale);
@@ -665,25 +781,40 @@ __global__ __launch_bounds__(256) void k_ke_seed(Geom g, const R* fpre, const ui
 // Adjoint of the initial condition fbar(x, 0) = f^eq(rho0, u0) - S(F, u0)/2
 // with respect to F (D3Q27): S is the inverse-pass image of the central moments
 // (0; F; 0, ...), so dL/dF = -(scale/2) (first-order rows of P(u0)^T lam0).
-template <typename R>
-__global__ __launch_bounds__(256) void k_init_adjoint27(Geom g, const R* u0, const R* lam0, const uint8_t* mask,
-                                                        ForceArgs<R> force, double* dLdF, double* partials) {
+template <int Q, typename R>
+__global__ __launch_bounds__(256) void k_init_adjoint(Geom g, const R* u0, const R* lam0, const uint8_t* mask,
+                                                      ForceArgs<R> force, double* dLdF, double* partials) {
   double acc[3] = {0, 0, 0};
   for (uint32_t n = blockIdx.x * blockDim.x + threadIdx.x; n < g.N; n += gridDim.x * blockDim.x) {
     if (mask && mask[n]) continue;
     const R ux = u0[n], uy = u0[g.N + n], uz = u0[2 * g.N + n];
-    R gm[27], zero[27];
+    R gx_, gy_, gz_;
+    if constexpr (Q == 27) {
+      // fbar(0) = inverse passes of (Maxwellian moments, -F/2 on the first
+      // central moments): the F adjoint is -1/2 times the first-order entries
+      // of the inverse passes' adjoint.
+      R gm[27], zero[27];
 #pragma unroll
-    for (int a = 0; a < 27; ++a) {
-      gm[cube27(a)] = lam0[uint64_t(a) * g.N + n];
-      zero[a] = R(0);
+      for (int a = 0; a < 27; ++a) {
+        gm[cube27(a)] = lam0[uint64_t(a) * g.N + n];
+        zero[a] = R(0);
+      }
+      R gu = R(0);
+      inv_pass_adj<2>(zero, uz, gm, gu);
+      inv_pass_adj<1>(zero, uy, gm, gu);
+      inv_pass_adj<0>(zero, ux, gm, gu);
+      gx_ = R(-0.5) * gm[K3(1, 0, 0)];
+      gy_ = R(-0.5) * gm[K3(0, 1, 0)];
+      gz_ = R(-0.5) * gm[K3(0, 0, 1)];
+    } else {
+      R lam[15];
+#pragma unroll
+      for (int a = 0; a < 15; ++a) lam[a] = lam0[uint64_t(a) * g.N + n];
+      gx_ = gy_ = gz_ = R(0);
+      initial15_adj_force(ux, uy, uz, lam, gx_, gy_, gz_);
     }
-    R gu = R(0);
-    inv_pass_adj<2>(zero, uz, gm, gu);
-    inv_pass_adj<1>(zero, uy, gm, gu);
-    inv_pass_adj<0>(zero, ux, gm, gu);
-    const double c = -0.5 * double(force.scale);
-    const double gx = c * double(gm[K3(1, 0, 0)]), gy = c * double(gm[K3(0, 1, 0)]), gz = c * double(gm[K3(0, 0, 1)]);
+    const double c = double(force.scale);
+    const double gx = c * double(gx_), gy = c * double(gy_), gz = c * double(gz_);
     if (force.field) {
       dLdF[n] += gx;
       dLdF[g.N + n] += gy;
@@ -719,6 +850,12 @@ inline dim3 step_grid(const Geom& g, int bx) {
   return dim3(unsigned((g.nx + bx - 1) / bx) * unsigned(g.ny) * unsigned(g.nz));
 }
 
+}  // namespace
+
+uint64_t step_blocks(const Geom& g) { return step_grid(g, step_block(g)).x; }
+
+namespace {
+
 inline int adjoint_block(const Geom& g) { return g.nx < 256 ? ((g.nx + 63) / 64) * 64 : 256; }
 
 inline unsigned aux_grid(const Geom& g) {
@@ -729,10 +866,21 @@ inline unsigned aux_grid(const Geom& g) {
 template <int Q, class ST>
 hipError_t step_impl(const StepArgs<typename ST::R>& a, hipStream_t st) {
   const int bx = step_block(a.g);
+  const dim3 grid = step_grid(a.g, bx);
+  if (!a.partials) {
+    if (a.mask)
+      hipLaunchKernelGGL((k_step<Q, ST, true, false>), grid, dim3(bx), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_step<Q, ST, false, false>), grid, dim3(bx), 0, st, a);
+    return hipGetLastError();
+  }
   if (a.mask)
-    hipLaunchKernelGGL((k_step<Q, ST, true>), step_grid(a.g, bx), dim3(bx), 0, st, a);
+    hipLaunchKernelGGL((k_step<Q, ST, true, true>), grid, dim3(bx), 0, st, a);
   else
-    hipLaunchKernelGGL((k_step<Q, ST, false>), step_grid(a.g, bx), dim3(bx), 0, st, a);
+    hipLaunchKernelGGL((k_step<Q, ST, false, true>), grid, dim3(bx), 0, st, a);
+  hipLaunchKernelGGL(k_reduce_chunks<4>, dim3(kReduceChunks), dim3(kBlock), 0, st, a.partials, uint64_t(grid.x),
+                     a.stage);
+  hipLaunchKernelGGL(k_reduce_rows, dim3(4), dim3(kBlock), 0, st, a.stage, kReduceChunks, 4, a.totals, 0);
   return hipGetLastError();
 }
 
@@ -789,14 +937,14 @@ hipError_t init_impl(const Geom& g, const void* rho0, const void* u0, const Forc
   return hipGetLastError();
 }
 
-template <class ST>
+template <int Q, class ST>
 hipError_t adjoint_impl(const AdjArgs<typename ST::R>& a, double* partials, int nblk, double* dLdomega,
                         double* dLdF_uniform, hipStream_t st) {
   if (a.mask)
-    hipLaunchKernelGGL((k_adjoint27<ST, true>), dim3(nblk), dim3(adjoint_block(a.g)), 0, st, a, partials);
+    hipLaunchKernelGGL((k_adjoint<Q, ST, true>), dim3(nblk), dim3(adjoint_block(a.g)), 0, st, a, partials);
   else
-    hipLaunchKernelGGL((k_adjoint27<ST, false>), dim3(nblk), dim3(adjoint_block(a.g)), 0, st, a, partials);
-  hipLaunchKernelGGL(k_reduce_rows, dim3(23), dim3(kBlock), 0, st, partials, nblk, 26, dLdomega, 1);
+    hipLaunchKernelGGL((k_adjoint<Q, ST, false>), dim3(nblk), dim3(adjoint_block(a.g)), 0, st, a, partials);
+  hipLaunchKernelGGL(k_reduce_rows, dim3(Q - 4), dim3(kBlock), 0, st, partials, nblk, 26, dLdomega, 1);
   if (dLdF_uniform)
     hipLaunchKernelGGL(k_reduce_rows, dim3(3), dim3(kBlock), 0, st, partials + 23, nblk, 26, dLdF_uniform, 1);
   return hipGetLastError();
@@ -881,12 +1029,18 @@ hipError_t launch_init(int q, int prec, const Geom& g, const void* rho0, const v
                  (init_impl<15, StBF16>(g, rho0, u0, f32, mask, fpre, fpost, st)))
 }
 
-hipError_t launch_adjoint(int prec, const AdjArgs<double>& a64, const AdjArgs<float>& a32, double* partials,
+hipError_t launch_adjoint(int q, int prec, const AdjArgs<double>& a64, const AdjArgs<float>& a32, double* partials,
                           int nblk, double* dLdomega, double* dLdF_uniform, hipStream_t st) {
-  CMLBM_DISPATCH(prec, (adjoint_impl<StF64>(a64, partials, nblk, dLdomega, dLdF_uniform, st)),
-                 (adjoint_impl<StF32>(a32, partials, nblk, dLdomega, dLdF_uniform, st)),
-                 (adjoint_impl<StF16>(a32, partials, nblk, dLdomega, dLdF_uniform, st)),
-                 (adjoint_impl<StBF16>(a32, partials, nblk, dLdomega, dLdF_uniform, st)))
+  if (q == 27) {
+    CMLBM_DISPATCH(prec, (adjoint_impl<27, StF64>(a64, partials, nblk, dLdomega, dLdF_uniform, st)),
+                   (adjoint_impl<27, StF32>(a32, partials, nblk, dLdomega, dLdF_uniform, st)),
+                   (adjoint_impl<27, StF16>(a32, partials, nblk, dLdomega, dLdF_uniform, st)),
+                   (adjoint_impl<27, StBF16>(a32, partials, nblk, dLdomega, dLdF_uniform, st)))
+  }
+  CMLBM_DISPATCH(prec, (adjoint_impl<15, StF64>(a64, partials, nblk, dLdomega, dLdF_uniform, st)),
+                 (adjoint_impl<15, StF32>(a32, partials, nblk, dLdomega, dLdF_uniform, st)),
+                 (adjoint_impl<15, StF16>(a32, partials, nblk, dLdomega, dLdF_uniform, st)),
+                 (adjoint_impl<15, StBF16>(a32, partials, nblk, dLdomega, dLdF_uniform, st)))
 }
 
 #undef CMLBM_DISPATCH
@@ -908,10 +1062,10 @@ hipError_t ke_seed_impl(const Geom& g, const void* fpre, const uint8_t* mask, co
   if (!f.field) hipLaunchKernelGGL(k_reduce_rows, dim3(3), dim3(kBlock), 0, st, partials, nblk, 3, dLdF, 1);
   return hipGetLastError();
 }
-template <typename R>
+template <int Q, typename R>
 hipError_t init_adj_impl(const Geom& g, const void* u0, const void* lam0, const uint8_t* mask, const ForceArgs<R>& f,
                          double* dLdF, double* partials, int nblk, hipStream_t st) {
-  hipLaunchKernelGGL((k_init_adjoint27<R>), dim3(nblk), dim3(kBlock), 0, st, g, static_cast<const R*>(u0),
+  hipLaunchKernelGGL((k_init_adjoint<Q, R>), dim3(nblk), dim3(kBlock), 0, st, g, static_cast<const R*>(u0),
                      static_cast<const R*>(lam0), mask, f, dLdF, partials);
   if (!f.field) hipLaunchKernelGGL(k_reduce_rows, dim3(3), dim3(kBlock), 0, st, partials, nblk, 3, dLdF, 1);
   return hipGetLastError();
@@ -938,11 +1092,14 @@ hipError_t launch_ke_seed(int q, int prec, const Geom& g, const void* fpre, cons
                  : ke_seed_impl<15>(g, fpre, mask, f32, scale, lam, dLdF, partials, nblk, st);
 }
 
-hipError_t launch_init_adjoint(int prec, const Geom& g, const void* u0, const void* lam0, const uint8_t* mask,
-                               const ForceArgs<double>& f64, const ForceArgs<float>& f32, double* dLdF,
-                               double* partials, int nblk, hipStream_t st) {
-  if (prec == 0) return init_adj_impl<double>(g, u0, lam0, mask, f64, dLdF, partials, nblk, st);
-  return init_adj_impl<float>(g, u0, lam0, mask, f32, dLdF, partials, nblk, st);
+hipError_t launch_init_adjoint(int q, int prec, const Geom& g, const void* u0, const void* lam0,
+                               const uint8_t* mask, const ForceArgs<double>& f64, const ForceArgs<float>& f32,
+                               double* dLdF, double* partials, int nblk, hipStream_t st) {
+  if (prec == 0)
+    return q == 27 ? init_adj_impl<27, double>(g, u0, lam0, mask, f64, dLdF, partials, nblk, st)
+                   : init_adj_impl<15, double>(g, u0, lam0, mask, f64, dLdF, partials, nblk, st);
+  return q == 27 ? init_adj_impl<27, float>(g, u0, lam0, mask, f32, dLdF, partials, nblk, st)
+                 : init_adj_impl<15, float>(g, u0, lam0, mask, f32, dLdF, partials, nblk, st);
 }
 
 

@@ -32,6 +32,12 @@ struct StepArgs {
   const uint8_t* mask;
   ForceArgs<R> force;
   Rates<R> rates;
+  // Optional FP64 totals of the input state, fused into the step: per-block
+  // partials [step_blocks(g)][4], a second-stage buffer [kReduceChunks][4] and
+  // the device output [4].  All null for a plain step.
+  double* partials;
+  double* stage;
+  double* totals;
 };
 
 template <typename R>
@@ -67,7 +73,7 @@ hipError_t launch_totals(int q, int prec, const AuxArgs<double>& a64, const AuxA
                          int nblk, double* out4, hipStream_t st);
 hipError_t launch_init(int q, int prec, const Geom& g, const void* rho0, const void* u0, const ForceArgs<double>& f64,
                        const ForceArgs<float>& f32, const uint8_t* mask, void* fpre, void* fpost, hipStream_t st);
-hipError_t launch_adjoint(int prec, const AdjArgs<double>& a64, const AdjArgs<float>& a32, double* partials,
+hipError_t launch_adjoint(int q, int prec, const AdjArgs<double>& a64, const AdjArgs<float>& a32, double* partials,
                           int nblk, double* dLdomega, double* dLdF_uniform, hipStream_t st);
 
 hipError_t launch_ke_sum(int q, int prec, const Geom& g, const void* fpre, const uint8_t* mask,
@@ -76,9 +82,9 @@ hipError_t launch_ke_sum(int q, int prec, const Geom& g, const void* fpre, const
 hipError_t launch_ke_seed(int q, int prec, const Geom& g, const void* fpre, const uint8_t* mask,
                           const ForceArgs<double>& f64, const ForceArgs<float>& f32, double scale, void* lam,
                           double* dLdF, double* partials, int nblk, hipStream_t st);
-hipError_t launch_init_adjoint(int prec, const Geom& g, const void* u0, const void* lam0, const uint8_t* mask,
-                               const ForceArgs<double>& f64, const ForceArgs<float>& f32, double* dLdF,
-                               double* partials, int nblk, hipStream_t st);
+hipError_t launch_init_adjoint(int q, int prec, const Geom& g, const void* u0, const void* lam0,
+                               const uint8_t* mask, const ForceArgs<double>& f64, const ForceArgs<float>& f32,
+                               double* dLdF, double* partials, int nblk, hipStream_t st);
 
 // Blocks of the grid-stride adjoint launch (each thread visits at most 8 nodes).
 inline int adjoint_blocks(const Geom& g) {
@@ -90,5 +96,9 @@ inline int adjoint_blocks(const Geom& g) {
 }
 
 constexpr int kTotalsBlocks = 2048;
+constexpr int kReduceChunks = 256;
+
+// Blocks of one step launch (one block per CMLBM_STEP_BLOCK-wide row segment).
+uint64_t step_blocks(const Geom& g);
 
 }  // namespace cmlbm

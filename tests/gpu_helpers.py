@@ -16,12 +16,14 @@ def shear_rates(q, shear, others=1.0):
     return [shear] * 5 + [others] * (q - 9)
 
 
-def gpu_setup(q, shape, precision, omega, F=None, solid=None):
+def gpu_setup(q, shape, precision, omega, F=None, solid=None, per_mass=False):
     """Create a Sim; F is None, a 3-vector or a (3, nz, ny, nx) array."""
     cm = lib()
     nz, ny, nx = shape
     sim = cm.Sim(q, nx, ny, nz, precision)
     sim.set_rates(omega)
+    if per_mass:
+        sim.set_attractor_per_mass(True)
     if F is not None:
         F = np.asarray(F, dtype=float)
         if F.ndim == 1:
@@ -46,13 +48,13 @@ def gpu_pre(sim, f_post):
     return sim.gather(f_post).double().cpu().numpy()
 
 
-def oracle_run(q, rho0, u0, F, omega, nsteps, solid=None):
+def oracle_run(q, rho0, u0, F, omega, nsteps, solid=None, per_mass=False):
     lat = LATTICES[q]
     Fo = np.zeros(3) if F is None else np.asarray(F, dtype=float)
     f = lbm.initial_state(lat, rho0, u0, Fo, solid)
     states = [f]
     for _ in range(nsteps):
-        f = lbm.step(lat, f, Fo, omega, solid)
+        f = lbm.step(lat, f, Fo, omega, solid, per_mass)
         states.append(f)
     return states
 

@@ -1,4 +1,4 @@
-"""GPU parity of the D3Q27 adjoint (through the C ABI) against derivatives of the
+"""GPU parity of the adjoint (D3Q27 and D3Q15, through the C ABI) against derivatives of the
 FP64 oracle taken by the complex step (exact to rounding: every operation of
 the step is analytic).
 
@@ -17,7 +17,7 @@ import torch
 import lbm_inputs as inp
 from gpu_helpers import gpu_setup, shear_rates
 from oracle import lbm
-from oracle.lattice import D3Q27
+from oracle.lattice import D3Q27, LATTICES
 
 pytestmark = pytest.mark.gpu
 
@@ -32,27 +32,30 @@ def _walls(shape):
     return solid
 
 
-@pytest.mark.parametrize("force_kind", ["field", "uniform"])
-@pytest.mark.parametrize("masked", [False, True])
-def test_single_adjoint_step(force_kind, masked):
-    print(f"case adjoint-step {force_kind} masked={masked}", flush=True)
+@pytest.mark.parametrize("q,force_kind,masked,per_mass", [
+    (27, "field", False, False), (27, "uniform", False, False), (27, "field", True, False),
+    (27, "uniform", True, False), (27, "field", True, True),
+    (15, "field", False, False), (15, "uniform", True, False), (15, "field", True, True)])
+def test_single_adjoint_step(q, force_kind, masked, per_mass):
+    print(f"case adjoint-step q{q} {force_kind} masked={masked} per_mass={per_mass}", flush=True)
+    lat = LATTICES[q]
     shape = (5, 6, 67)
     rng = np.random.default_rng(21)
-    om = list(rng.uniform(0.7, 1.9, 23))
+    om = list(rng.uniform(0.7, 1.9, q - 4))
     F = inp.gaussian_force(shape, 1e-4, 4) if force_kind == "field" else np.array([2e-4, -1e-4, 3e-5])
     solid = _walls(shape) if masked else None
     fluid = np.ones(shape, bool) if solid is None else ~solid
-    sim = gpu_setup(27, shape, F64, om, F, solid)
+    sim = gpu_setup(q, shape, F64, om, F, solid, per_mass)
     rho0 = 1 + 0.01 * rng.standard_normal(shape)
     u0 = 0.05 * rng.uniform(-1, 1, (3,) + shape)
     x, _ = sim.init_equilibrium(torch.from_numpy(rho0).cuda(), torch.from_numpy(u0).cuda())
     x = sim.run(x, sim.populations(), 2)
     f_pre = sim.gather(x).cpu().numpy()
-    mu = rng.standard_normal((27,) + shape)
+    mu = rng.standard_normal((q,) + shape)
     mu[:, ~fluid] = 0.0
-    lam = torch.zeros((27,) + shape, dtype=torch.float64, device="cuda")
+    lam = torch.zeros((q,) + shape, dtype=torch.float64, device="cuda")
     dLdF = torch.zeros(F.shape, dtype=torch.float64, device="cuda")
-    dLdw = torch.zeros(23, dtype=torch.float64, device="cuda")
+    dLdw = torch.zeros(q - 4, dtype=torch.float64, device="cuda")
     sim.adjoint_step(x, torch.from_numpy(mu).cuda(), lam, dLdF, dLdw)
     lam = lam.cpu().numpy()
     lam[:, ~fluid] = 0.0
@@ -60,7 +63,7 @@ def test_single_adjoint_step(force_kind, masked):
     dLdw = dLdw.cpu().numpy()
 
     def L(f, Fv, w):
-        return np.sum(mu * lbm.step(D3Q27, f, Fv, w, solid))
+        return np.sum(mu * lbm.step(lat, f, Fv, w, solid, per_mass))
 
     for k in range(3):
         v = rng.standard_normal(f_pre.shape)
@@ -72,50 +75,56 @@ def test_single_adjoint_step(force_kind, masked):
             vF[:, ~fluid] = 0.0
         ref = L(f_pre.astype(complex), F + 1j * H * vF, np.array(om, dtype=complex)).imag / H
         assert abs(np.sum(dLdF * vF) - ref) <= 1e-9 * abs(ref) + 1e-14, (k, np.sum(dLdF * vF), ref)
-    for b in range(23):
+    for b in range(q - 4):
         w = np.array(om, dtype=complex)
         w[b] += 1j * H
         ref = L(f_pre.astype(complex), F.astype(complex), w).imag / H
         assert abs(dLdw[b] - ref) <= 1e-9 * abs(ref) + 1e-13, (b, dLdw[b], ref)
 
 
-def _oracle_loss(rho0, u0, F, om, nsteps, solid):
-    f = lbm.initial_state(D3Q27, rho0, u0, F, solid)
-    f = lbm.run(D3Q27, f, F, om, nsteps, solid)
-    return lbm.kinetic_energy(D3Q27, f, F, solid)
+def _oracle_loss(rho0, u0, F, om, nsteps, solid, per_mass=False, q=27):
+    lat = LATTICES[q]
+    f = lbm.initial_state(lat, rho0, u0, F, solid)
+    f = lbm.run(lat, f, F, om, nsteps, solid, per_mass=per_mass)
+    return lbm.kinetic_energy(lat, f, F, solid)
 
 
-@pytest.mark.parametrize("schedule", [{"every": 2}, {"snapshots": 2}, {"snapshots": 0}])
-@pytest.mark.parametrize("masked", [False, True])
-def test_whole_run_gradient_fp64(schedule, masked):
+RUN_CASES = [({"every": 2}, False, False, 27), ({"snapshots": 2}, False, False, 27),
+             ({"snapshots": 0}, False, False, 27), ({"every": 2}, True, False, 27),
+             ({"snapshots": 2}, True, False, 27), ({"snapshots": 0}, True, False, 27),
+             ({"snapshots": 2}, True, True, 27), ({"every": 2}, True, False, 15), ({"snapshots": 2}, False, True, 15)]
+
+
+@pytest.mark.parametrize("schedule,masked,per_mass,q", RUN_CASES)
+def test_whole_run_gradient_fp64(schedule, masked, per_mass, q):
     from paper_1202_6081_amd import autograd as ag
-    print(f"case run-grad {schedule} masked={masked}", flush=True)
+    print(f"case run-grad q{q} {schedule} masked={masked} per_mass={per_mass}", flush=True)
     shape = (4, 5, 66)
     nsteps = 6
     rng = np.random.default_rng(31)
-    om = np.array(rng.uniform(0.8, 1.9, 23))
+    om = np.array(rng.uniform(0.8, 1.9, q - 4))
     F = inp.gaussian_force(shape, 1e-4, 8)
     solid = _walls(shape) if masked else None
     fluid = np.ones(shape, bool) if solid is None else ~solid
     rho0 = 1 + 0.01 * rng.standard_normal(shape)
     u0 = 0.05 * rng.uniform(-1, 1, (3,) + shape)
-    sim = gpu_setup(27, shape, F64, list(om), None, solid)
+    sim = gpu_setup(q, shape, F64, list(om), None, solid, per_mass)
     Ft = torch.from_numpy(F).cuda().requires_grad_(True)
     wt = torch.from_numpy(om.copy()).requires_grad_(True)
     out = ag.run(sim, torch.from_numpy(rho0).cuda(), torch.from_numpy(u0).cuda(), Ft, wt, nsteps, **schedule)
     loss = ag.kinetic_energy(sim, out, Ft, n_fluid=int(fluid.sum()))
     loss.backward()
-    ref_loss = _oracle_loss(rho0, u0, F, om, nsteps, solid)
+    ref_loss = _oracle_loss(rho0, u0, F, om, nsteps, solid, per_mass, q)
     assert abs(float(loss) - ref_loss) <= 1e-12 * abs(ref_loss)
     gF = Ft.grad.cpu().numpy()
     gw = wt.grad.numpy()
     for k in range(3):
         v = rng.standard_normal(F.shape)
         v[:, ~fluid] = 0.0
-        ref = _oracle_loss(rho0, u0, F + 1j * H * v, om.astype(complex), nsteps, solid).imag / H
+        ref = _oracle_loss(rho0, u0, F + 1j * H * v, om.astype(complex), nsteps, solid, per_mass, q).imag / H
         assert abs(np.sum(gF * v) - ref) <= 1e-9 * abs(ref), (k, np.sum(gF * v), ref)
-    for vw in (np.r_[np.ones(5), np.zeros(18)], rng.standard_normal(23)):
-        ref = _oracle_loss(rho0, u0, F.astype(complex), om + 1j * H * vw, nsteps, solid).imag / H
+    for vw in (np.r_[np.ones(5), np.zeros(q - 9)], rng.standard_normal(q - 4)):
+        ref = _oracle_loss(rho0, u0, F.astype(complex), om + 1j * H * vw, nsteps, solid, per_mass, q).imag / H
         assert abs(np.sum(gw * vw) - ref) <= 1e-9 * abs(ref), (np.sum(gw * vw), ref)
 
 

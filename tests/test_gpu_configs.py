@@ -1,0 +1,120 @@
+"""The measurement configurations as GPU parity cases.
+
+* 32^3 Taylor-Green, FP64, 100 steps: every step's FP64 totals and mean kinetic
+  energy, and the final pre-collision populations, against the FP64 oracle.
+* 256^3 random-phase decaying field, 1000 steps, D3Q27 and D3Q15: FP32 and the
+  two 16-bit deviation storages against the FP64 GPU run (itself parity-green
+  with the oracle at 1e-12): kinetic energy every 10 steps, final velocity,
+  FP64 mass drift.
+"""
+import numpy as np
+import pytest
+import torch
+
+import lbm_inputs as inp
+from gpu_helpers import gpu_initial, gpu_setup, shear_rates, velocity_l2
+from oracle import lbm
+from oracle.lattice import LATTICES
+
+pytestmark = pytest.mark.gpu
+
+F64, F32, F16, BF16 = 0, 1, 2, 3
+
+
+@pytest.mark.timeout(900)
+def test_taylor_green_32_fp64_100_steps():
+    # k0 = 2 pi / 32, u0 = 0.02, rho = 1, F = (1e-6, 0, 0), shear 1.6, others 1.
+    print("case tg32 f64 100 steps", flush=True)
+    n, steps, q = 32, 100, 27
+    lat = LATTICES[q]
+    omega = shear_rates(q, 1.6)
+    F = np.array([1e-6, 0.0, 0.0])
+    u0 = inp.taylor_green(n, 0.02)
+    rho0 = np.ones((n, n, n))
+    sim = gpu_setup(q, (n, n, n), F64, omega, F)
+    f_post, pre = gpu_initial(sim, rho0, u0)
+    other = sim.populations()
+    tot_g, ke_g = [], []
+    for _ in range(steps):
+        sim.step(f_post, other)
+        f_post, other = other, f_post
+        tot_g.append(sim.totals(f_post))
+        sim.gather(f_post, out=pre)
+        ke_g.append(sim.kinetic_energy_sum(pre) / n**3)
+    f_gpu = pre.cpu().numpy()
+    tot_o, ke_o = [], []
+
+    def record(_, f):
+        tot_o.append(lbm.totals(lat, f, F))
+        ke_o.append(lbm.kinetic_energy(lat, f, F))
+
+    f0 = lbm.initial_state(lat, rho0, u0, F)
+    f_ora = lbm.run(lat, f0, F, omega, steps, callback=record)
+    tot_g, tot_o = np.array(tot_g), np.array(tot_o)
+    # FP64 totals of the pre-collision state: mass, and x-momentum growing by
+    # n^3 F_x per step
+    # (bounds relative to n^3 and to the momentum scale n^3 max|u0|: the net
+    # momentum itself is close to zero)
+    assert np.abs(tot_g[:, 0] - tot_o[:, 0]).max() <= 1e-12 * n**3
+    assert np.abs(tot_g[:, 1:] - tot_o[:, 1:]).max() <= 1e-12 * n**3 * np.abs(u0).max()
+    assert np.allclose(np.diff(tot_o[:, 1]), F[0] * n**3, rtol=1e-9)
+    assert np.abs(np.array(ke_g) - np.array(ke_o)).max() <= 1e-12 * max(ke_o)
+    err = np.abs(f_gpu - f_ora).max() / np.abs(f_ora).max()
+    print(f"tg32 fp64: population rel err {err:.3e}; KE(100)/KE(0) {ke_o[-1] / ke_o[0]:.6f}", flush=True)
+    assert err <= 1e-12
+
+
+def _decay_run(q, prec, u0, steps, every, shear):
+    n = u0.shape[-1]
+    sim = gpu_setup(q, (n, n, n), prec, shear_rates(q, shear))
+    f_post, pre = gpu_initial(sim, np.ones((n, n, n)), u0)
+    m0 = sim.totals(f_post)[0]
+    other = sim.populations()
+    ke = []
+    for s in range(1, steps + 1):
+        sim.step(f_post, other)
+        f_post, other = other, f_post
+        if s % every == 0:
+            sim.gather(f_post, out=pre)
+            ke.append(sim.kinetic_energy_sum(pre) / n**3)
+    drift = (sim.totals(f_post)[0] - m0) / m0
+    _, u = sim.macroscopic(f_post)
+    u = u.double().cpu().numpy()
+    del f_post, other, pre, sim
+    torch.cuda.empty_cache()
+    return np.array(ke), u, drift
+
+
+# bounds on (max relative KE error over the run, final velocity rel L2, |mass
+# drift|), about three times the larger of the two lattices' measurements
+# (D3Q27 / D3Q15: FP32 3.1e-7 / 1.5e-6, 1.5e-6 / 1.5e-6, 1.7e-8 / 6.7e-9;
+# FP16 2.5e-4 / 5.1e-4, 3.3e-4 / 4.7e-4, 3.1e-5 / 1.8e-5; BF16 8.5e-3 /
+# 1.7e-3, 3.7e-2 / 4.1e-2, 4.8e-6 / 2.2e-4)
+STORAGE_BOUNDS = {F32: (5e-6, 5e-6, 1e-7), F16: (2e-3, 2e-3, 1e-4), BF16: (3e-2, 1.5e-1, 7e-4)}
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("q,shear", [(27, 1.9), (15, 1.6)])
+def test_storage_precision_kinetic_energy_256(q, shear):
+    # 256^3 periodic, F = 0, rho = 1, solenoidal random-phase velocity (shells
+    # 1..8, E ~ s^-5/3, per-component rms 0.03, max |u| 0.12, seed 7), shear
+    # rate as given, others 1, 1000 steps, kinetic energy every 10 steps.
+    # D3Q15 runs at shear 1.6: at 1.9 this field excites a growing mode of the
+    # D3Q15 scheme (any seed grows ~e^(0.028 t); FP32 rounding reaches O(1)
+    # near step 575), so the comparison would measure the instability, not
+    # the storage.
+    print(f"case decay256 q{q} shear {shear}", flush=True)
+    n, steps, every = 256, 1000, 10
+    u0 = inp.random_spectrum_velocity(n, seed=7)
+    ke64, u64, drift64 = _decay_run(q, F64, u0, steps, every, shear)
+    assert abs(drift64) <= 1e-13
+    assert ke64[-1] < ke64[0]
+    results = {}
+    for prec in (F32, F16, BF16):
+        ke, u, drift = _decay_run(q, prec, u0, steps, every, shear)
+        results[prec] = (float(np.abs(ke / ke64 - 1).max()), velocity_l2(u, u64), abs(drift))
+        print(f"decay256 q{q} p{prec}: KE max rel err {results[prec][0]:.3e}, final u rel L2 "
+              f"{results[prec][1]:.3e}, mass drift {drift:.3e} (FP64 {drift64:.1e}); "
+              f"KE(1000)/KE(0) {ke64[-1] / ke64[0]:.4f}", flush=True)
+    for prec, got in results.items():
+        assert all(v <= b for v, b in zip(got, STORAGE_BOUNDS[prec])), (prec, got, STORAGE_BOUNDS[prec])

@@ -64,16 +64,22 @@ CASES = [
     (27, F64, (2, 3, 1), "field", None, 2),
     (15, F64, (1, 1, 5), "field", None, 2),
     (27, F32, (3, 1, 129), None, None, 2),
+    # per-unit-mass factorized attractors (rho varies by ~1% here)
+    (27, F64, (6, 5, 67), "field", "walls", 3, True),
+    (15, F64, (5, 6, 70), "uniform", "walls", 3, True),
+    (27, F32, (5, 6, 70), "field", None, 3, True),
 ]
 
 
 def _ids(c):
-    return f"q{c[0]}-p{c[1]}-{'x'.join(map(str, c[2]))}-{c[3]}-{c[4]}-n{c[5]}"
+    pm = "-per_mass" if len(c) > 6 and c[6] else ""
+    return f"q{c[0]}-p{c[1]}-{'x'.join(map(str, c[2]))}-{c[3]}-{c[4]}-n{c[5]}{pm}"
 
 
 @pytest.mark.parametrize("case", CASES, ids=[_ids(c) for c in CASES])
 def test_forward_matches_oracle(case):
-    q, prec, shape, fkind, mkind, steps = case
+    q, prec, shape, fkind, mkind, steps = case[:6]
+    per_mass = len(case) > 6 and case[6]
     print(f"case {_ids(case)}", flush=True)
     rng = np.random.default_rng(7)
     omega = list(rng.uniform(0.7, 1.9, q - 4))
@@ -81,9 +87,9 @@ def test_forward_matches_oracle(case):
     solid = _mask(mkind, shape)
     rho0, u0 = _fields(shape, 5)
     fluid = None if solid is None else ~solid
-    sim = gpu_setup(q, shape, prec, omega, F, solid)
+    sim = gpu_setup(q, shape, prec, omega, F, solid, per_mass)
     f_post, f_pre0 = gpu_initial(sim, rho0, u0)
-    states = oracle_run(q, rho0, u0, F, omega, steps, solid)
+    states = oracle_run(q, rho0, u0, F, omega, steps, solid, per_mass)
     tol = 1e-12 if prec == F64 else None
     # initial pre-collision state, from the kernel that builds it and from the
     # post-collision buffer through the pull
@@ -176,6 +182,37 @@ def test_fp32_taylor_green_velocity_l2():
     assert velocity_l2(u_g.double().cpu().numpy(), u_o) < 2e-5
 
 
+@pytest.mark.parametrize("q,prec,shape,force,mask", [
+    (27, F32, (6, 5, 300), "field", "walls"),
+    (27, F64, (5, 6, 70), "uniform", None),
+    (15, F32, (6, 5, 67), "field", None),
+    (15, BF16, (5, 6, 70), "uniform", "walls"),
+    (27, F16, (3, 1, 129), None, None),
+])
+def test_step_totals_fused(q, prec, shape, force, mask):
+    # The fused FP64 totals of a step's input state equal cmlbm_totals of the
+    # same buffer (same populations, different summation order), and the step
+    # output equals the plain step's bit for bit.
+    print(f"case step_totals q{q} p{prec} {shape}", flush=True)
+    rho0, u0 = _fields(shape, 17)
+    F = _force(force, shape, 5)
+    solid = _mask(mask, shape)
+    sim = gpu_setup(q, shape, prec, shear_rates(q, 1.7), F, solid)
+    f_post, _ = gpu_initial(sim, rho0, u0)
+    f_post = sim.run(f_post, sim.populations(), 2)
+    want = np.array(sim.totals(f_post))
+    out_a, out_b = sim.populations().zero_(), sim.populations().zero_()   # solid nodes are not written
+    tot = torch.zeros(4, dtype=torch.float64, device="cuda")
+    sim.step(f_post, out_a, totals=tot)
+    sim.step(f_post, out_b)
+    got = tot.cpu().numpy()
+    n = int(np.prod(shape))
+    assert np.abs(got - want).max() <= 1e-13 * n, (got, want)
+    assert torch.equal(out_a.view(torch.uint8), out_b.view(torch.uint8))
+    with pytest.raises(lib().CmlbmError):
+        sim.step(f_post, out_a, totals=torch.zeros(4, dtype=torch.float32, device="cuda"))
+
+
 def test_run_ping_pong_and_errors():
     cm = lib()
     sim = gpu_setup(27, (4, 4, 64), F32, shear_rates(27, 1.5))
@@ -189,10 +226,10 @@ def test_run_ping_pong_and_errors():
         sim.set_rates([2.5] * 23)                      # outside (0, 2)
     with pytest.raises(cm.CmlbmError):
         sim.set_rates([1.0] * 11)                      # wrong count
-    s15 = cm.Sim(15, 8, 8, 8, F32)
     with pytest.raises(cm.CmlbmError) as e:
-        s15.adjoint_step(f_post, f_post, b, b, b)
-    assert e.value.code == -2
+        sim.adjoint_step(f_post, f_post, b, b, b)             # aliasing is rejected
+    assert e.value.code == -1
+    assert cm.load_library().cmlbm_set_attractor_per_mass(sim.h, 2) == -1   # only 0 or 1
 
 
 @pytest.mark.parametrize("q", [27, 15])

@@ -161,3 +161,59 @@ def test_unit_rates_reach_attractors(lat):
     higher = {17: 3 * (rho / 3) ** 2, 18: 0, 19: 0, 26: (rho / 3) ** 3} if lat.Q == 27 else {14: (rho / 3) ** 2}
     for b in range(10, lat.Q):
         assert cm[b] == higher.get(b, 0), b
+
+
+# ----------------------------------------------------------------------------
+# Per-unit-mass factorized attractors (the alternative reading of Sec. 3)
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("lat", [D3Q27, D3Q15], ids=str)
+def test_per_mass_equilibrium_fixed_point_any_density(lat):
+    # rho (kxx/rho)(kyy/rho) equals the Maxwellian c_s^4 rho at equilibrium for
+    # every rho, so f^eq is a fixed point at any density; the literal form
+    # moves it when rho != 1.
+    rng = np.random.default_rng(52)
+    u = np.array([_rat(rng, -0.3, 0.3, 37) for _ in range(3)], dtype=object)
+    rho = Fraction(7, 5)
+    feq = collision.equilibrium(lat, np.array(rho, dtype=object), u)
+    zero = np.array([Fraction(0)] * 3, dtype=object)
+    om = [_rat(rng, 0.1, 1.95, 41) for _ in range(lat.Q - 4)]
+    assert list(collision.collide(lat, feq, zero, om, per_mass=True)) == list(feq)
+    assert list(collision.collide(lat, feq, zero, om)) != list(feq)
+
+
+@pytest.mark.parametrize("lat", [D3Q27, D3Q15], ids=str)
+def test_per_mass_equals_literal_at_unit_density(lat):
+    rng = np.random.default_rng(53)
+    f, F, om = _random_node(lat, rng)
+    f = f / f.sum()                                         # rho = 1 exactly
+    assert f.sum() == 1
+    assert list(collision.collide(lat, f, F, om, per_mass=True)) == list(collision.collide(lat, f, F, om))
+
+
+@pytest.mark.parametrize("lat", [D3Q27, D3Q15], ids=str)
+def test_per_mass_conservation_and_frame_independence(lat):
+    rng = np.random.default_rng(54)
+    f, F, om = _random_node(lat, rng)
+    if lat.Q == 15:
+        F = np.array([Fraction(0)] * 3, dtype=object)
+    post = collision.collide(lat, f, F, om, per_mass=True)
+    E = lat.E.astype(object)
+    assert post.sum() == f.sum()
+    assert list(post @ E - f @ E) == list(F)
+    rho, u = collision.macroscopic(lat, f, F)
+    U = np.array([Fraction(2, 17), Fraction(-1, 13), Fraction(1, 11)], dtype=object)
+    cm = collision.central_moment_matrix(lat, u) @ f
+    f_shift = collision._solve(collision.central_moment_matrix(lat, u + U), cm)
+    post_shift = collision.collide(lat, f_shift, F, om, per_mass=True)
+    assert list(_central(lat, post, u)) == list(_central(lat, post_shift, u + U))
+
+
+def test_per_mass_attractor_value():
+    # combination 17 = xxyy + xxzz + yyzz relaxes to 3 rho (1/3)^2 = rho/3 at
+    # equilibrium second moments, for any rho.
+    u = np.array([Fraction(1, 10), Fraction(0), Fraction(-1, 20)], dtype=object)
+    rho = Fraction(6, 5)
+    feq = collision.equilibrium(D3Q27, np.array(rho, dtype=object), u)
+    zero = np.array([Fraction(0)] * 3, dtype=object)
+    post = collision.collide(D3Q27, feq, zero, [Fraction(1)] * 23, per_mass=True)
+    assert _central(D3Q27, post, u)[17] == rho / 3

@@ -44,6 +44,21 @@ def duct_startup(yc, zc, a, F, nu, t, nterms=80):
     return u
 
 
+def womersley(z, a, Fm, Om, nu, t, nterms=400):
+    """u(z, t) between plates at z = +-a for du/dt = nu u'' + F_m cos(Om t),
+    u(z, 0) = 0: each cosine mode k (odd) with lambda = (k pi / 2a)^2 obeys
+    b' = -nu lambda b + F_m cos(Om t), b(0) = 0."""
+    u = np.zeros_like(z, dtype=float)
+    for n in range(nterms):
+        k = 2 * n + 1
+        lam = (k * math.pi / (2 * a)) ** 2
+        c = 4 * (-1) ** n / (k * math.pi)
+        s = nu * lam
+        b = Fm * (s * math.cos(Om * t) + Om * math.sin(Om * t) - s * math.exp(-s * t)) / (s * s + Om * Om)
+        u = u + c * b * np.cos(k * math.pi * z / (2 * a))
+    return u
+
+
 def duct_steady_paper(y, z, a, F, nu, rho=1.0, nterms=200):
     """Eq. ductFourier, as printed."""
     s = 0.0
@@ -78,6 +93,19 @@ def test_womersley_numbers():
     Om = 2 * math.pi / 10000
     for omega, Wo in [(1.724, 3.3), (1.923, 6.6)]:
         assert abs(math.sqrt(Om / nu_of(omega)) * a - Wo) < 0.01
+
+
+def test_womersley_series_limits():
+    # Om -> 0 reduces to the constant-force start-up; late times to the
+    # periodic profile, whose amplitude at the centre tends to F_m / Om for
+    # large Wo.
+    a, nu, F = 21.5, 0.02, 1e-5
+    z = np.linspace(-a, a, 9)
+    assert np.allclose(womersley(z, a, F, 1e-12, nu, 3000.0), channel_startup(z, a, F, nu, 3000.0), rtol=1e-6,
+                       atol=1e-12)
+    Om = 2 * math.pi / 50.0          # Wo = a sqrt(Om / nu) ~ 76
+    t = 400 * 50.0 + 12.5            # quarter period: cos = 0, sin = 1
+    assert abs(womersley(np.array([0.0]), a, F, Om, nu, t)[0] - F / Om) < 1e-3 * F / Om
 
 
 def test_duct_reynolds_number():
@@ -200,3 +228,30 @@ def test_streaming_periodic_shift():
     out = lbm.stream(lat, post)
     for a, (ex, ey, ez) in enumerate(lat.E):
         assert out[a, (1 + ez) % 4, (2 + ey) % 5, (3 + ex) % 6] == a + 1
+
+
+def _duct_crossflow(per_mass, steps, N=13, omega=1.923):
+    lat = D3Q15
+    shape = (N, N, 3)
+    solid = np.zeros(shape, dtype=bool)
+    solid[0] = solid[-1] = True
+    solid[:, 0] = solid[:, -1] = True
+    F = np.array([1e-6, 0.0, 0.0])
+    om = [omega] * 5 + [1.0] * (lat.Q - 9)
+    f = lbm.initial_state(lat, np.ones(shape), np.zeros((3,) + shape), F, solid)
+    f = lbm.run(lat, f, F, om, steps, solid, per_mass=per_mass)
+    _, u = lbm.macroscopic_fields(lat, f, F, solid)
+    return float(np.abs(u[1:]).max()), float(np.abs(u[0]).max())
+
+
+def test_d3q15_duct_literal_attractor_unstable_per_mass_stable():
+    # The paper's D3Q15 duct (Sec. 9) at its omega = 1.923, on a 3 x 13 x 13
+    # cross-section: with the literal factorized attractor (the printed form,
+    # the default here) a cross-flow mode grows ~20x per 200 steps from
+    # rounding level, so the steady Re 65.7 flow the paper reports cannot be
+    # reached; with the per-unit-mass form the cross-flow stays at the level
+    # the streamwise flow drives.
+    lit_cross, lit_ux = _duct_crossflow(False, 1000)
+    pm_cross, pm_ux = _duct_crossflow(True, 1000)
+    assert not (lit_cross < 1e-4)                   # grown (or overflowed)
+    assert pm_cross < 1e-6 and 1e-4 < pm_ux < 2e-3
