@@ -17,6 +17,9 @@
 //     moments to populations (the K g + S rows of Appendix G).
 #pragma once
 
+#include <type_traits>
+#include <utility>
+
 #include "collide_d3q27.hpp"   // Rates<R>
 #include "lattice.hpp"
 
@@ -51,6 +54,53 @@ CMLBM_HDC int k15_norm(int b) {
   return d;
 }
 
+// Compile-time tables: kB15.v[b][a] = K_b(e_a), kM15.v[m][a] = the monomial m
+// (order below) at e_a, kD15[b] = D_b.  Loops over them run through
+// static_for so that every entry is a literal constant in the generated code.
+struct Tab15 {
+  int v[15][15];
+};
+
+CMLBM_HDC Vel mono15(int m) {
+  constexpr Vel t[15] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1}, {2, 0, 0},
+                         {0, 2, 0}, {0, 0, 2}, {1, 2, 0}, {2, 1, 0}, {2, 0, 1}, {1, 1, 1}, {2, 2, 0}};
+  return t[m];
+}
+
+CMLBM_HDC int ipow(int v, int n) { return n == 0 ? 1 : (n == 1 ? v : v * v); }
+
+CMLBM_HDC Tab15 make_basis15() {
+  Tab15 t{};
+  for (int b = 0; b < 15; ++b)
+    for (int a = 0; a < 15; ++a) t.v[b][a] = k15_basis(b, kE15[a]);
+  return t;
+}
+
+CMLBM_HDC Tab15 make_mono15() {
+  Tab15 t{};
+  for (int m = 0; m < 15; ++m)
+    for (int a = 0; a < 15; ++a)
+      t.v[m][a] = ipow(kE15[a].x, mono15(m).x) * ipow(kE15[a].y, mono15(m).y) * ipow(kE15[a].z, mono15(m).z);
+  return t;
+}
+
+constexpr Tab15 kB15 = make_basis15();
+constexpr Tab15 kM15 = make_mono15();
+
+template <int I>
+using Ic = std::integral_constant<int, I>;
+
+template <class Fn, int... I>
+CMLBM_HD void static_for_impl(Fn&& fn, std::integer_sequence<int, I...>) {
+  (fn(Ic<I>{}), ...);
+}
+
+// fn(Ic<0>{}), ..., fn(Ic<N-1>{}): the index is a compile-time constant.
+template <int N, class Fn>
+CMLBM_HD void static_for(Fn&& fn) {
+  static_for_impl(fn, std::make_integer_sequence<int, N>{});
+}
+
 // Source S_a = sum_b K_b(e_a) m^s_b / D_b with the printed m^s (Appendix G).
 template <typename R>
 CMLBM_HD void source15(R Fx, R Fy, R Fz, R ux, R uy, R uz, R (&S)[15]) {
@@ -72,18 +122,18 @@ CMLBM_HD void source15(R Fx, R Fy, R Fz, R ux, R uy, R uz, R (&S)[15]) {
   ms[13] = Fx * uy * uz + Fy * ux * uz + Fz * ux * uy;
   ms[14] = R(20) * (Fx * ux * (R(3) * (uy2 + uz2) - R(4)) + Fy * uy * (R(3) * (ux2 + uz2) - R(4)) +
                     Fz * uz * (R(3) * (ux2 + uy2) - R(4)));
-#pragma unroll
-  for (int b = 0; b < 15; ++b) ms[b] *= R(1.0 / k15_norm(b));
-#pragma unroll
-  for (int a = 0; a < 15; ++a) {
+  static_for<15>([&](auto b) {
+    constexpr int d = k15_norm(decltype(b)::value);
+    ms[b] *= R(1.0 / d);
+  });
+  static_for<15>([&](auto a) {
     R acc = R(0);
-#pragma unroll
-    for (int b = 1; b < 15; ++b) {
-      const int k = k15_basis(b, kE15[a]);
-      if (k != 0) acc += R(k) * ms[b];
-    }
+    static_for<14>([&](auto b1) {
+      constexpr int k = kB15.v[decltype(b1)::value + 1][decltype(a)::value];
+      if constexpr (k != 0) acc += R(k) * ms[decltype(b1)::value + 1];
+    });
     S[a] = acc;
-  }
+  });
 }
 
 // Populations with the given central moments about u: rho; first order
@@ -239,28 +289,20 @@ CMLBM_HDC Groups15 groups15() {
     return {{{0, 3, 9}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, 1, {{1, 5}, {2, 6}, {4, 13}, {7, 12}}, 4};
 }
 
-// Exponents (x, y, z) of moment m.
-CMLBM_HDC Vel mono15(int m) {
-  constexpr Vel t[15] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1}, {2, 0, 0},
-                         {0, 2, 0}, {0, 0, 2}, {1, 2, 0}, {2, 1, 0}, {2, 0, 1}, {1, 1, 1}, {2, 2, 0}};
-  return t[m];
-}
-
-CMLBM_HDC int ipow(int v, int n) { return n == 0 ? 1 : (n == 1 ? v : v * v); }
-
 // Shift of moments m by u along axis AX (sg = -1: raw to central, +1: back).
 template <int AX, typename R>
 CMLBM_HD void shift15(R (&m)[15], R u, R sg) {
   constexpr Groups15 G = groups15<AX>();
   const R v = sg * u;
-#pragma unroll
-  for (int i = 0; i < G.nt; ++i) {
-    const int a = G.t[i][0], b = G.t[i][1], c = G.t[i][2];
+  static_for<G.nt>([&](auto i) {
+    constexpr int a = G.t[decltype(i)::value][0], b = G.t[decltype(i)::value][1], c = G.t[decltype(i)::value][2];
     m[c] = m[c] + v * (R(2) * m[b] + v * m[a]);
     m[b] = m[b] + v * m[a];
-  }
-#pragma unroll
-  for (int i = 0; i < G.np; ++i) m[G.p[i][1]] += v * m[G.p[i][0]];
+  });
+  static_for<G.np>([&](auto i) {
+    constexpr int a = G.p[decltype(i)::value][0], b = G.p[decltype(i)::value][1];
+    m[b] += v * m[a];
+  });
 }
 
 // Adjoint of shift15: m = its input, g = adjoint of its output (in place ->
@@ -270,54 +312,46 @@ CMLBM_HD void shift15_adj(const R (&m)[15], R u, R sg, R (&g)[15], R& gu) {
   constexpr Groups15 G = groups15<AX>();
   const R v = sg * u;
   R gv = R(0);
-#pragma unroll
-  for (int i = 0; i < G.nt; ++i) {
-    const int a = G.t[i][0], b = G.t[i][1], c = G.t[i][2];
+  static_for<G.nt>([&](auto i) {
+    constexpr int a = G.t[decltype(i)::value][0], b = G.t[decltype(i)::value][1], c = G.t[decltype(i)::value][2];
     const R g1 = g[b], g2 = g[c];
     gv += g1 * m[a] + g2 * R(2) * (m[b] + v * m[a]);
     g[a] += v * g1 + v * v * g2;
     g[b] = g1 + R(2) * v * g2;
-  }
-#pragma unroll
-  for (int i = 0; i < G.np; ++i) {
-    const int a = G.p[i][0], b = G.p[i][1];
+  });
+  static_for<G.np>([&](auto i) {
+    constexpr int a = G.p[decltype(i)::value][0], b = G.p[decltype(i)::value][1];
     gv += g[b] * m[a];
     g[a] += v * g[b];
-  }
+  });
   gu += sg * gv;
 }
 
 // Raw moments of h, and the transpose (adjoint) of that linear map.
 template <typename R>
 CMLBM_HD void raw15(const R (&h)[15], R (&r)[15]) {
-#pragma unroll
-  for (int m = 0; m < 15; ++m) {
-    const Vel e = mono15(m);
+  static_for<15>([&](auto m) {
     R acc = R(0);
-#pragma unroll
-    for (int a = 0; a < 15; ++a) {
-      const int k = ipow(kE15[a].x, e.x) * ipow(kE15[a].y, e.y) * ipow(kE15[a].z, e.z);
-      if (k == 1) acc += h[a];
-      if (k == -1) acc -= h[a];
-    }
+    static_for<15>([&](auto a) {
+      constexpr int k = kM15.v[decltype(m)::value][decltype(a)::value];
+      if constexpr (k == 1) acc += h[a];
+      if constexpr (k == -1) acc -= h[a];
+    });
     r[m] = acc;
-  }
+  });
 }
 
 template <typename R>
 CMLBM_HD void raw15_adj(const R (&gr)[15], R (&gh)[15]) {
-#pragma unroll
-  for (int a = 0; a < 15; ++a) {
+  static_for<15>([&](auto a) {
     R acc = R(0);
-#pragma unroll
-    for (int m = 0; m < 15; ++m) {
-      const Vel e = mono15(m);
-      const int k = ipow(kE15[a].x, e.x) * ipow(kE15[a].y, e.y) * ipow(kE15[a].z, e.z);
-      if (k == 1) acc += gr[m];
-      if (k == -1) acc -= gr[m];
-    }
+    static_for<15>([&](auto m) {
+      constexpr int k = kM15.v[decltype(m)::value][decltype(a)::value];
+      if constexpr (k == 1) acc += gr[m];
+      if constexpr (k == -1) acc -= gr[m];
+    });
     gh[a] = acc;
-  }
+  });
 }
 
 // Transpose of the raw-moment inversion at the end of populations15:
@@ -362,16 +396,16 @@ template <typename R>
 CMLBM_HD void source15_adj(R Fx, R Fy, R Fz, R ux, R uy, R uz, const R (&gS)[15], R& gFx, R& gFy, R& gFz,
                            R& gux, R& guy, R& guz) {
   R G[15];
-#pragma unroll
-  for (int b = 1; b < 15; ++b) {
+  static_for<14>([&](auto b1) {
+    constexpr int b = decltype(b1)::value + 1;
     R acc = R(0);
-#pragma unroll
-    for (int a = 0; a < 15; ++a) {
-      const int k = k15_basis(b, kE15[a]);
-      if (k != 0) acc += R(k) * gS[a];
-    }
-    G[b] = acc * R(1.0 / k15_norm(b));
-  }
+    static_for<15>([&](auto a) {
+      constexpr int k = kB15.v[b][decltype(a)::value];
+      if constexpr (k != 0) acc += R(k) * gS[a];
+    });
+    constexpr int d = k15_norm(b);
+    G[b] = acc * R(1.0 / d);
+  });
   const R ux2 = ux * ux, uy2 = uy * uy, uz2 = uz * uz;
   gFx += G[1];
   gFy += G[2];
@@ -420,14 +454,14 @@ CMLBM_HD void source15_adj(R Fx, R Fy, R Fz, R ux, R uy, R uz, const R (&gS)[15]
 // Adjoint of collide15.  f: pre-collision populations.  g: on entry the
 // adjoint of the post-collision populations, on exit the adjoint of f.  Adds
 // the force adjoint and gw[b] (adjoint of omega_b, b = 4..14).
-template <typename R, typename W>
+template <int PM = -1, typename R, typename W>
 CMLBM_HD void collide15_adj(const R (&f)[15], R Fx, R Fy, R Fz, const Rates<R>& p, R (&g)[15], R& gFx, R& gFy,
                             R& gFz, W& gw) {
+  const bool pm = PM < 0 ? p.per_mass != 0 : PM != 0;
   R rho, ux, uy, uz;
   moments0_15(f, Fx, Fy, Fz, rho, ux, uy, uz);
   R gux = R(0), guy = R(0), guz = R(0), grho = R(0);
-  const R sm = p.per_mass ? R(1) / rho : R(1);
-  const R dsm = p.per_mass ? -sm : R(0);
+  const R sm = pm ? R(1) / rho : R(1);
 
   // forward: central moments c of h = f + S
   R c[15];
@@ -502,7 +536,7 @@ CMLBM_HD void collide15_adj(const R (&f)[15], R Fx, R Fy, R Fz, const Rates<R>& 
     gc[14] = p.wc[14] * G;
     gw[14] += (A - c[14]) * G;
     const R gA = p.w[14] * G;
-    grho += dsm * A * gA;
+    if (pm) grho -= sm * A * gA;
     gtxx += gA * tyy * sm;
     gtyy += gA * txx * sm;
   }

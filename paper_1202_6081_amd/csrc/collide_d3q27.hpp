@@ -176,10 +176,11 @@ CMLBM_HD void moments0_27(const R (&m)[27], R Fx, R Fy, R Fz, R& rho, R& ux, R& 
   uz = (tz[2] - tz[0] + R(0.5) * Fz) * inv;
 }
 
-// Relax the central moments in m (cube layout) in place.  Returns the
-// post-collision second-order diagonal moments through kxx, kyy, kzz.
-template <typename R>
+// Relax the central moments in m (cube layout) in place.  PM: attractor form,
+// 0 literal, 1 per unit mass, -1 as p.per_mass says (run time).
+template <int PM = -1, typename R>
 CMLBM_HD void relax27(R (&m)[27], R rho, R Fx, R Fy, R Fz, const Rates<R>& p) {
+  const bool pm = PM < 0 ? p.per_mass != 0 : PM != 0;
   // conserved: density and first central moments F/2
   m[K3(0, 0, 0)] = rho;
   m[K3(1, 0, 0)] = R(0.5) * Fx;
@@ -221,7 +222,7 @@ CMLBM_HD void relax27(R (&m)[27], R rho, R Fx, R Fy, R Fz, const Rates<R>& p) {
   }
   m[K3(1, 1, 1)] *= p.wc[16];
   // fourth order, diagonal pairs (g17, g18, g19) toward the factorized attractors
-  const R sm = p.per_mass ? R(1) / rho : R(1);
+  const R sm = pm ? R(1) / rho : R(1);
   {
     const R axy = kxx * kyy * sm, axz = kxx * kzz * sm, ayz = kyy * kzz * sm;
     const R A = m[K3(2, 2, 0)], B = m[K3(2, 0, 2)], C = m[K3(0, 2, 2)];
@@ -293,9 +294,10 @@ CMLBM_HD void collide27(R (&m)[27], R Fx, R Fy, R Fz, const Rates<R>& p) {
 // entry the adjoint of the relaxed moments, on exit the adjoint of m.  Adds to
 // grho, gF*, gw[b] (adjoint of omega_b, b = 4..26; gw is an array or any
 // accumulator whose operator[] yields an R&).
-template <typename R, typename W>
+template <int PM = -1, typename R, typename W>
 CMLBM_HD void relax27_adj(const R (&m)[27], R rho, const Rates<R>& p, R (&g)[27], R& grho,
                                             R& gFx, R& gFy, R& gFz, W& gw) {
+  const bool pm = PM < 0 ? p.per_mass != 0 : PM != 0;
   // recompute the second-order post values and attractor inputs
   const R xx = m[K3(2, 0, 0)], yy = m[K3(0, 2, 0)], zz = m[K3(0, 0, 2)];
   const R D1 = xx - yy, D2 = xx + yy - R(2) * zz, T = xx + yy + zz;
@@ -305,8 +307,7 @@ CMLBM_HD void relax27_adj(const R (&m)[27], R rho, const Rates<R>& p, R (&g)[27]
   const R kzz = (t - d2) * R(1.0 / 3.0);
   R gkxx = R(0), gkyy = R(0), gkzz = R(0);
   // per-mass attractors: A = P sm^(k-1), dA/drho = -(k-1) A sm
-  const R sm = p.per_mass ? R(1) / rho : R(1);
-  const R dsm = p.per_mass ? -sm : R(0);
+  const R sm = pm ? R(1) / rho : R(1);
 
   // sixth order
   {
@@ -315,7 +316,7 @@ CMLBM_HD void relax27_adj(const R (&m)[27], R rho, const Rates<R>& p, R (&g)[27]
     const R P = kxx * kyy * kzz * s2;
     gw[26] += (P - m[K3(2, 2, 2)]) * G;
     const R gP = p.w[26] * G;
-    grho += R(2) * dsm * P * gP;
+    if (pm) grho -= R(2) * sm * P * gP;
     const R gPs = gP * s2;
     gkxx += gPs * kyy * kzz;
     gkyy += gPs * kxx * kzz;
@@ -352,7 +353,7 @@ CMLBM_HD void relax27_adj(const R (&m)[27], R rho, const Rates<R>& p, R (&g)[27]
     const R ga1 = p.w[17] * gq1, ga2 = p.w[18] * gq2, ga3 = p.w[19] * gq3;
     const R gQ1 = p.wc[17] * gq1, gQ2 = p.wc[18] * gq2, gQ3 = p.wc[19] * gq3;
     const R gaxy = ga1 + ga2 + ga3, gaxz = ga1 + ga2 - ga3, gayz = ga1 - R(2) * ga2;
-    grho += dsm * (axy * gaxy + axz * gaxz + ayz * gayz);
+    if (pm) grho -= sm * (axy * gaxy + axz * gaxz + ayz * gayz);
     gkxx += sm * (gaxy * kyy + gaxz * kzz);
     gkyy += sm * (gaxy * kxx + gayz * kzz);
     gkzz += sm * (gaxz * kxx + gayz * kyy);
@@ -409,7 +410,7 @@ CMLBM_HD void relax27_adj(const R (&m)[27], R rho, const Rates<R>& p, R (&g)[27]
 // scratch.  Adds the force and rate adjoints.  Only the central moments c are
 // kept: the input of each forward pass is recovered from c by the inverse
 // passes, which undo the forward ones exactly (up to rounding).
-template <typename R, typename W>
+template <int PM = -1, typename R, typename W>
 CMLBM_HD void collide27_adj(R (&f)[27], R Fx, R Fy, R Fz, const Rates<R>& p, R (&g)[27], R (&s)[27],
                                               R& gFx, R& gFy, R& gFz, W& gw) {
   R rho, ux, uy, uz;
@@ -422,7 +423,7 @@ CMLBM_HD void collide27_adj(R (&f)[27], R Fx, R Fy, R Fz, const Rates<R>& p, R (
   // relaxed moments, then replay the inverse passes to get each pass's input
 #pragma unroll
   for (int k = 0; k < 27; ++k) s[k] = cm[k];
-  relax27(s, rho, Fx, Fy, Fz, p);
+  relax27<PM>(s, rho, Fx, Fy, Fz, p);
   inv_pass<0>(s, ux);
   inv_pass<1>(s, uy);                        // s = input of the z inverse pass
   inv_pass_adj<2>(s, uz, g, guz);
@@ -431,7 +432,7 @@ CMLBM_HD void collide27_adj(R (&f)[27], R Fx, R Fy, R Fz, const Rates<R>& p, R (
   fwd_pass<0>(s, ux);                        // s = relaxed central moments
   inv_pass_adj<0>(s, ux, g, gux);
 
-  relax27_adj(cm, rho, p, g, grho, gFx, gFy, gFz, gw);
+  relax27_adj<PM>(cm, rho, p, g, grho, gFx, gFy, gFz, gw);
 
   // forward passes x, y, z in reverse order
 #pragma unroll

@@ -597,7 +597,9 @@ constexpr int adjoint_waves() {
   return sizeof(typename ST::R) == 8 ? 1 : 3;
 }
 
-template <int Q, class ST, bool MASK>
+// PM: attractor form compiled in (0 literal, 1 per unit mass); the host picks
+// the instance that matches the rates' per_mass flag.
+template <int Q, class ST, bool MASK, int PM>
 __global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(adjoint_waves<ST>()))) void k_adjoint(
     AdjArgs<typename ST::R> args, double* partials) {
   using R = typename ST::R;
@@ -663,9 +665,9 @@ __global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(adjoi
     R gFx = R(0), gFy = R(0), gFz = R(0);
     if constexpr (Q == 27) {
       R s[27];
-      collide27_adj(f, Fx, Fy, Fz, args.rates, gm, s, gFx, gFy, gFz, wacc);
+      collide27_adj<PM>(f, Fx, Fy, Fz, args.rates, gm, s, gFx, gFy, gFz, wacc);
     } else {
-      collide15_adj(f, Fx, Fy, Fz, args.rates, gm, gFx, gFy, gFz, wacc);
+      collide15_adj<PM>(f, Fx, Fy, Fz, args.rates, gm, gFx, gFy, gFz, wacc);
     }
 #pragma unroll
     for (int a = 0; a < Q; ++a) st32(args.lam + uint64_t(a) * g.N + uint64_t(row) * nx, x, gm[slot<Q>(a)]);
@@ -940,10 +942,18 @@ hipError_t init_impl(const Geom& g, const void* rho0, const void* u0, const Forc
 template <int Q, class ST>
 hipError_t adjoint_impl(const AdjArgs<typename ST::R>& a, double* partials, int nblk, double* dLdomega,
                         double* dLdF_uniform, hipStream_t st) {
-  if (a.mask)
-    hipLaunchKernelGGL((k_adjoint<Q, ST, true>), dim3(nblk), dim3(adjoint_block(a.g)), 0, st, a, partials);
-  else
-    hipLaunchKernelGGL((k_adjoint<Q, ST, false>), dim3(nblk), dim3(adjoint_block(a.g)), 0, st, a, partials);
+  const dim3 grid(nblk), block(adjoint_block(a.g));
+  if (a.rates.per_mass) {
+    if (a.mask)
+      hipLaunchKernelGGL((k_adjoint<Q, ST, true, 1>), grid, block, 0, st, a, partials);
+    else
+      hipLaunchKernelGGL((k_adjoint<Q, ST, false, 1>), grid, block, 0, st, a, partials);
+  } else {
+    if (a.mask)
+      hipLaunchKernelGGL((k_adjoint<Q, ST, true, 0>), grid, block, 0, st, a, partials);
+    else
+      hipLaunchKernelGGL((k_adjoint<Q, ST, false, 0>), grid, block, 0, st, a, partials);
+  }
   hipLaunchKernelGGL(k_reduce_rows, dim3(Q - 4), dim3(kBlock), 0, st, partials, nblk, 26, dLdomega, 1);
   if (dLdF_uniform)
     hipLaunchKernelGGL(k_reduce_rows, dim3(3), dim3(kBlock), 0, st, partials + 23, nblk, 26, dLdF_uniform, 1);
