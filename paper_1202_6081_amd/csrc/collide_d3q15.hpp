@@ -176,7 +176,7 @@ CMLBM_HD void populations15(R rho, R ux, R uy, R uz, R hx, R hy, R hz, R txy, R 
 
 // Density and velocity (Eqs. densitycalculation, velocitycalculation).
 template <typename R>
-CMLBM_HD void moments0_15(const R (&f)[15], R Fx, R Fy, R Fz, R& rho, R& ux, R& uy, R& uz) {
+CMLBM_HD void moments0_15(const R (&f)[15], R Fx, R Fy, R Fz, R& rho, R& ux, R& uy, R& uz, R& inv_rho) {
   rho = R(0);
 #pragma unroll
   for (int a = 0; a < 15; ++a) rho += f[a];
@@ -188,6 +188,7 @@ CMLBM_HD void moments0_15(const R (&f)[15], R Fx, R Fy, R Fz, R& rho, R& ux, R& 
     cz += R(kE15[a].z) * f[a];
   }
   const R inv = R(1) / rho;
+  inv_rho = inv;
   ux = (f[1] - f[2] + cx + R(0.5) * Fx) * inv;
   uy = (f[3] - f[4] + cy + R(0.5) * Fy) * inv;
   uz = (f[5] - f[6] + cz + R(0.5) * Fz) * inv;
@@ -195,33 +196,41 @@ CMLBM_HD void moments0_15(const R (&f)[15], R Fx, R Fy, R Fz, R& rho, R& ux, R& 
 
 template <typename R>
 CMLBM_HD void collide15(R (&f)[15], R Fx, R Fy, R Fz, const Rates<R>& p) {
-  R rho, ux, uy, uz;
-  moments0_15(f, Fx, Fy, Fz, rho, ux, uy, uz);
-  R h[15];
-  source15(Fx, Fy, Fz, ux, uy, uz, h);
-#pragma unroll
-  for (int a = 0; a < 15; ++a) h[a] += f[a];
-
-  // raw moments of h (corner links 7..14 carry all mixed monomials)
+  R rho, ux, uy, uz, inv_rho;
+  moments0_15(f, Fx, Fy, Fz, rho, ux, uy, uz, inv_rho);
+  // raw moments of f (corner links 7..14 carry all mixed monomials; on the
+  // corners e_x e_y^2 = e_x, ..., e_x^2 e_y^2 = 1)
   R c0 = R(0), rxy = R(0), rxz = R(0), ryz = R(0), rxyz = R(0), rcx = R(0), rcy = R(0), rcz = R(0);
 #pragma unroll
   for (int a = 7; a < 15; ++a) {
     const int x = kE15[a].x, y = kE15[a].y, z = kE15[a].z;
-    c0 += h[a];
-    rcx += R(x) * h[a];
-    rcy += R(y) * h[a];
-    rcz += R(z) * h[a];
-    rxy += R(x * y) * h[a];
-    rxz += R(x * z) * h[a];
-    ryz += R(y * z) * h[a];
-    rxyz += R(x * y * z) * h[a];
+    c0 += f[a];
+    rcx += R(x) * f[a];
+    rcy += R(y) * f[a];
+    rcz += R(z) * f[a];
+    rxy += R(x * y) * f[a];
+    rxz += R(x * z) * f[a];
+    ryz += R(y * z) * f[a];
+    rxyz += R(x * y * z) * f[a];
   }
-  const R rx = h[1] - h[2] + rcx, ry = h[3] - h[4] + rcy, rz = h[5] - h[6] + rcz;
-  const R rxx = h[1] + h[2] + c0, ryy = h[3] + h[4] + c0, rzz = h[5] + h[6] + c0;
-  const R rxyy = rcx, rxxy = rcy, rxxz = rcz, rxxyy = c0;   // e_x e_y^2 = e_x on corners, ...
-
-  // central moments of h about u (binomial theorem)
+  // plus the raw moments of the source S = K D^-1 m^s (Appendix G): with
+  // K^T K = D they follow from the printed projections m^s alone, e.g. the xx
+  // moment is m^s_7/2 + m^s_8/6 + m^s_9/3 = 2 F_x u_x and the xyy moment is
+  // (4/5) m^s_1 + m^s_10/10.
   const R ux2 = ux * ux, uy2 = uy * uy, uz2 = uz * uz;
+  const R Fu = Fx * ux, Fv = Fy * uy, Fw = Fz * uz;
+  const R rx = f[1] - f[2] + rcx + Fx, ry = f[3] - f[4] + rcy + Fy, rz = f[5] - f[6] + rcz + Fz;
+  rxy += Fx * uy + Fy * ux;
+  rxz += Fx * uz + Fz * ux;
+  ryz += Fy * uz + Fz * uy;
+  rxyz += Fx * uy * uz + Fy * ux * uz + Fz * ux * uy;
+  const R rxx = f[1] + f[2] + c0 + R(2) * Fu, ryy = f[3] + f[4] + c0 + R(2) * Fv, rzz = f[5] + f[6] + c0 + R(2) * Fw;
+  const R rxyy = rcx + R(0.5) * (Fx * (R(3) * ux2 + uy2 + uz2 - R(1)) + R(2) * ux * (Fv + Fw));
+  const R rxxy = rcy + R(0.5) * (Fy * (ux2 + R(3) * uy2 + uz2 - R(1)) + R(2) * uy * (Fu + Fw));
+  const R rxxz = rcz + R(0.5) * (Fz * (ux2 + uy2 + R(3) * uz2 - R(1)) + R(2) * uz * (Fu + Fv));
+  const R rxxyy = c0 + R(2.0 / 3.0) * (Fu * (uy2 + uz2) + Fv * (ux2 + uz2) + Fw * (ux2 + uy2));
+
+  // central moments of h = f + S about u (binomial theorem)
   const R cxy = rxy - ux * ry - uy * rx + ux * uy * rho;
   const R cxz = rxz - ux * rz - uz * rx + ux * uz * rho;
   const R cyz = ryz - uy * rz - uz * ry + uy * uz * rho;
@@ -245,7 +254,7 @@ CMLBM_HD void collide15(R (&f)[15], R Fx, R Fy, R Fz, const Rates<R>& p) {
   const R tzz = (t9 - d2) * R(1.0 / 3.0);
   populations15(rho, ux, uy, uz, R(0.5) * Fx, R(0.5) * Fy, R(0.5) * Fz, p.wc[4] * cxy, p.wc[5] * cxz,
                 p.wc[6] * cyz, txx, tyy, tzz, p.wc[10] * cxyy, p.wc[11] * cxxy, p.wc[12] * cxxz, p.wc[13] * cxyz,
-                p.wc[14] * cxxyy + p.w[14] * (txx * tyy * (p.per_mass ? R(1) / rho : R(1))), f);
+                p.wc[14] * cxxyy + p.w[14] * (txx * tyy * (p.per_mass ? inv_rho : R(1))), f);
 }
 
 // Initial transformed populations fbar = f^eq(rho, u) - S/2: f^eq has the
@@ -458,10 +467,10 @@ template <int PM = -1, typename R, typename W>
 CMLBM_HD void collide15_adj(const R (&f)[15], R Fx, R Fy, R Fz, const Rates<R>& p, R (&g)[15], R& gFx, R& gFy,
                             R& gFz, W& gw) {
   const bool pm = PM < 0 ? p.per_mass != 0 : PM != 0;
-  R rho, ux, uy, uz;
-  moments0_15(f, Fx, Fy, Fz, rho, ux, uy, uz);
+  R rho, ux, uy, uz, inv_rho;
+  moments0_15(f, Fx, Fy, Fz, rho, ux, uy, uz, inv_rho);
   R gux = R(0), guy = R(0), guz = R(0), grho = R(0);
-  const R sm = pm ? R(1) / rho : R(1);
+  const R sm = pm ? inv_rho : R(1);
 
   // forward: central moments c of h = f + S
   R c[15];
@@ -569,7 +578,7 @@ CMLBM_HD void collide15_adj(const R (&f)[15], R Fx, R Fy, R Fz, const Rates<R>& 
   R gh[15];
   raw15_adj(gc, gh);
   source15_adj(Fx, Fy, Fz, ux, uy, uz, gh, gFx, gFy, gFz, gux, guy, guz);
-  const R inv = R(1) / rho;
+  const R inv = inv_rho;
   const R gjx = gux * inv, gjy = guy * inv, gjz = guz * inv;
   grho -= (ux * gux + uy * guy + uz * guz) * inv;
   gFx += R(0.5) * gjx;

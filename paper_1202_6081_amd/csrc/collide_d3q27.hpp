@@ -179,7 +179,7 @@ CMLBM_HD void moments0_27(const R (&m)[27], R Fx, R Fy, R Fz, R& rho, R& ux, R& 
 // Relax the central moments in m (cube layout) in place.  PM: attractor form,
 // 0 literal, 1 per unit mass, -1 as p.per_mass says (run time).
 template <int PM = -1, typename R>
-CMLBM_HD void relax27(R (&m)[27], R rho, R Fx, R Fy, R Fz, const Rates<R>& p) {
+CMLBM_HD void relax27(R (&m)[27], R rho, R inv_rho, R Fx, R Fy, R Fz, const Rates<R>& p) {
   const bool pm = PM < 0 ? p.per_mass != 0 : PM != 0;
   // conserved: density and first central moments F/2
   m[K3(0, 0, 0)] = rho;
@@ -222,7 +222,7 @@ CMLBM_HD void relax27(R (&m)[27], R rho, R Fx, R Fy, R Fz, const Rates<R>& p) {
   }
   m[K3(1, 1, 1)] *= p.wc[16];
   // fourth order, diagonal pairs (g17, g18, g19) toward the factorized attractors
-  const R sm = pm ? R(1) / rho : R(1);
+  const R sm = pm ? inv_rho : R(1);
   {
     const R axy = kxx * kyy * sm, axz = kxx * kzz * sm, ayz = kyy * kzz * sm;
     const R A = m[K3(2, 2, 0)], B = m[K3(2, 0, 2)], C = m[K3(0, 2, 2)];
@@ -249,7 +249,7 @@ CMLBM_HD void relax27(R (&m)[27], R rho, R Fx, R Fy, R Fz, const Rates<R>& p) {
 // (s0, s1, s2) = (a+b+c, c-a, c+a) of each line give rho and j, then the shift
 // to central moments about u_z is the same arithmetic as fwd_line.
 template <typename R>
-CMLBM_HD void first_pass27(R (&m)[27], R Fx, R Fy, R Fz, R& rho, R& ux, R& uy, R& uz) {
+CMLBM_HD void first_pass27(R (&m)[27], R Fx, R Fy, R Fz, R& rho, R& ux, R& uy, R& uz, R& inv_rho) {
   R s0[9], s1[9];
 #pragma unroll
   for (int l = 0; l < 9; ++l) {
@@ -263,6 +263,7 @@ CMLBM_HD void first_pass27(R (&m)[27], R Fx, R Fy, R Fz, R& rho, R& ux, R& uy, R
   const R jy = (s0[2] + s0[5] + s0[8]) - (s0[0] + s0[3] + s0[6]);
   const R jz = ((s1[0] + s1[1] + s1[2]) + (s1[3] + s1[4] + s1[5])) + (s1[6] + s1[7] + s1[8]);
   const R inv = R(1) / rho;
+  inv_rho = inv;
   ux = (jx + R(0.5) * Fx) * inv;
   uy = (jy + R(0.5) * Fy) * inv;
   uz = (jz + R(0.5) * Fz) * inv;
@@ -280,11 +281,11 @@ CMLBM_HD void first_pass27(R (&m)[27], R Fx, R Fy, R Fz, R& rho, R& ux, R& uy, R
 // Full collision: cube-ordered pre-collision populations in, post-collision out.
 template <typename R>
 CMLBM_HD void collide27(R (&m)[27], R Fx, R Fy, R Fz, const Rates<R>& p) {
-  R rho, ux, uy, uz;
-  first_pass27(m, Fx, Fy, Fz, rho, ux, uy, uz);
+  R rho, ux, uy, uz, inv_rho;
+  first_pass27(m, Fx, Fy, Fz, rho, ux, uy, uz, inv_rho);
   fwd_pass<1>(m, uy);
   fwd_pass<0>(m, ux);
-  relax27(m, rho, Fx, Fy, Fz, p);
+  relax27(m, rho, inv_rho, Fx, Fy, Fz, p);
   inv_pass<0>(m, ux);
   inv_pass<1>(m, uy);
   inv_pass<2>(m, uz);
@@ -413,9 +414,9 @@ CMLBM_HD void relax27_adj(const R (&m)[27], R rho, const Rates<R>& p, R (&g)[27]
 template <int PM = -1, typename R, typename W>
 CMLBM_HD void collide27_adj(R (&f)[27], R Fx, R Fy, R Fz, const Rates<R>& p, R (&g)[27], R (&s)[27],
                                               R& gFx, R& gFy, R& gFz, W& gw) {
-  R rho, ux, uy, uz;
+  R rho, ux, uy, uz, inv_rho;
   R(&cm)[27] = f;
-  first_pass27(cm, Fx, Fy, Fz, rho, ux, uy, uz);
+  first_pass27(cm, Fx, Fy, Fz, rho, ux, uy, uz, inv_rho);
   fwd_pass<1>(cm, uy);
   fwd_pass<0>(cm, ux);
   R gux = R(0), guy = R(0), guz = R(0), grho = R(0);
@@ -423,7 +424,7 @@ CMLBM_HD void collide27_adj(R (&f)[27], R Fx, R Fy, R Fz, const Rates<R>& p, R (
   // relaxed moments, then replay the inverse passes to get each pass's input
 #pragma unroll
   for (int k = 0; k < 27; ++k) s[k] = cm[k];
-  relax27<PM>(s, rho, Fx, Fy, Fz, p);
+  relax27<PM>(s, rho, inv_rho, Fx, Fy, Fz, p);
   inv_pass<0>(s, ux);
   inv_pass<1>(s, uy);                        // s = input of the z inverse pass
   inv_pass_adj<2>(s, uz, g, guz);
@@ -445,7 +446,7 @@ CMLBM_HD void collide27_adj(R (&f)[27], R Fx, R Fy, R Fz, const Rates<R>& p, R (
   fwd_pass_adj<2>(s, uz, g, guz);
 
   // u = (sum f e + F/2) / rho, rho = sum f
-  const R inv = R(1) / rho;
+  const R inv = inv_rho;
   const R gjx = gux * inv, gjy = guy * inv, gjz = guz * inv;
   grho -= (ux * gux + uy * guy + uz * guz) * inv;
   gFx += R(0.5) * gjx;

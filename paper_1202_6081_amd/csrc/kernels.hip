@@ -252,48 +252,62 @@ __device__ __forceinline__ void add_node_totals(const R (&f)[Q], R Fx, R Fy, R F
 template <int NV>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double* sh /* [NV][8] */);
 
+// The two ends of one node's update: pull + force, and the store.
+template <int Q, class ST, bool MASK>
+__device__ __forceinline__ void load_node(const StepArgs<typename ST::R>& args, const Geom& g, uint32_t row,
+                                          uint32_t x, typename ST::R (&f)[Q], typename ST::R& Fx,
+                                          typename ST::R& Fy, typename ST::R& Fz) {
+  using R = typename ST::R;
+  const Coord c{int(x), int(row % uint32_t(g.ny)), int(row / uint32_t(g.ny))};
+  const Stencil st(g, c, +1);
+  pull<Q, ST, MASK>(static_cast<const typename ST::T*>(args.fin), g, args.mask, st, row, x, f);
+  if (args.force.field) {
+    const R* Ff = args.force.field + uint64_t(row) * uint32_t(g.nx);
+    const R sc = R(args.force.scale);
+    Fx = sc * ld32(Ff, x);
+    Fy = sc * ld32(Ff + g.N, x);
+    Fz = sc * ld32(Ff + 2 * g.N, x);
+  } else {
+    Fx = R(args.force.uni[0]);
+    Fy = R(args.force.uni[1]);
+    Fz = R(args.force.uni[2]);
+  }
+}
+
+template <int Q, class ST>
+__device__ __forceinline__ void store_node(const StepArgs<typename ST::R>& args, const Geom& g, uint32_t row,
+                                           uint32_t x, const typename ST::R (&f)[Q]) {
+  using T = typename ST::T;
+  const uint32_t rowQ = uint32_t(g.nx) * uint32_t(Q);
+  const __amdgpu_buffer_rsrc_t rs =
+      array_rsrc(static_cast<T*>(args.fout) + uint64_t(row) * rowQ, rowQ * uint32_t(sizeof(T)));
+#pragma unroll
+  for (int a = 0; a < Q; ++a)
+    buf_store(encode<ST, Q>(f[a], a), rs, in_row<Q>(uint32_t(g.nx), a, x) * uint32_t(sizeof(T)));
+}
+
 // With TOT, the step also writes its block's FP64 totals of the input state to
 // args.partials[blockIdx.x][0..3].
 template <int Q, class ST, bool MASK, bool TOT>
 __global__ __launch_bounds__(CMLBM_STEP_BLOCK) void k_step(StepArgs<typename ST::R> args) {
   using R = typename ST::R;
-  using T = typename ST::T;
   const Geom g = args.g;
   const uint32_t nseg = (uint32_t(g.nx) + blockDim.x - 1) / blockDim.x;
   const uint32_t L = step_block_id();
   const uint32_t row = L / nseg;                  // row = z * ny + y, uniform over the block
   const uint32_t x = (L - row * nseg) * blockDim.x + threadIdx.x;
-  const uint32_t node = row * uint32_t(g.nx) + x;
-  const bool active = x < uint32_t(g.nx) && !(MASK && args.mask[node]);
+  const bool active = x < uint32_t(g.nx) && !(MASK && args.mask[row * uint32_t(g.nx) + x]);
   double acc[4] = {0, 0, 0, 0};
   if constexpr (!TOT) {
     if (!active) return;
   }
   if (active) {
-    const Coord c{int(x), int(row % uint32_t(g.ny)), int(row / uint32_t(g.ny))};
-    const Stencil st(g, c, +1);
     R f[Q];
-    pull<Q, ST, MASK>(static_cast<const T*>(args.fin), g, args.mask, st, row, x, f);
     R Fx, Fy, Fz;
-    if (args.force.field) {
-      const R* Ff = args.force.field + uint64_t(row) * uint32_t(g.nx);
-      const R sc = R(args.force.scale);
-      Fx = sc * ld32(Ff, x);
-      Fy = sc * ld32(Ff + g.N, x);
-      Fz = sc * ld32(Ff + 2 * g.N, x);
-    } else {
-      Fx = R(args.force.uni[0]);
-      Fy = R(args.force.uni[1]);
-      Fz = R(args.force.uni[2]);
-    }
+    load_node<Q, ST, MASK>(args, g, row, x, f, Fx, Fy, Fz);
     if constexpr (TOT) add_node_totals<Q>(f, Fx, Fy, Fz, acc);
     collide<Q>(f, Fx, Fy, Fz, args.rates);
-    const uint32_t rowQ = uint32_t(g.nx) * uint32_t(Q);
-    const __amdgpu_buffer_rsrc_t rs =
-        array_rsrc(static_cast<T*>(args.fout) + uint64_t(row) * rowQ, rowQ * uint32_t(sizeof(T)));
-#pragma unroll
-    for (int a = 0; a < Q; ++a)
-      buf_store(encode<ST, Q>(f[a], a), rs, in_row<Q>(uint32_t(g.nx), a, x) * uint32_t(sizeof(T)));
+    store_node<Q, ST>(args, g, row, x, f);
   }
   if constexpr (TOT) {
     __shared__ double sh[4 * 8];
