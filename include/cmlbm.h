@@ -17,7 +17,9 @@
  *             duration of a call, except the force field and the mask, which
  *             are borrowed until replaced or until cmlbm_destroy.  The library
  *             owns only the opaque handle and device scratch for reductions
- *             (about nx*ny*nz/8 bytes plus 64 KiB, allocated by cmlbm_create).
+ *             (nx*ny*nz/8 bytes for the fused step totals, about
+ *             26*ceil(nx/256)*ny*nz bytes for the adjoint's partial sums, and
+ *             64 KiB), all allocated by cmlbm_create: no other call allocates.
  *             Device pointers must be 256-byte aligned.
  * Streams:    `stream` is a hipStream_t (NULL = the default stream).  Work is
  *             enqueued asynchronously; only cmlbm_totals synchronizes.

@@ -24,7 +24,7 @@ struct cmlbm_sim {
   const uint8_t* mask = nullptr;
   double* totals_partials = nullptr;   // [kTotalsBlocks][4]
   double* totals_out = nullptr;        // [4]
-  double* adj_partials = nullptr;      // [adj_nblk][26]
+  double* adj_partials = nullptr;      // [adj_nblk][26], adjoint dL/domega and uniform dL/dF partials
   int adj_nblk = 0;
   double* step_partials = nullptr;     // [step_blocks][4] + [kReduceChunks][4], fused step totals
   std::string err;
@@ -148,9 +148,11 @@ cmlbm_status cmlbm_create(int q, int nx, int ny, int nz, int precision, cmlbm_si
   s->g.N = N;
   for (double& w : s->omega) w = 1.0;
   const uint64_t step_rows = cmlbm::step_blocks(s->g) + cmlbm::kReduceChunks;
+  s->adj_nblk = cmlbm::adjoint_blocks(s->g);
   if (hipMalloc(&s->totals_partials, sizeof(double) * 4 * cmlbm::kTotalsBlocks) != hipSuccess ||
       hipMalloc(&s->totals_out, sizeof(double) * 4) != hipSuccess ||
-      hipMalloc(&s->step_partials, sizeof(double) * 4 * step_rows) != hipSuccess) {
+      hipMalloc(&s->step_partials, sizeof(double) * 4 * step_rows) != hipSuccess ||
+      hipMalloc(&s->adj_partials, sizeof(double) * 26 * size_t(s->adj_nblk)) != hipSuccess) {
     g_create_error = "device scratch allocation failed";
     cmlbm_destroy(s);
     return CMLBM_ENOMEM;
@@ -345,15 +347,7 @@ cmlbm_status cmlbm_adjoint_step(cmlbm_sim* s, const void* f_post_prev, const voi
   if (!f_post_prev || !lam_next || !lam || !dLdF_dev || !dLdomega_dev) return fail(s, CMLBM_EINVAL, "NULL buffer");
   if (lam == lam_next || lam == f_post_prev || lam_next == f_post_prev)
     return fail(s, CMLBM_EINVAL, "lam, lam_next and f_post_prev must differ");
-  const int nblk = cmlbm::adjoint_blocks(s->g);
-  if (nblk > s->adj_nblk) {
-    if (s->adj_partials) (void)hipFree(s->adj_partials);
-    s->adj_partials = nullptr;
-    s->adj_nblk = 0;
-    if (hipMalloc(&s->adj_partials, sizeof(double) * 26 * size_t(nblk)) != hipSuccess)
-      return fail(s, CMLBM_ENOMEM, "adjoint scratch allocation failed");
-    s->adj_nblk = nblk;
-  }
+  const int nblk = s->adj_nblk;
   cmlbm::AdjArgs<double> a64{};
   cmlbm::AdjArgs<float> a32{};
   if (s->prec == CMLBM_F64) {
