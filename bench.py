@@ -63,6 +63,7 @@ def cpu_baseline(seconds_target=15.0):
     om = [1.9] * 5 + [1.0] * 18
     f = lbm.initial_state(D3Q27, np.ones((n, n, n)), np.zeros((3, n, n, n)), F)
     t0 = time.perf_counter()
+    c0 = time.process_time()
     steps = 0
     while True:
         f = lbm.step(D3Q27, f, F, om)
@@ -70,7 +71,8 @@ def cpu_baseline(seconds_target=15.0):
         el = time.perf_counter() - t0
         if el > seconds_target * 0.5 or steps >= 8:
             break
-    return {"value": n**3 * steps / el / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+    cores = max(1, round((time.process_time() - c0) / el))     # threads the oracle actually kept busy
+    return {"value": n**3 * steps / el / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
             "sample": f"{steps} step(s) of a {n}^3 D3Q27 periodic box, FP64 NumPy oracle, "
                       f"Kolmogorov force, shear rate 1.9 ({el:.1f} s)"}
 
