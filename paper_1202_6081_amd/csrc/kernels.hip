@@ -126,28 +126,71 @@ struct Stencil {
   }
 };
 
+// Element of a byte offset from a uniform base (scalar-base load form).
+template <typename T>
+__device__ __forceinline__ T ldb(const void* base, uint32_t byte_off) {
+  return *reinterpret_cast<const T*>(static_cast<const char*>(base) + byte_off);
+}
+
 // Pull the pre-collision populations of node (row0, x) from the blocked
 // post-collision buffer `fin`.  With MASK, a link whose source is solid takes
 // the node's own reversed population (half-way bounce-back).
-template <int Q, class ST, bool MASK>
+//
+// WAVE: the caller guarantees that a wavefront covers one 64-node block of
+// one row (block size a multiple of 64, one row per block).  Then the block
+// start and length of the node's own x are wave-uniform, and the byte offset
+// of direction a splits into a per-lane part and a scalar part a*len, folded
+// into the base pointer; only the x-neighbour directions keep a per-lane
+// multiply-add.
+template <int Q, class ST, bool MASK, bool WAVE = false>
 __device__ __forceinline__ void pull(const typename ST::T* __restrict__ fin, const Geom& g, const uint8_t* mask,
                                      const Stencil& st, uint32_t row0, uint32_t x, typename ST::R (&f)[Q]) {
   using T = typename ST::T;
   const uint64_t rowQ = uint64_t(g.nx) * Q;
+  if constexpr (WAVE) {
+    constexpr uint32_t sz = uint32_t(sizeof(T));
+    const uint32_t nx = uint32_t(g.nx);
+    const uint32_t b0 = __builtin_amdgcn_readfirstlane(x & ~63u);
+    const uint32_t lenB = min(64u, nx - b0) * sz;            // wave-uniform
+    const uint32_t cbase = (b0 * uint32_t(Q) + (x - b0)) * sz;
+    uint32_t nbase[3], nlen[3];
 #pragma unroll
-  for (int a = 0; a < Q; ++a) {
-    const Vel e = Lattice<Q>::e(a);
-    const T* rp = fin + uint64_t(st.row[e.y + 1][e.z + 1]) * rowQ;
-    T v;
-    if constexpr (MASK) {
-      if (mask[st.node(e, uint32_t(g.nx))])
-        v = ld32(fin + uint64_t(row0) * rowQ, in_row<Q>(uint32_t(g.nx), opposite<Q>(a), x));
-      else
-        v = ld32(rp, in_row<Q>(uint32_t(g.nx), a, st.xs[e.x + 1]));
-    } else {
-      v = ld32(rp, in_row<Q>(uint32_t(g.nx), a, st.xs[e.x + 1]));
+    for (int i = 0; i < 3; i += 2) {
+      const uint32_t xs = st.xs[i];
+      const uint32_t bb = xs & ~63u;
+      nbase[i] = (bb * uint32_t(Q) + (xs - bb)) * sz;
+      nlen[i] = min(64u, nx - bb) * sz;
     }
-    f[a] = decode<ST, Q>(v, a);
+    const T* own = fin + uint64_t(row0) * rowQ;
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      const Vel e = Lattice<Q>::e(a);
+      const T* rp = fin + uint64_t(st.row[e.y + 1][e.z + 1]) * rowQ;
+      T v;
+      if (MASK && mask[st.node(e, nx)])
+        v = ldb<T>(reinterpret_cast<const char*>(own) + uint32_t(opposite<Q>(a)) * lenB, cbase);
+      else if (e.x == 0)
+        v = ldb<T>(reinterpret_cast<const char*>(rp) + uint32_t(a) * lenB, cbase);
+      else
+        v = ldb<T>(rp, nbase[e.x + 1] + uint32_t(a) * nlen[e.x + 1]);
+      f[a] = decode<ST, Q>(v, a);
+    }
+  } else {
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      const Vel e = Lattice<Q>::e(a);
+      const T* rp = fin + uint64_t(st.row[e.y + 1][e.z + 1]) * rowQ;
+      T v;
+      if constexpr (MASK) {
+        if (mask[st.node(e, uint32_t(g.nx))])
+          v = ld32(fin + uint64_t(row0) * rowQ, in_row<Q>(uint32_t(g.nx), opposite<Q>(a), x));
+        else
+          v = ld32(rp, in_row<Q>(uint32_t(g.nx), a, st.xs[e.x + 1]));
+      } else {
+        v = ld32(rp, in_row<Q>(uint32_t(g.nx), a, st.xs[e.x + 1]));
+      }
+      f[a] = decode<ST, Q>(v, a);
+    }
   }
 }
 
@@ -214,15 +257,16 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t array_rsrc(void* base, uint32_
   return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, int(bytes), 0x00020000);
 }
 
+// voff: per-lane byte offset; soff: wave-uniform byte offset.
 template <typename T>
-__device__ __forceinline__ void buf_store(T v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+__device__ __forceinline__ void buf_store(T v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
   if constexpr (sizeof(T) == 4) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, kStoreAux);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, kStoreAux);
   } else if constexpr (sizeof(T) == 8) {
     typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, kStoreAux);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, kStoreAux);
   } else {
-    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, off, 0, kStoreAux);
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, voff, soff, kStoreAux);
   }
 }
 
@@ -260,7 +304,7 @@ __device__ __forceinline__ void load_node(const StepArgs<typename ST::R>& args, 
   using R = typename ST::R;
   const Coord c{int(x), int(row % uint32_t(g.ny)), int(row / uint32_t(g.ny))};
   const Stencil st(g, c, +1);
-  pull<Q, ST, MASK>(static_cast<const typename ST::T*>(args.fin), g, args.mask, st, row, x, f);
+  pull<Q, ST, MASK, true>(static_cast<const typename ST::T*>(args.fin), g, args.mask, st, row, x, f);
   if (args.force.field) {
     const R* Ff = args.force.field + uint64_t(row) * uint32_t(g.nx);
     const R sc = R(args.force.scale);
@@ -274,16 +318,21 @@ __device__ __forceinline__ void load_node(const StepArgs<typename ST::R>& args, 
   }
 }
 
+// Store of node (row, x); a wavefront covers one 64-node block of the row, so
+// the direction stride of the blocked layout is wave-uniform (scalar offset).
 template <int Q, class ST>
 __device__ __forceinline__ void store_node(const StepArgs<typename ST::R>& args, const Geom& g, uint32_t row,
                                            uint32_t x, const typename ST::R (&f)[Q]) {
   using T = typename ST::T;
-  const uint32_t rowQ = uint32_t(g.nx) * uint32_t(Q);
-  const __amdgpu_buffer_rsrc_t rs =
-      array_rsrc(static_cast<T*>(args.fout) + uint64_t(row) * rowQ, rowQ * uint32_t(sizeof(T)));
+  constexpr uint32_t sz = uint32_t(sizeof(T));
+  const uint32_t nx = uint32_t(g.nx);
+  const uint32_t rowQ = nx * uint32_t(Q);
+  const __amdgpu_buffer_rsrc_t rs = array_rsrc(static_cast<T*>(args.fout) + uint64_t(row) * rowQ, rowQ * sz);
+  const uint32_t b0 = __builtin_amdgcn_readfirstlane(x & ~63u);
+  const uint32_t lenB = min(64u, nx - b0) * sz;
+  const uint32_t cbase = (b0 * uint32_t(Q) + (x - b0)) * sz;
 #pragma unroll
-  for (int a = 0; a < Q; ++a)
-    buf_store(encode<ST, Q>(f[a], a), rs, in_row<Q>(uint32_t(g.nx), a, x) * uint32_t(sizeof(T)));
+  for (int a = 0; a < Q; ++a) buf_store(encode<ST, Q>(f[a], a), rs, cbase, uint32_t(a) * lenB);
 }
 
 // With TOT, the step also writes its block's FP64 totals of the input state to
@@ -644,7 +693,7 @@ __global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(adjoi
     {
       const Stencil st(g, c, +1);
       R fa[Q];
-      pull<Q, ST, MASK>(static_cast<const T*>(args.fpost), g, args.mask, st, row, x, fa);
+      pull<Q, ST, MASK, true>(static_cast<const T*>(args.fpost), g, args.mask, st, row, x, fa);
 #pragma unroll
       for (int a = 0; a < Q; ++a) f[slot<Q>(a)] = fa[a];
     }

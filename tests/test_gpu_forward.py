@@ -288,6 +288,35 @@ def test_duct_128_transient_closed_form():
     assert err < 1e-2
 
 
+def test_duct_128_steady_series():
+    # The same duct run to steady state: 4e5 steps, the slowest start-up mode
+    # (rate 2 nu (pi/2a)^2 = 2.3e-5 per step) is down to e^-9.2; against the
+    # steady Fourier series (Eq. ductFourier) and its centre value
+    # 0.2946854 a^2 F / (rho nu).
+    print("case duct128 steady", flush=True)
+    n, steps, omega, Fx = 128, 400000, 1.8, 1e-6
+    solid = inp.duct_mask(n, n, n)
+    sim = gpu_setup(27, (n, n, n), F32, shear_rates(27, omega), np.array([Fx, 0, 0]), solid)
+    f_post, _ = gpu_initial(sim, np.ones((n, n, n)), np.zeros((3, n, n, n)))
+    f_last = sim.run(f_post, sim.populations(), steps)
+    _, u = sim.macroscopic(f_last)
+    u = u.double().cpu().numpy()
+    ux = u[0, 1:-1, 1:-1, n // 2]
+    from test_oracle_flows import duct_steady_paper, nu_of
+    a, nu = (n - 2) / 2, nu_of(omega)
+    c = np.arange(1, n - 1) - (n - 1) / 2
+    Z, Y = np.meshgrid(c, c, indexing="ij")
+    ua = duct_steady_paper(Y, Z, a, Fx, nu)
+    err = np.linalg.norm(ux - ua) / np.linalg.norm(ua)
+    centre = 0.25 * (ux[62, 62] + ux[62, 63] + ux[63, 62] + ux[63, 63])   # the centre lies between nodes
+    print(f"duct128 steady: relative L2 {err:.3e}; centre {centre:.6e} vs series "
+          f"{duct_steady_paper(0.0, 0.0, a, Fx, nu):.6e} (0.2946854 a^2 F/nu = {0.2946854 * a * a * Fx / nu:.6e})",
+          flush=True)
+    assert err < 2e-3                                                       # measured 1.8e-4
+    assert abs(centre / (0.2946854 * a * a * Fx / nu) - 1) < 2e-3           # measured 3.3e-4
+    assert np.abs(u[1:, 1:-1, 1:-1]).max() < 1e-3 * np.abs(ux).max()        # no cross flow
+
+
 @pytest.mark.parametrize("prec", [F64, F32, F16, BF16])
 @pytest.mark.parametrize("q,nx", [(27, 130), (15, 64), (27, 5)])
 def test_population_buffer_layout(prec, q, nx):
