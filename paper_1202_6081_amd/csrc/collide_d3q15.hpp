@@ -194,6 +194,67 @@ CMLBM_HD void moments0_15(const R (&f)[15], R Fx, R Fy, R Fz, R& rho, R& ux, R& 
   uz = (f[5] - f[6] + cz + R(0.5) * Fz) * inv;
 }
 
+// Raw moments of the source S = K D^-1 m^s (Appendix G), in the moment order
+// 1, x, y, z, xy, xz, yz, xx, yy, zz, xyy, xxy, xxz, xyz, xxyy.  With K^T K = D
+// they follow from the printed projections m^s alone: e.g. the xx moment is
+// m^s_7/2 + m^s_8/6 + m^s_9/3 = 2 F_x u_x and the xyy moment is
+// (4/5) m^s_1 + m^s_10/10.
+template <typename R>
+CMLBM_HD void source_raw15(R Fx, R Fy, R Fz, R ux, R uy, R uz, R (&r)[15]) {
+  const R ux2 = ux * ux, uy2 = uy * uy, uz2 = uz * uz;
+  const R Fu = Fx * ux, Fv = Fy * uy, Fw = Fz * uz;
+  r[0] = R(0);
+  r[1] = Fx;
+  r[2] = Fy;
+  r[3] = Fz;
+  r[4] = Fx * uy + Fy * ux;
+  r[5] = Fx * uz + Fz * ux;
+  r[6] = Fy * uz + Fz * uy;
+  r[7] = R(2) * Fu;
+  r[8] = R(2) * Fv;
+  r[9] = R(2) * Fw;
+  r[10] = R(0.5) * (Fx * (R(3) * ux2 + uy2 + uz2 - R(1)) + R(2) * ux * (Fv + Fw));
+  r[11] = R(0.5) * (Fy * (ux2 + R(3) * uy2 + uz2 - R(1)) + R(2) * uy * (Fu + Fw));
+  r[12] = R(0.5) * (Fz * (ux2 + uy2 + R(3) * uz2 - R(1)) + R(2) * uz * (Fu + Fv));
+  r[13] = Fx * uy * uz + Fy * ux * uz + Fz * ux * uy;
+  r[14] = R(2.0 / 3.0) * (Fu * (uy2 + uz2) + Fv * (ux2 + uz2) + Fw * (ux2 + uy2));
+}
+
+// Adjoint of source_raw15 with respect to F and u (gr: adjoint of r).
+template <typename R>
+CMLBM_HD void source_raw15_adj(R Fx, R Fy, R Fz, R ux, R uy, R uz, const R (&gr)[15], R& gFx, R& gFy, R& gFz,
+                               R& gux, R& guy, R& guz) {
+  const R ux2 = ux * ux, uy2 = uy * uy, uz2 = uz * uz;
+  const R Fu = Fx * ux, Fv = Fy * uy, Fw = Fz * uz;
+  gFx += gr[1] + uy * gr[4] + uz * gr[5] + R(2) * ux * gr[7];
+  gFy += gr[2] + ux * gr[4] + uz * gr[6] + R(2) * uy * gr[8];
+  gFz += gr[3] + ux * gr[5] + uy * gr[6] + R(2) * uz * gr[9];
+  gux += Fy * gr[4] + Fz * gr[5] + R(2) * Fx * gr[7];
+  guy += Fx * gr[4] + Fz * gr[6] + R(2) * Fy * gr[8];
+  guz += Fx * gr[5] + Fy * gr[6] + R(2) * Fz * gr[9];
+  // third order
+  gFx += R(0.5) * (R(3) * ux2 + uy2 + uz2 - R(1)) * gr[10] + ux * uy * gr[11] + ux * uz * gr[12];
+  gFy += ux * uy * gr[10] + R(0.5) * (ux2 + R(3) * uy2 + uz2 - R(1)) * gr[11] + uy * uz * gr[12];
+  gFz += ux * uz * gr[10] + uy * uz * gr[11] + R(0.5) * (ux2 + uy2 + R(3) * uz2 - R(1)) * gr[12];
+  gux += (R(3) * Fu + Fv + Fw) * gr[10] + (Fy * ux + Fx * uy) * gr[11] + (Fz * ux + Fx * uz) * gr[12];
+  guy += (Fx * uy + Fy * ux) * gr[10] + (R(3) * Fv + Fu + Fw) * gr[11] + (Fz * uy + Fy * uz) * gr[12];
+  guz += (Fx * uz + Fz * ux) * gr[10] + (Fy * uz + Fz * uy) * gr[11] + (R(3) * Fw + Fu + Fv) * gr[12];
+  gFx += uy * uz * gr[13];
+  gFy += ux * uz * gr[13];
+  gFz += ux * uy * gr[13];
+  gux += (Fy * uz + Fz * uy) * gr[13];
+  guy += (Fx * uz + Fz * ux) * gr[13];
+  guz += (Fx * uy + Fy * ux) * gr[13];
+  // fourth order
+  const R c = R(2.0 / 3.0) * gr[14];
+  gFx += c * ux * (uy2 + uz2);
+  gFy += c * uy * (ux2 + uz2);
+  gFz += c * uz * (ux2 + uy2);
+  gux += c * (Fx * (uy2 + uz2) + R(2) * ux * (Fv + Fw));
+  guy += c * (Fy * (ux2 + uz2) + R(2) * uy * (Fu + Fw));
+  guz += c * (Fz * (ux2 + uy2) + R(2) * uz * (Fu + Fv));
+}
+
 template <typename R>
 CMLBM_HD void collide15(R (&f)[15], R Fx, R Fy, R Fz, const Rates<R>& p) {
   R rho, ux, uy, uz, inv_rho;
@@ -213,22 +274,17 @@ CMLBM_HD void collide15(R (&f)[15], R Fx, R Fy, R Fz, const Rates<R>& p) {
     ryz += R(y * z) * f[a];
     rxyz += R(x * y * z) * f[a];
   }
-  // plus the raw moments of the source S = K D^-1 m^s (Appendix G): with
-  // K^T K = D they follow from the printed projections m^s alone, e.g. the xx
-  // moment is m^s_7/2 + m^s_8/6 + m^s_9/3 = 2 F_x u_x and the xyy moment is
-  // (4/5) m^s_1 + m^s_10/10.
+  // plus the raw moments of the source
+  R rs[15];
+  source_raw15(Fx, Fy, Fz, ux, uy, uz, rs);
   const R ux2 = ux * ux, uy2 = uy * uy, uz2 = uz * uz;
-  const R Fu = Fx * ux, Fv = Fy * uy, Fw = Fz * uz;
-  const R rx = f[1] - f[2] + rcx + Fx, ry = f[3] - f[4] + rcy + Fy, rz = f[5] - f[6] + rcz + Fz;
-  rxy += Fx * uy + Fy * ux;
-  rxz += Fx * uz + Fz * ux;
-  ryz += Fy * uz + Fz * uy;
-  rxyz += Fx * uy * uz + Fy * ux * uz + Fz * ux * uy;
-  const R rxx = f[1] + f[2] + c0 + R(2) * Fu, ryy = f[3] + f[4] + c0 + R(2) * Fv, rzz = f[5] + f[6] + c0 + R(2) * Fw;
-  const R rxyy = rcx + R(0.5) * (Fx * (R(3) * ux2 + uy2 + uz2 - R(1)) + R(2) * ux * (Fv + Fw));
-  const R rxxy = rcy + R(0.5) * (Fy * (ux2 + R(3) * uy2 + uz2 - R(1)) + R(2) * uy * (Fu + Fw));
-  const R rxxz = rcz + R(0.5) * (Fz * (ux2 + uy2 + R(3) * uz2 - R(1)) + R(2) * uz * (Fu + Fv));
-  const R rxxyy = c0 + R(2.0 / 3.0) * (Fu * (uy2 + uz2) + Fv * (ux2 + uz2) + Fw * (ux2 + uy2));
+  const R rx = f[1] - f[2] + rcx + rs[1], ry = f[3] - f[4] + rcy + rs[2], rz = f[5] - f[6] + rcz + rs[3];
+  rxy += rs[4];
+  rxz += rs[5];
+  ryz += rs[6];
+  rxyz += rs[13];
+  const R rxx = f[1] + f[2] + c0 + rs[7], ryy = f[3] + f[4] + c0 + rs[8], rzz = f[5] + f[6] + c0 + rs[9];
+  const R rxyy = rcx + rs[10], rxxy = rcy + rs[11], rxxz = rcz + rs[12], rxxyy = c0 + rs[14];
 
   // central moments of h = f + S about u (binomial theorem)
   const R cxy = rxy - ux * ry - uy * rx + ux * uy * rho;
@@ -472,14 +528,14 @@ CMLBM_HD void collide15_adj(const R (&f)[15], R Fx, R Fy, R Fz, const Rates<R>& 
   R gux = R(0), guy = R(0), guz = R(0), grho = R(0);
   const R sm = pm ? inv_rho : R(1);
 
-  // forward: central moments c of h = f + S
+  // forward: central moments c of h = f + S (raw moments of f plus those of S)
   R c[15];
   {
-    R h[15];
-    source15(Fx, Fy, Fz, ux, uy, uz, h);
+    R rs[15];
+    raw15(f, c);
+    source_raw15(Fx, Fy, Fz, ux, uy, uz, rs);
 #pragma unroll
-    for (int a = 0; a < 15; ++a) h[a] += f[a];
-    raw15(h, c);
+    for (int m = 0; m < 15; ++m) c[m] += rs[m];
   }
   shift15<0>(c, ux, R(-1));
   shift15<1>(c, uy, R(-1));
@@ -574,10 +630,10 @@ CMLBM_HD void collide15_adj(const R (&f)[15], R Fx, R Fy, R Fz, const Rates<R>& 
     shift15<0>(v, ux, R(1));   // raw moments of h
     shift15_adj<0>(v, ux, R(-1), gc, gux);
   }
-  // raw moments, source, density and velocity
+  // raw moments (of f and of the source), density and velocity
   R gh[15];
   raw15_adj(gc, gh);
-  source15_adj(Fx, Fy, Fz, ux, uy, uz, gh, gFx, gFy, gFz, gux, guy, guz);
+  source_raw15_adj(Fx, Fy, Fz, ux, uy, uz, gc, gFx, gFy, gFz, gux, guy, guz);
   const R inv = inv_rho;
   const R gjx = gux * inv, gjy = guy * inv, gjz = guz * inv;
   grho -= (ux * gux + uy * guy + uz * guz) * inv;
