@@ -51,7 +51,7 @@ def measured_traffic(n_nodes):
     return rec.get("hbm_bytes_per_dispatch")
 
 
-def cpu_baseline(seconds_target=15.0):
+def cpu_baseline(seconds_target=12.0):
     """The FP64 oracle on a bounded sample of the same workload: single steps of
     a 40^3 D3Q27 box with the same rates and a Kolmogorov force."""
     import numpy as np
@@ -69,7 +69,7 @@ def cpu_baseline(seconds_target=15.0):
         f = lbm.step(D3Q27, f, F, om)
         steps += 1
         el = time.perf_counter() - t0
-        if el > seconds_target * 0.5 or steps >= 8:
+        if el > seconds_target or steps >= 16:
             break
     cores = max(1, round((time.process_time() - c0) / el))     # threads the oracle actually kept busy
     return {"value": n**3 * steps / el / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",

@@ -224,6 +224,11 @@ def test_run_ping_pong_and_errors():
     b = sim.populations()
     assert sim.run(f_post, b, 3) is b
     assert sim.run(f_post, b, 2) is f_post
+    before = f_post.clone()
+    assert sim.run(f_post, b, 0) is f_post                # zero steps: nothing happens
+    assert torch.equal(before, f_post)
+    with pytest.raises(cm.CmlbmError):
+        sim.run(f_post, b, -1)
     with pytest.raises(cm.CmlbmError):
         sim.step(f_post, f_post)                        # aliasing is rejected
     with pytest.raises(cm.CmlbmError):
