@@ -9,8 +9,9 @@ Synthetic inputs, no dataset.
 
 Prints ONE JSON line: MLUPS (whole job), the HBM roofline of the step kernel
 (algorithmic 228 B per node update: 27 FP32 loads + 27 FP32 stores + 3 FP32
-force loads), the FP64 CPU oracle timed on a bounded sample, and the
-adjoint/forward time ratio of a 100-step checkpointed adjoint.
+force loads), the FP64 CPU oracle timed on a bounded sample, the
+adjoint/forward time ratio of a 100-step checkpointed adjoint, and the
+per-launch step time of every lattice/storage variant on the same workload.
 """
 import argparse
 import hashlib
@@ -77,15 +78,60 @@ def cpu_baseline(seconds_target=12.0):
                       f"Kolmogorov force, shear rate 1.9 ({el:.1f} s)"}
 
 
+def variant_sweep(n, steps=30, warmup=3):
+    """Per-launch step time of every lattice and storage variant on the same
+    512^3 workload (events around each launch on its stream)."""
+    import torch
+    import lbm_inputs as inp
+    from paper_1202_6081_amd import cmlbm
+    dev = torch.device("cuda", 0)
+    out = []
+    for q in (27, 15):
+        for prec, name, tb in ((cmlbm.F64, "f64", 8), (cmlbm.F32, "f32", 4), (cmlbm.F32_F16DEV, "f16dev", 2),
+                               (cmlbm.F32_BF16DEV, "bf16dev", 2)):
+            sim = cmlbm.Sim(q, n, n, n, prec)
+            sim.set_rates([1.9] * 5 + [1.0] * (q - 9))
+            sim.set_force(torch.from_numpy(inp.kolmogorov_force(n, amplitude=1e-6, waves=4)).to(dev, sim.real))
+            a, b = sim.populations(), sim.populations()
+            pre = sim.real_populations()
+            sim.init_equilibrium(torch.ones((n, n, n), device=dev, dtype=sim.real),
+                                 torch.zeros((3, n, n, n), device=dev, dtype=sim.real), f_post=a, f_pre=pre)
+            del pre
+            bufs = [a, b]
+            for i in range(warmup):
+                sim.step(bufs[i & 1], bufs[(i + 1) & 1])
+            stream = torch.cuda.current_stream()
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+            torch.cuda.synchronize()
+            for i in range(steps):
+                j = warmup + i
+                ev[i][0].record(stream)
+                sim.step(bufs[j & 1], bufs[(j + 1) & 1])
+                ev[i][1].record(stream)
+            torch.cuda.synchronize()
+            ms = sum(e0.elapsed_time(e1) for e0, e1 in ev) / steps
+            bpn = q * tb * 2 + 3 * (8 if prec == cmlbm.F64 else 4)
+            gbs = bpn * n**3 / (ms * 1e-3) / 1e9
+            out.append({"lattice": f"D3Q{q}", "storage": name, "ms": round(ms, 4),
+                        "MLUPS": round(n**3 / (ms * 1e-3) / 1e6, 1), "bytes_per_node": bpn,
+                        "GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)})
+            del a, b, bufs, sim
+            torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=200,
+                    help="untimed steps first (about 1 s at 512^3: the clocks settle within that)")
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--adjoint-steps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the per-variant step timings (both lattices, four storage types)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 4 GiB device buffer 8 times (known bytes, for scaling HBM counters)")
     args = ap.parse_args()
@@ -177,6 +223,7 @@ def main():
         result["adjoint"] = None
         result["adjoint_forward_ratio"] = None
     torch.cuda.empty_cache()
+    result["variants"] = None if args.no_variants else variant_sweep(n)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline()
     print(json.dumps(result), flush=True)

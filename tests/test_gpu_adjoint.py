@@ -82,6 +82,55 @@ def test_single_adjoint_step(q, force_kind, masked, per_mass):
         assert abs(dLdw[b] - ref) <= 1e-9 * abs(ref) + 1e-13, (b, dLdw[b], ref)
 
 
+@pytest.mark.parametrize("q,prec", [(27, F32), (15, F32), (27, 2), (15, 3)])
+def test_single_adjoint_step_fp32_arithmetic(q, prec):
+    # FP32 arithmetic (FP32 or 16-bit deviation storage): the adjoint at the
+    # decoded pre-collision state, against the oracle's complex-step
+    # derivative at that same state, to FP32 accuracy.
+    print(f"case adjoint-step-fp32 q{q} p{prec}", flush=True)
+    lat = LATTICES[q]
+    shape = (5, 6, 70)
+    rng = np.random.default_rng(23)
+    om = list(rng.uniform(0.7, 1.9, q - 4))
+    F = inp.gaussian_force(shape, 1e-4, 6)
+    solid = _walls(shape)
+    fluid = ~solid
+    sim = gpu_setup(q, shape, prec, om, F, solid)
+    rho0 = 1 + 0.01 * rng.standard_normal(shape)
+    u0 = 0.05 * rng.uniform(-1, 1, (3,) + shape)
+    x, _ = sim.init_equilibrium(torch.from_numpy(rho0).float().cuda(), torch.from_numpy(u0).float().cuda())
+    x = sim.run(x, sim.populations(), 2)
+    f_pre = sim.gather(x).double().cpu().numpy()             # decoded state the adjoint linearizes at
+    mu = rng.standard_normal((q,) + shape)
+    mu[:, ~fluid] = 0.0
+    lam = torch.zeros((q,) + shape, dtype=torch.float32, device="cuda")
+    dLdF = torch.zeros(F.shape, dtype=torch.float64, device="cuda")
+    dLdw = torch.zeros(q - 4, dtype=torch.float64, device="cuda")
+    sim.adjoint_step(x, torch.from_numpy(mu).float().cuda(), lam, dLdF, dLdw)
+    lam = lam.double().cpu().numpy()
+    lam[:, ~fluid] = 0.0
+    dLdF = dLdF.cpu().numpy()
+    dLdw = dLdw.cpu().numpy()
+    Fr = F.astype(np.float32).astype(np.float64)               # the force the FP32 kernels read
+
+    def L(f, Fv, w):
+        return np.sum(mu * lbm.step(lat, f, Fv, w, solid))
+
+    for k in range(2):
+        v = rng.standard_normal(f_pre.shape)
+        v[:, ~fluid] = 0.0
+        ref = L(f_pre + 1j * H * v, Fr.astype(complex), np.array(om, dtype=complex)).imag / H
+        assert abs(np.sum(lam * v) - ref) <= 1e-5 * np.linalg.norm(lam) * np.linalg.norm(v), (k, np.sum(lam * v), ref)
+        vF = rng.standard_normal(F.shape)
+        vF[:, ~fluid] = 0.0
+        ref = L(f_pre.astype(complex), Fr + 1j * H * vF, np.array(om, dtype=complex)).imag / H
+        assert abs(np.sum(dLdF * vF) - ref) <= 1e-4 * np.linalg.norm(dLdF) * np.linalg.norm(vF)
+    w = np.array(om, dtype=complex)
+    w[0] += 1j * H
+    ref = L(f_pre.astype(complex), Fr.astype(complex), w).imag / H
+    assert abs(dLdw[0] - ref) <= 1e-4 * np.abs(dLdw).max(), (dLdw[0], ref)
+
+
 def _oracle_loss(rho0, u0, F, om, nsteps, solid, per_mass=False, q=27):
     lat = LATTICES[q]
     f = lbm.initial_state(lat, rho0, u0, F, solid)
