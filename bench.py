@@ -11,7 +11,8 @@ Prints ONE JSON line: MLUPS (whole job), the HBM roofline of the step kernel
 (algorithmic 228 B per node update: 27 FP32 loads + 27 FP32 stores + 3 FP32
 force loads), the FP64 CPU oracle timed on a bounded sample, the
 adjoint/forward time ratio of a 100-step checkpointed adjoint, and the
-per-launch step time of every lattice/storage variant on the same workload.
+per-launch step time of every lattice/storage variant on the same workload,
+two-buffer and in-place.
 """
 import argparse
 import hashlib
@@ -80,7 +81,8 @@ def cpu_baseline(seconds_target=12.0):
 
 def variant_sweep(n, steps=30, warmup=3):
     """Per-launch step time of every lattice and storage variant on the same
-    512^3 workload (events around each launch on its stream)."""
+    512^3 workload (events around each launch on its stream), for the
+    two-buffer step and for the in-place step (mean of its two phases)."""
     import torch
     import lbm_inputs as inp
     from paper_1202_6081_amd import cmlbm
@@ -96,28 +98,48 @@ def variant_sweep(n, steps=30, warmup=3):
             pre = sim.real_populations()
             sim.init_equilibrium(torch.ones((n, n, n), device=dev, dtype=sim.real),
                                  torch.zeros((3, n, n, n), device=dev, dtype=sim.real), f_post=a, f_pre=pre)
-            del pre
             bufs = [a, b]
             for i in range(warmup):
                 sim.step(bufs[i & 1], bufs[(i + 1) & 1])
-            stream = torch.cuda.current_stream()
-            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
-            torch.cuda.synchronize()
-            for i in range(steps):
-                j = warmup + i
-                ev[i][0].record(stream)
-                sim.step(bufs[j & 1], bufs[(j + 1) & 1])
-                ev[i][1].record(stream)
-            torch.cuda.synchronize()
-            ms = sum(e0.elapsed_time(e1) for e0, e1 in ev) / steps
+            ms = _launch_ms(lambda i: sim.step(bufs[(warmup + i) & 1], bufs[(warmup + i + 1) & 1]), steps)
+            # the in-place (one-buffer) step from the same initial state
+            sim.import_populations(pre, b)
+            del pre
+            for i in range(warmup + (warmup & 1)):
+                sim.step_inplace(b, i & 1)
+            t_in = _launch_ms(lambda i: sim.step_inplace(b, i & 1), 2 * (steps // 2), per_launch=True)
+            ms_even, ms_odd = sum(t_in[0::2]) / len(t_in[0::2]), sum(t_in[1::2]) / len(t_in[1::2])
+            ms_in = (ms_even + ms_odd) / 2
             bpn = q * tb * 2 + 3 * (8 if prec == cmlbm.F64 else 4)
             gbs = bpn * n**3 / (ms * 1e-3) / 1e9
+            gbs_in = bpn * n**3 / (ms_in * 1e-3) / 1e9
             out.append({"lattice": f"D3Q{q}", "storage": name, "ms": round(ms, 4),
                         "MLUPS": round(n**3 / (ms * 1e-3) / 1e6, 1), "bytes_per_node": bpn,
-                        "GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)})
+                        "GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                        "inplace": {"ms": round(ms_in, 4), "ms_collide_phase": round(ms_even, 4),
+                                    "ms_scatter_phase": round(ms_odd, 4),
+                                    "MLUPS": round(n**3 / (ms_in * 1e-3) / 1e6, 1),
+                                    "frac": round(gbs_in / HBM_PEAK_GBS, 4),
+                                    "state_GiB": round(q * tb * n**3 / 2**30, 2)}})
             del a, b, bufs, sim
             torch.cuda.empty_cache()
     return out
+
+
+def _launch_ms(launch, count, per_launch=False):
+    """Duration of each of `count` launches (event pair around each on the
+    launch stream); their mean, or the list with per_launch."""
+    import torch
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(count)]
+    torch.cuda.synchronize()
+    for i in range(count):
+        ev[i][0].record(stream)
+        launch(i)
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    t = [e0.elapsed_time(e1) for e0, e1 in ev]
+    return t if per_launch else sum(t) / count
 
 
 def main():
@@ -224,6 +246,9 @@ def main():
         result["adjoint_forward_ratio"] = None
     torch.cuda.empty_cache()
     result["variants"] = None if args.no_variants else variant_sweep(n)
+    # the same workload stepped in place (one population buffer)
+    result["inplace"] = None if args.no_variants else next(
+        v["inplace"] for v in result["variants"] if v["lattice"] == "D3Q27" and v["storage"] == "f32")
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline()
     print(json.dumps(result), flush=True)

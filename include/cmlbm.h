@@ -179,6 +179,37 @@ cmlbm_status cmlbm_macroscopic(cmlbm_sim *sim, const void *f_post, void *rho, vo
  * output; synchronizes `stream`. */
 cmlbm_status cmlbm_totals(cmlbm_sim *sim, const void *f_post, double out4[4], void *stream);
 
+/* In-place stepping: one population buffer instead of two, same bytes moved
+ * per step (the AA pattern of Bailey et al., 2009, applied to the step of
+ * Eqs. cascadedcollision1 and cascadedstreaming1, with the half-way
+ * bounce-back of Sec. 9).  The buffer has the blocked layout and storage type
+ * of the other population buffers and is in one of two phases:
+ *   phase 0: slot a of node x holds the pre-collision fbar_a(x, t), the
+ *            paper's state (cmlbm_import_populations of the f_pre written by
+ *            cmlbm_init_equilibrium or cmlbm_gather_precollision gives it;
+ *            cmlbm_export_populations reads it back);
+ *   phase 1: slot abar of node x holds the post-collision fbar~_a(x, t).
+ * parity = the phase of f on entry; each call is one time step (one
+ * collision of every fluid node).  parity 0: phase 0 holding fbar(t) ->
+ * phase 1 holding fbar~(t), every node reading and writing only its own
+ * slots.  parity 1: phase 1 holding fbar~(t) -> phase 0 holding fbar(t + 2):
+ * each node gathers fbar(x, t + 1) from its neighbours, collides, and scatters
+ * the result to the slots its neighbours pull from next.  Solid nodes' slots
+ * are never read or written.  Errors: EINVAL (NULL, parity not 0 or 1).  Calls
+ * on one buffer must be ordered (one stream). */
+cmlbm_status cmlbm_step_inplace(cmlbm_sim *sim, void *f, int parity, void *stream);
+
+/* nsteps in-place steps (parities 0, 1, 0, 1, ...): f holds the pre-collision
+ * fbar(t) in phase 0 on entry and fbar(t + nsteps) in phase 0 on return, the
+ * same populations that cmlbm_run followed by cmlbm_gather_precollision gives.
+ * Errors: EINVAL (NULL, nsteps odd or negative). */
+cmlbm_status cmlbm_run_inplace(cmlbm_sim *sim, void *f, int nsteps, void *stream);
+
+/* cmlbm_macroscopic and cmlbm_totals of a buffer in phase 0 (pre-collision
+ * populations read in place rather than pulled). */
+cmlbm_status cmlbm_macroscopic_pre(cmlbm_sim *sim, const void *f_pre_buf, void *rho, void *u, void *stream);
+cmlbm_status cmlbm_totals_pre(cmlbm_sim *sim, const void *f_pre_buf, double out4[4], void *stream);
+
 /* Adjoint of one step, D3Q27 or D3Q15 (reverse streaming plus the transposed
  * Jacobian of the central-moment collision and force terms of Sec. 7 and
  * Appendix G).  Forward step n maps the pre-collision state fbar^n, pulled

@@ -54,6 +54,10 @@ def load_library():
         "cmlbm_import_populations": (i, [vp, vp, vp, vp]),
         "cmlbm_macroscopic": (i, [vp, vp, vp, vp, vp]),
         "cmlbm_totals": (i, [vp, vp, ctypes.POINTER(d), vp]),
+        "cmlbm_step_inplace": (i, [vp, vp, i, vp]),
+        "cmlbm_run_inplace": (i, [vp, vp, i, vp]),
+        "cmlbm_macroscopic_pre": (i, [vp, vp, vp, vp, vp]),
+        "cmlbm_totals_pre": (i, [vp, vp, ctypes.POINTER(d), vp]),
         "cmlbm_adjoint_step": (i, [vp, vp, vp, vp, vp, vp, vp]),
         "cmlbm_kinetic_energy_sum": (i, [vp, vp, ctypes.POINTER(d), vp]),
         "cmlbm_kinetic_energy_seed": (i, [vp, vp, d, vp, vp, vp]),
@@ -75,6 +79,7 @@ def exported_symbols():
             "cmlbm_set_force_field", "cmlbm_set_force_scale", "cmlbm_set_attractor_per_mass", "cmlbm_set_mask",
             "cmlbm_init_equilibrium", "cmlbm_step", "cmlbm_step_totals", "cmlbm_run", "cmlbm_gather_precollision",
             "cmlbm_export_populations", "cmlbm_import_populations", "cmlbm_macroscopic", "cmlbm_totals",
+            "cmlbm_step_inplace", "cmlbm_run_inplace", "cmlbm_macroscopic_pre", "cmlbm_totals_pre",
             "cmlbm_adjoint_step", "cmlbm_kinetic_energy_sum", "cmlbm_kinetic_energy_seed", "cmlbm_init_adjoint",
             "cmlbm_status_string", "cmlbm_last_error", "cmlbm_version"]
 
@@ -201,6 +206,24 @@ def cmlbm_macroscopic(h, f_post, rho, u, stream=None):
 def cmlbm_totals(h, f_post, stream=None):
     out = (ctypes.c_double * 4)()
     _check(load_library().cmlbm_totals(h, _ptr(f_post), out, _stream(stream)), h)
+    return [out[i] for i in range(4)]
+
+
+def cmlbm_step_inplace(h, f, parity, stream=None):
+    _check(load_library().cmlbm_step_inplace(h, _ptr(f), int(parity), _stream(stream)), h)
+
+
+def cmlbm_run_inplace(h, f, nsteps, stream=None):
+    _check(load_library().cmlbm_run_inplace(h, _ptr(f), int(nsteps), _stream(stream)), h)
+
+
+def cmlbm_macroscopic_pre(h, f_pre_buf, rho, u, stream=None):
+    _check(load_library().cmlbm_macroscopic_pre(h, _ptr(f_pre_buf), _ptr(rho), _ptr(u), _stream(stream)), h)
+
+
+def cmlbm_totals_pre(h, f_pre_buf, stream=None):
+    out = (ctypes.c_double * 4)()
+    _check(load_library().cmlbm_totals_pre(h, _ptr(f_pre_buf), out, _stream(stream)), h)
     return [out[i] for i in range(4)]
 
 
@@ -336,6 +359,25 @@ class Sim:
 
     def totals(self, f_post, stream=None):
         return cmlbm_totals(self.h, f_post, stream)
+
+    # in-place stepping (one buffer; phase 0 = pre-collision populations) --
+    def step_inplace(self, f, parity, stream=None):
+        cmlbm_step_inplace(self.h, f, parity, stream)
+
+    def run_inplace(self, f, nsteps, stream=None):
+        """nsteps (even) in-place steps; f holds the pre-collision state in
+        phase 0 before and after."""
+        cmlbm_run_inplace(self.h, f, nsteps, stream)
+        return f
+
+    def macroscopic_pre(self, f_pre_buf, stream=None):
+        rho = torch.empty((self.nz, self.ny, self.nx), dtype=self.real, device=self.device)
+        u = torch.empty((3, self.nz, self.ny, self.nx), dtype=self.real, device=self.device)
+        cmlbm_macroscopic_pre(self.h, f_pre_buf, rho, u, stream)
+        return rho, u
+
+    def totals_pre(self, f_pre_buf, stream=None):
+        return cmlbm_totals_pre(self.h, f_pre_buf, stream)
 
     def adjoint_step(self, f_post_prev, lam_next, lam, dLdF, dLdomega, stream=None):
         cmlbm_adjoint_step(self.h, f_post_prev, lam_next, lam, dLdF, dLdomega, stream)

@@ -320,25 +320,81 @@ cmlbm_status cmlbm_import_populations(cmlbm_sim* s, const void* f_soa, void* f_b
   return check_hip(s, e, "import_populations");
 }
 
-cmlbm_status cmlbm_macroscopic(cmlbm_sim* s, const void* f_post, void* rho, void* u, void* stream) {
-  if (!s) return CMLBM_EINVAL;
-  if (!f_post || !rho || !u) return fail(s, CMLBM_EINVAL, "NULL buffer");
-  hipError_t e = cmlbm::launch_macro(s->q, s->prec, make_aux<double>(s, f_post, rho, u),
-                                     make_aux<float>(s, f_post, rho, u), static_cast<hipStream_t>(stream));
+namespace {
+
+cmlbm_status macro_common(cmlbm_sim* s, const void* f, void* rho, void* u, bool pre, void* stream) {
+  if (!f || !rho || !u) return fail(s, CMLBM_EINVAL, "NULL buffer");
+  hipError_t e = cmlbm::launch_macro(s->q, s->prec, make_aux<double>(s, f, rho, u), make_aux<float>(s, f, rho, u),
+                                     pre, static_cast<hipStream_t>(stream));
   return check_hip(s, e, "macroscopic");
 }
 
-cmlbm_status cmlbm_totals(cmlbm_sim* s, const void* f_post, double out4[4], void* stream) {
-  if (!s) return CMLBM_EINVAL;
-  if (!f_post || !out4) return fail(s, CMLBM_EINVAL, "NULL buffer");
+cmlbm_status totals_common(cmlbm_sim* s, const void* f, double out4[4], bool pre, void* stream) {
+  if (!f || !out4) return fail(s, CMLBM_EINVAL, "NULL buffer");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  hipError_t e = cmlbm::launch_totals(s->q, s->prec, make_aux<double>(s, f_post, nullptr, nullptr),
-                                      make_aux<float>(s, f_post, nullptr, nullptr), s->totals_partials,
+  hipError_t e = cmlbm::launch_totals(s->q, s->prec, make_aux<double>(s, f, nullptr, nullptr),
+                                      make_aux<float>(s, f, nullptr, nullptr), pre, s->totals_partials,
                                       cmlbm::kTotalsBlocks, s->totals_out, st);
   if (e != hipSuccess) return check_hip(s, e, "totals");
   e = hipMemcpyAsync(out4, s->totals_out, sizeof(double) * 4, hipMemcpyDeviceToHost, st);
   if (e != hipSuccess) return check_hip(s, e, "totals copy");
   return check_hip(s, hipStreamSynchronize(st), "totals sync");
+}
+
+}  // namespace
+
+cmlbm_status cmlbm_macroscopic(cmlbm_sim* s, const void* f_post, void* rho, void* u, void* stream) {
+  if (!s) return CMLBM_EINVAL;
+  return macro_common(s, f_post, rho, u, false, stream);
+}
+
+cmlbm_status cmlbm_totals(cmlbm_sim* s, const void* f_post, double out4[4], void* stream) {
+  if (!s) return CMLBM_EINVAL;
+  return totals_common(s, f_post, out4, false, stream);
+}
+
+cmlbm_status cmlbm_step_inplace(cmlbm_sim* s, void* f, int parity, void* stream) {
+  if (!s) return CMLBM_EINVAL;
+  if (!f) return fail(s, CMLBM_EINVAL, "NULL population buffer");
+  if (parity != 0 && parity != 1) return fail(s, CMLBM_EINVAL, "parity must be 0 or 1");
+  cmlbm::StepArgs<double> a64{};
+  cmlbm::StepArgs<float> a32{};
+  if (s->prec == CMLBM_F64) {
+    a64.g = s->g;
+    a64.fout = f;
+    a64.mask = s->mask;
+    a64.force = make_force<double>(s);
+    a64.rates = make_rates<double>(s);
+  } else {
+    a32.g = s->g;
+    a32.fout = f;
+    a32.mask = s->mask;
+    a32.force = make_force<float>(s);
+    a32.rates = make_rates<float>(s);
+  }
+  return check_hip(s, cmlbm::launch_step_inplace(s->q, s->prec, a64, a32, parity, static_cast<hipStream_t>(stream)),
+                   "step_inplace");
+}
+
+cmlbm_status cmlbm_run_inplace(cmlbm_sim* s, void* f, int nsteps, void* stream) {
+  if (!s) return CMLBM_EINVAL;
+  if (!f) return fail(s, CMLBM_EINVAL, "NULL population buffer");
+  if (nsteps < 0 || (nsteps & 1)) return fail(s, CMLBM_EINVAL, "nsteps must be even and >= 0");
+  for (int n = 0; n < nsteps; ++n) {
+    cmlbm_status st = cmlbm_step_inplace(s, f, n & 1, stream);
+    if (st != CMLBM_OK) return st;
+  }
+  return ok(s);
+}
+
+cmlbm_status cmlbm_macroscopic_pre(cmlbm_sim* s, const void* f_pre_buf, void* rho, void* u, void* stream) {
+  if (!s) return CMLBM_EINVAL;
+  return macro_common(s, f_pre_buf, rho, u, true, stream);
+}
+
+cmlbm_status cmlbm_totals_pre(cmlbm_sim* s, const void* f_pre_buf, double out4[4], void* stream) {
+  if (!s) return CMLBM_EINVAL;
+  return totals_common(s, f_pre_buf, out4, true, stream);
 }
 
 cmlbm_status cmlbm_adjoint_step(cmlbm_sim* s, const void* f_post_prev, const void* lam_next, void* lam,

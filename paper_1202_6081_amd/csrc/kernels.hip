@@ -257,16 +257,17 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t array_rsrc(void* base, uint32_
   return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, int(bytes), 0x00020000);
 }
 
-// voff: per-lane byte offset; soff: wave-uniform byte offset.
-template <typename T>
+// voff: per-lane byte offset; soff: wave-uniform byte offset; AUX: cache
+// policy bits (kStoreAux streams past the caches; 0 keeps the line).
+template <int AUX = kStoreAux, typename T>
 __device__ __forceinline__ void buf_store(T v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
   if constexpr (sizeof(T) == 4) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, kStoreAux);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, AUX);
   } else if constexpr (sizeof(T) == 8) {
     typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, kStoreAux);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, AUX);
   } else {
-    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, voff, soff, kStoreAux);
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, voff, soff, AUX);
   }
 }
 
@@ -296,15 +297,10 @@ __device__ __forceinline__ void add_node_totals(const R (&f)[Q], R Fx, R Fy, R F
 template <int NV>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double* sh /* [NV][8] */);
 
-// The two ends of one node's update: pull + force, and the store.
-template <int Q, class ST, bool MASK>
-__device__ __forceinline__ void load_node(const StepArgs<typename ST::R>& args, const Geom& g, uint32_t row,
-                                          uint32_t x, typename ST::R (&f)[Q], typename ST::R& Fx,
-                                          typename ST::R& Fy, typename ST::R& Fz) {
-  using R = typename ST::R;
-  const Coord c{int(x), int(row % uint32_t(g.ny)), int(row / uint32_t(g.ny))};
-  const Stencil st(g, c, +1);
-  pull<Q, ST, MASK, true>(static_cast<const typename ST::T*>(args.fin), g, args.mask, st, row, x, f);
+// Body force at node (row, x), row = z*ny + y uniform across the wavefront.
+template <typename R>
+__device__ __forceinline__ void force_row(const StepArgs<R>& args, const Geom& g, uint32_t row, uint32_t x, R& Fx,
+                                          R& Fy, R& Fz) {
   if (args.force.field) {
     const R* Ff = args.force.field + uint64_t(row) * uint32_t(g.nx);
     const R sc = R(args.force.scale);
@@ -316,6 +312,17 @@ __device__ __forceinline__ void load_node(const StepArgs<typename ST::R>& args, 
     Fy = R(args.force.uni[1]);
     Fz = R(args.force.uni[2]);
   }
+}
+
+// The two ends of one node's update: pull + force, and the store.
+template <int Q, class ST, bool MASK>
+__device__ __forceinline__ void load_node(const StepArgs<typename ST::R>& args, const Geom& g, uint32_t row,
+                                          uint32_t x, typename ST::R (&f)[Q], typename ST::R& Fx,
+                                          typename ST::R& Fy, typename ST::R& Fz) {
+  const Coord c{int(x), int(row % uint32_t(g.ny)), int(row / uint32_t(g.ny))};
+  const Stencil st(g, c, +1);
+  pull<Q, ST, MASK, true>(static_cast<const typename ST::T*>(args.fin), g, args.mask, st, row, x, f);
+  force_row(args, g, row, x, Fx, Fy, Fz);
 }
 
 // Store of node (row, x); a wavefront covers one 64-node block of the row, so
@@ -369,6 +376,116 @@ __global__ __launch_bounds__(CMLBM_STEP_BLOCK) void k_step(StepArgs<typename ST:
 }
 
 // ---------------------------------------------------------------------------
+// In-place step: one population buffer (the AA pattern of Bailey, Myre, Walsh,
+// Lilja and Saar, 2009)
+// ---------------------------------------------------------------------------
+// The buffer alternates between two phases of the same blocked rows:
+//   phase 0: slot a of node x holds the pre-collision fbar_a(x);
+//   phase 1: slot abar of node x holds the post-collision fbar~_a(x).
+// Phase 0 -> 1 (ODD = false) reads and writes only the node's own slots.
+// Phase 1 -> 0 (ODD = true) takes fbar_a(x) = fbar~_a(x - e_a) from slot abar
+// of x - e_a (when x - e_a is solid, bounce-back gives fbar~_abar(x), which is
+// slot a of x), collides, and moves fbar~_a(x), the next fbar_a(x + e_a), into
+// slot a of x + e_a (when x + e_a is solid, it returns as fbar_abar(x) into
+// slot abar of x).  Writing b = abar in the second list shows that the slots a
+// node writes are exactly the slots it read, and a slot (y, c) of a fluid node
+// y is read by y - e_c alone (or by y itself when y - e_c is solid), so no two
+// nodes touch one slot: the update is race-free in place.  Solid nodes' slots
+// are never touched.
+// Its stores keep the written lines in the caches (measured faster here than
+// streaming stores: the lines were just read, and the scattered phase writes
+// each line in two parts).
+constexpr int kInplaceAux = 0;
+
+template <int Q, class ST, bool MASK, bool ODD>
+__global__ __launch_bounds__(CMLBM_STEP_BLOCK) void k_step_inplace(StepArgs<typename ST::R> args) {
+  using R = typename ST::R;
+  using T = typename ST::T;
+  constexpr uint32_t sz = uint32_t(sizeof(T));
+  const Geom g = args.g;
+  const uint32_t nx = uint32_t(g.nx);
+  const uint32_t nseg = (nx + blockDim.x - 1) / blockDim.x;
+  const uint32_t L = step_block_id();
+  const uint32_t row = L / nseg;                  // uniform over the block
+  const uint32_t x = (L - row * nseg) * blockDim.x + threadIdx.x;
+  if (x >= nx || (MASK && args.mask[row * nx + x])) return;
+  T* const buf = static_cast<T*>(args.fout);
+  const uint32_t rowQ = nx * uint32_t(Q);
+  const uint32_t b0 = __builtin_amdgcn_readfirstlane(x & ~63u);
+  const uint32_t lenB = min(64u, nx - b0) * sz;            // wave-uniform direction stride
+  const uint32_t cbase = (b0 * uint32_t(Q) + (x - b0)) * sz;
+  const char* own = reinterpret_cast<const char*>(buf + uint64_t(row) * rowQ);
+  R f[Q];
+  if constexpr (!ODD) {
+#pragma unroll
+    for (int a = 0; a < Q; ++a) f[a] = decode<ST, Q>(ldb<T>(own + uint32_t(a) * lenB, cbase), a);
+    R Fx, Fy, Fz;
+    force_row(args, g, row, x, Fx, Fy, Fz);
+    collide<Q>(f, Fx, Fy, Fz, args.rates);
+    const __amdgpu_buffer_rsrc_t rs = array_rsrc(buf + uint64_t(row) * rowQ, rowQ * sz);
+#pragma unroll
+    for (int a = 0; a < Q; ++a) buf_store<kInplaceAux>(encode<ST, Q>(f[a], a), rs, cbase, uint32_t(opposite<Q>(a)) * lenB);
+  } else {
+    const Coord c{int(x), int(row % uint32_t(g.ny)), int(row / uint32_t(g.ny))};
+    const Stencil st(g, c, +1);      // row[ey+1][ez+1], xs[ex+1]: x - e; index with -e for x + e
+    uint32_t nbase[3], nlen[3];      // blocked offsets of x - 1 ([2]) and x + 1 ([0]), and their block strides
+#pragma unroll
+    for (int i = 0; i < 3; i += 2) {
+      const uint32_t xs = st.xs[i];
+      const uint32_t bb = xs & ~63u;
+      nbase[i] = (bb * uint32_t(Q) + (xs - bb)) * sz;
+      nlen[i] = min(64u, nx - bb) * sz;
+    }
+    uint32_t solid = 0;              // bit a: x - e_a is solid
+    if constexpr (MASK) {
+#pragma unroll
+      for (int a = 0; a < Q; ++a) solid |= uint32_t(args.mask[st.node(Lattice<Q>::e(a), nx)] != 0) << a;
+    }
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      const Vel e = Lattice<Q>::e(a);
+      const char* rp = reinterpret_cast<const char*>(buf + uint64_t(st.row[e.y + 1][e.z + 1]) * rowQ);
+      const uint32_t ab = uint32_t(opposite<Q>(a));
+      T v;
+      if (MASK && ((solid >> a) & 1u))
+        v = ldb<T>(own + uint32_t(a) * lenB, cbase);
+      else if (e.x == 0)
+        v = ldb<T>(rp + ab * lenB, cbase);
+      else
+        v = ldb<T>(rp, nbase[e.x + 1] + ab * nlen[e.x + 1]);
+      f[a] = decode<ST, Q>(v, a);
+    }
+    R Fx, Fy, Fz;
+    force_row(args, g, row, x, Fx, Fy, Fz);
+    collide<Q>(f, Fx, Fy, Fz, args.rates);
+    if constexpr (MASK) {
+      // Finish the collision before the per-lane store branches: otherwise the
+      // compiler sinks its last operations into them, where multiplies and adds
+      // in different blocks are not fused, and the rounding departs from the
+      // two-buffer step's.  (Empty statements: no instruction is emitted.)
+#pragma unroll
+      for (int a = 0; a < Q; ++a) asm volatile("" : "+v"(f[a]));
+    }
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      const Vel e = Lattice<Q>::e(a);
+      const int ab = opposite<Q>(a);
+      const T v = encode<ST, Q>(f[a], a);
+      if (MASK && ((solid >> ab) & 1u)) {            // x + e_a = x - e_abar is solid
+        buf_store<kInplaceAux>(v, array_rsrc(buf + uint64_t(row) * rowQ, rowQ * sz), cbase, uint32_t(ab) * lenB);
+      } else {
+        const __amdgpu_buffer_rsrc_t rt =
+            array_rsrc(buf + uint64_t(st.row[1 - e.y][1 - e.z]) * rowQ, rowQ * sz);
+        if (e.x == 0)
+          buf_store<kInplaceAux>(v, rt, cbase, uint32_t(a) * lenB);
+        else
+          buf_store<kInplaceAux>(v, rt, nbase[1 - e.x] + uint32_t(a) * nlen[1 - e.x], 0u);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Read-out kernels (grid-stride over nodes)
 // ---------------------------------------------------------------------------
 // Observable pre-collision state fbar(x): full populations, compute type,
@@ -414,8 +531,33 @@ __global__ __launch_bounds__(256) void k_convert(Geom g, const void* in, void* o
   }
 }
 
+// Populations of node n read from its own slots: the pre-collision state of a
+// buffer in phase 0 of the in-place scheme.
+template <int Q, class ST>
+__device__ __forceinline__ void load_own(const typename ST::T* buf, const Geom& g, uint32_t n,
+                                         typename ST::R (&f)[Q]) {
+  const uint32_t row = n / uint32_t(g.nx), x = n - row * uint32_t(g.nx);
+  const typename ST::T* rp = buf + uint64_t(row) * uint64_t(g.nx) * Q;
+#pragma unroll
+  for (int a = 0; a < Q; ++a) f[a] = decode<ST, Q>(ld32(rp, in_row<Q>(uint32_t(g.nx), a, x)), a);
+}
+
+// Pre-collision populations of fluid node n: pulled from a post-collision
+// buffer, or (PRE) read in place from a pre-collision one.
+template <int Q, class ST, bool MASK, bool PRE>
+__device__ __forceinline__ void node_state(const AuxArgs<typename ST::R>& args, uint32_t n, Coord c,
+                                           typename ST::R (&f)[Q]) {
+  const auto* in = static_cast<const typename ST::T*>(args.in0);
+  if constexpr (PRE) {
+    load_own<Q, ST>(in, args.g, n, f);
+  } else {
+    const Stencil st(args.g, c, +1);
+    pull<Q, ST, MASK>(in, args.g, args.mask, st, n / uint32_t(args.g.nx), uint32_t(c.x), f);
+  }
+}
+
 // rho and u (Eqs. densitycalculation, velocitycalculation), zero at solid nodes.
-template <int Q, class ST, bool MASK>
+template <int Q, class ST, bool MASK, bool PRE>
 __global__ __launch_bounds__(256) void k_macro(AuxArgs<typename ST::R> args) {
   using R = typename ST::R;
   const Geom g = args.g;
@@ -427,11 +569,8 @@ __global__ __launch_bounds__(256) void k_macro(AuxArgs<typename ST::R> args) {
       u_out[n] = u_out[g.N + n] = u_out[2 * g.N + n] = R(0);
       continue;
     }
-    const Coord c = coord_of(g, n);
-    const Stencil st(g, c, +1);
     R f[Q];
-    pull<Q, ST, MASK>(static_cast<const typename ST::T*>(args.in0), g, args.mask, st, n / uint32_t(g.nx),
-                      uint32_t(c.x), f);
+    node_state<Q, ST, MASK, PRE>(args, n, coord_of(g, n), f);
     R Fx, Fy, Fz;
     force_at(args.force, g.N, n, Fx, Fy, Fz);
     R rho = R(0), jx = R(0), jy = R(0), jz = R(0);
@@ -476,18 +615,15 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* sh /* [NV][8]
 }
 
 // FP64 partial sums of (rho, j_x, j_y, j_z), j = sum fbar e + F/2, per block.
-template <int Q, class ST, bool MASK>
+template <int Q, class ST, bool MASK, bool PRE>
 __global__ __launch_bounds__(256) void k_totals(AuxArgs<typename ST::R> args, double* partials) {
   using R = typename ST::R;
   const Geom g = args.g;
   double acc[4] = {0, 0, 0, 0};
   for (uint32_t n = blockIdx.x * blockDim.x + threadIdx.x; n < g.N; n += gridDim.x * blockDim.x) {
     if (MASK && args.mask[n]) continue;
-    const Coord c = coord_of(g, n);
-    const Stencil st(g, c, +1);
     R f[Q];
-    pull<Q, ST, MASK>(static_cast<const typename ST::T*>(args.in0), g, args.mask, st, n / uint32_t(g.nx),
-                      uint32_t(c.x), f);
+    node_state<Q, ST, MASK, PRE>(args, n, coord_of(g, n), f);
     R Fx, Fy, Fz;
     force_at(args.force, g.N, n, Fx, Fy, Fz);
 #pragma unroll
@@ -950,6 +1086,24 @@ hipError_t step_impl(const StepArgs<typename ST::R>& a, hipStream_t st) {
 }
 
 template <int Q, class ST>
+hipError_t inplace_impl(const StepArgs<typename ST::R>& a, int parity, hipStream_t st) {
+  const int bx = step_block(a.g);
+  const dim3 grid = step_grid(a.g, bx);
+  if (parity == 0) {
+    if (a.mask)
+      hipLaunchKernelGGL((k_step_inplace<Q, ST, true, false>), grid, dim3(bx), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_step_inplace<Q, ST, false, false>), grid, dim3(bx), 0, st, a);
+  } else {
+    if (a.mask)
+      hipLaunchKernelGGL((k_step_inplace<Q, ST, true, true>), grid, dim3(bx), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_step_inplace<Q, ST, false, true>), grid, dim3(bx), 0, st, a);
+  }
+  return hipGetLastError();
+}
+
+template <int Q, class ST>
 hipError_t gather_impl(const AuxArgs<typename ST::R>& a, hipStream_t st) {
   if (a.mask)
     hipLaunchKernelGGL((k_gather<Q, ST, true>), dim3(aux_grid(a.g)), dim3(kBlock), 0, st, a);
@@ -968,21 +1122,30 @@ hipError_t convert_impl(const Geom& g, const void* in, void* out, bool to_soa, h
 }
 
 template <int Q, class ST>
-hipError_t macro_impl(const AuxArgs<typename ST::R>& a, hipStream_t st) {
-  if (a.mask)
-    hipLaunchKernelGGL((k_macro<Q, ST, true>), dim3(aux_grid(a.g)), dim3(kBlock), 0, st, a);
+hipError_t macro_impl(const AuxArgs<typename ST::R>& a, bool pre, hipStream_t st) {
+  const dim3 grid(aux_grid(a.g)), block(kBlock);
+  if (pre && a.mask)
+    hipLaunchKernelGGL((k_macro<Q, ST, true, true>), grid, block, 0, st, a);
+  else if (pre)
+    hipLaunchKernelGGL((k_macro<Q, ST, false, true>), grid, block, 0, st, a);
+  else if (a.mask)
+    hipLaunchKernelGGL((k_macro<Q, ST, true, false>), grid, block, 0, st, a);
   else
-    hipLaunchKernelGGL((k_macro<Q, ST, false>), dim3(aux_grid(a.g)), dim3(kBlock), 0, st, a);
+    hipLaunchKernelGGL((k_macro<Q, ST, false, false>), grid, block, 0, st, a);
   return hipGetLastError();
 }
 
 template <int Q, class ST>
-hipError_t totals_impl(const AuxArgs<typename ST::R>& a, double* partials, int nblk, double* out4,
+hipError_t totals_impl(const AuxArgs<typename ST::R>& a, bool pre, double* partials, int nblk, double* out4,
                        hipStream_t st) {
-  if (a.mask)
-    hipLaunchKernelGGL((k_totals<Q, ST, true>), dim3(nblk), dim3(kBlock), 0, st, a, partials);
+  if (pre && a.mask)
+    hipLaunchKernelGGL((k_totals<Q, ST, true, true>), dim3(nblk), dim3(kBlock), 0, st, a, partials);
+  else if (pre)
+    hipLaunchKernelGGL((k_totals<Q, ST, false, true>), dim3(nblk), dim3(kBlock), 0, st, a, partials);
+  else if (a.mask)
+    hipLaunchKernelGGL((k_totals<Q, ST, true, false>), dim3(nblk), dim3(kBlock), 0, st, a, partials);
   else
-    hipLaunchKernelGGL((k_totals<Q, ST, false>), dim3(nblk), dim3(kBlock), 0, st, a, partials);
+    hipLaunchKernelGGL((k_totals<Q, ST, false, false>), dim3(nblk), dim3(kBlock), 0, st, a, partials);
   hipLaunchKernelGGL(k_reduce_rows, dim3(4), dim3(kBlock), 0, st, partials, nblk, 4, out4, 0);
   return hipGetLastError();
 }
@@ -1043,6 +1206,16 @@ hipError_t launch_step(int q, int prec, const StepArgs<double>& a64, const StepA
                  (step_impl<15, StF16>(a32, st)), (step_impl<15, StBF16>(a32, st)))
 }
 
+hipError_t launch_step_inplace(int q, int prec, const StepArgs<double>& a64, const StepArgs<float>& a32, int parity,
+                              hipStream_t st) {
+  if (q == 27) {
+    CMLBM_DISPATCH(prec, (inplace_impl<27, StF64>(a64, parity, st)), (inplace_impl<27, StF32>(a32, parity, st)),
+                   (inplace_impl<27, StF16>(a32, parity, st)), (inplace_impl<27, StBF16>(a32, parity, st)))
+  }
+  CMLBM_DISPATCH(prec, (inplace_impl<15, StF64>(a64, parity, st)), (inplace_impl<15, StF32>(a32, parity, st)),
+                 (inplace_impl<15, StF16>(a32, parity, st)), (inplace_impl<15, StBF16>(a32, parity, st)))
+}
+
 hipError_t launch_gather(int q, int prec, const AuxArgs<double>& a64, const AuxArgs<float>& a32, hipStream_t st) {
   if (q == 27) {
     CMLBM_DISPATCH(prec, (gather_impl<27, StF64>(a64, st)), (gather_impl<27, StF32>(a32, st)),
@@ -1065,27 +1238,28 @@ hipError_t launch_convert(int q, int prec, const Geom& g, const void* in, void* 
                  (convert_impl<15, StBF16>(g, in, out, to_soa, st)))
 }
 
-hipError_t launch_macro(int q, int prec, const AuxArgs<double>& a64, const AuxArgs<float>& a32, hipStream_t st) {
+hipError_t launch_macro(int q, int prec, const AuxArgs<double>& a64, const AuxArgs<float>& a32, bool pre,
+                        hipStream_t st) {
   if (q == 27) {
-    CMLBM_DISPATCH(prec, (macro_impl<27, StF64>(a64, st)), (macro_impl<27, StF32>(a32, st)),
-                   (macro_impl<27, StF16>(a32, st)), (macro_impl<27, StBF16>(a32, st)))
+    CMLBM_DISPATCH(prec, (macro_impl<27, StF64>(a64, pre, st)), (macro_impl<27, StF32>(a32, pre, st)),
+                   (macro_impl<27, StF16>(a32, pre, st)), (macro_impl<27, StBF16>(a32, pre, st)))
   }
-  CMLBM_DISPATCH(prec, (macro_impl<15, StF64>(a64, st)), (macro_impl<15, StF32>(a32, st)),
-                 (macro_impl<15, StF16>(a32, st)), (macro_impl<15, StBF16>(a32, st)))
+  CMLBM_DISPATCH(prec, (macro_impl<15, StF64>(a64, pre, st)), (macro_impl<15, StF32>(a32, pre, st)),
+                 (macro_impl<15, StF16>(a32, pre, st)), (macro_impl<15, StBF16>(a32, pre, st)))
 }
 
-hipError_t launch_totals(int q, int prec, const AuxArgs<double>& a64, const AuxArgs<float>& a32, double* partials,
-                         int nblk, double* out4, hipStream_t st) {
+hipError_t launch_totals(int q, int prec, const AuxArgs<double>& a64, const AuxArgs<float>& a32, bool pre,
+                         double* partials, int nblk, double* out4, hipStream_t st) {
   if (q == 27) {
-    CMLBM_DISPATCH(prec, (totals_impl<27, StF64>(a64, partials, nblk, out4, st)),
-                   (totals_impl<27, StF32>(a32, partials, nblk, out4, st)),
-                   (totals_impl<27, StF16>(a32, partials, nblk, out4, st)),
-                   (totals_impl<27, StBF16>(a32, partials, nblk, out4, st)))
+    CMLBM_DISPATCH(prec, (totals_impl<27, StF64>(a64, pre, partials, nblk, out4, st)),
+                   (totals_impl<27, StF32>(a32, pre, partials, nblk, out4, st)),
+                   (totals_impl<27, StF16>(a32, pre, partials, nblk, out4, st)),
+                   (totals_impl<27, StBF16>(a32, pre, partials, nblk, out4, st)))
   }
-  CMLBM_DISPATCH(prec, (totals_impl<15, StF64>(a64, partials, nblk, out4, st)),
-                 (totals_impl<15, StF32>(a32, partials, nblk, out4, st)),
-                 (totals_impl<15, StF16>(a32, partials, nblk, out4, st)),
-                 (totals_impl<15, StBF16>(a32, partials, nblk, out4, st)))
+  CMLBM_DISPATCH(prec, (totals_impl<15, StF64>(a64, pre, partials, nblk, out4, st)),
+                 (totals_impl<15, StF32>(a32, pre, partials, nblk, out4, st)),
+                 (totals_impl<15, StF16>(a32, pre, partials, nblk, out4, st)),
+                 (totals_impl<15, StBF16>(a32, pre, partials, nblk, out4, st)))
 }
 
 hipError_t launch_init(int q, int prec, const Geom& g, const void* rho0, const void* u0, const ForceArgs<double>& f64,

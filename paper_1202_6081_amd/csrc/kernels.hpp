@@ -68,9 +68,16 @@ hipError_t launch_gather(int q, int prec, const AuxArgs<double>& a64, const AuxA
 // Population buffer (blocked layout) <-> full populations in compute type,
 // structure of arrays [Q][N]; to_soa selects the direction.
 hipError_t launch_convert(int q, int prec, const Geom& g, const void* in, void* out, bool to_soa, hipStream_t st);
-hipError_t launch_macro(int q, int prec, const AuxArgs<double>& a64, const AuxArgs<float>& a32, hipStream_t st);
-hipError_t launch_totals(int q, int prec, const AuxArgs<double>& a64, const AuxArgs<float>& a32, double* partials,
-                         int nblk, double* out4, hipStream_t st);
+// pre: the buffer holds pre-collision populations (phase 0 of the in-place
+// step) and is read in place instead of pulled.
+hipError_t launch_macro(int q, int prec, const AuxArgs<double>& a64, const AuxArgs<float>& a32, bool pre,
+                        hipStream_t st);
+hipError_t launch_totals(int q, int prec, const AuxArgs<double>& a64, const AuxArgs<float>& a32, bool pre,
+                         double* partials, int nblk, double* out4, hipStream_t st);
+// One in-place step on the buffer a.fout (a.fin unused); parity = phase of the
+// buffer on entry (0 or 1).
+hipError_t launch_step_inplace(int q, int prec, const StepArgs<double>& a64, const StepArgs<float>& a32, int parity,
+                               hipStream_t st);
 hipError_t launch_init(int q, int prec, const Geom& g, const void* rho0, const void* u0, const ForceArgs<double>& f64,
                        const ForceArgs<float>& f32, const uint8_t* mask, void* fpre, void* fpost, hipStream_t st);
 hipError_t launch_adjoint(int q, int prec, const AdjArgs<double>& a64, const AdjArgs<float>& a32, double* partials,
