@@ -199,6 +199,15 @@ cmlbm_status cmlbm_totals(cmlbm_sim *sim, const void *f_post, double out4[4], vo
  * on one buffer must be ordered (one stream). */
 cmlbm_status cmlbm_step_inplace(cmlbm_sim *sim, void *f, int parity, void *stream);
 
+/* The initial state of cmlbm_init_equilibrium, fbar(x, 0), written straight
+ * into an in-place buffer f_dev in phase 0 (population storage type, blocked
+ * rows): the same values as cmlbm_import_populations of its f_pre, without
+ * the full-size "real" intermediate.  Solid nodes get zero populations (the
+ * 16-bit formats store the rounded deviation -w_a).
+ * Errors: EINVAL (NULL). */
+cmlbm_status cmlbm_init_equilibrium_inplace(cmlbm_sim *sim, const void *rho_dev, const void *u_dev, void *f_dev,
+                                            void *stream);
+
 /* nsteps in-place steps (parities 0, 1, 0, 1, ...): f holds the pre-collision
  * fbar(t) in phase 0 on entry and fbar(t + nsteps) in phase 0 on return, the
  * same populations that cmlbm_run followed by cmlbm_gather_precollision gives.

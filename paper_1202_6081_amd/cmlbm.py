@@ -54,6 +54,7 @@ def load_library():
         "cmlbm_import_populations": (i, [vp, vp, vp, vp]),
         "cmlbm_macroscopic": (i, [vp, vp, vp, vp, vp]),
         "cmlbm_totals": (i, [vp, vp, ctypes.POINTER(d), vp]),
+        "cmlbm_init_equilibrium_inplace": (i, [vp, vp, vp, vp, vp]),
         "cmlbm_step_inplace": (i, [vp, vp, i, vp]),
         "cmlbm_run_inplace": (i, [vp, vp, i, vp]),
         "cmlbm_macroscopic_pre": (i, [vp, vp, vp, vp, vp]),
@@ -79,7 +80,7 @@ def exported_symbols():
             "cmlbm_set_force_field", "cmlbm_set_force_scale", "cmlbm_set_attractor_per_mass", "cmlbm_set_mask",
             "cmlbm_init_equilibrium", "cmlbm_step", "cmlbm_step_totals", "cmlbm_run", "cmlbm_gather_precollision",
             "cmlbm_export_populations", "cmlbm_import_populations", "cmlbm_macroscopic", "cmlbm_totals",
-            "cmlbm_step_inplace", "cmlbm_run_inplace", "cmlbm_macroscopic_pre", "cmlbm_totals_pre",
+            "cmlbm_init_equilibrium_inplace", "cmlbm_step_inplace", "cmlbm_run_inplace", "cmlbm_macroscopic_pre", "cmlbm_totals_pre",
             "cmlbm_adjoint_step", "cmlbm_kinetic_energy_sum", "cmlbm_kinetic_energy_seed", "cmlbm_init_adjoint",
             "cmlbm_status_string", "cmlbm_last_error", "cmlbm_version"]
 
@@ -207,6 +208,10 @@ def cmlbm_totals(h, f_post, stream=None):
     out = (ctypes.c_double * 4)()
     _check(load_library().cmlbm_totals(h, _ptr(f_post), out, _stream(stream)), h)
     return [out[i] for i in range(4)]
+
+
+def cmlbm_init_equilibrium_inplace(h, rho, u, f, stream=None):
+    _check(load_library().cmlbm_init_equilibrium_inplace(h, _ptr(rho), _ptr(u), _ptr(f), _stream(stream)), h)
 
 
 def cmlbm_step_inplace(h, f, parity, stream=None):
@@ -361,6 +366,14 @@ class Sim:
         return cmlbm_totals(self.h, f_post, stream)
 
     # in-place stepping (one buffer; phase 0 = pre-collision populations) --
+    def init_equilibrium_inplace(self, rho, u, f=None, stream=None):
+        """fbar(x, 0) into an in-place buffer (phase 0)."""
+        rho = rho.to(device=self.device, dtype=self.real).contiguous()
+        u = u.to(device=self.device, dtype=self.real).contiguous()
+        f = self.populations() if f is None else f
+        cmlbm_init_equilibrium_inplace(self.h, rho, u, f, stream)
+        return f
+
     def step_inplace(self, f, parity, stream=None):
         cmlbm_step_inplace(self.h, f, parity, stream)
 

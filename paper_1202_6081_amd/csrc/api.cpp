@@ -231,6 +231,16 @@ cmlbm_status cmlbm_init_equilibrium(cmlbm_sim* s, const void* rho_dev, const voi
   return check_hip(s, e, "init_equilibrium");
 }
 
+cmlbm_status cmlbm_init_equilibrium_inplace(cmlbm_sim* s, const void* rho_dev, const void* u_dev, void* f_dev,
+                                            void* stream) {
+  if (!s) return CMLBM_EINVAL;
+  if (!rho_dev || !u_dev || !f_dev) return fail(s, CMLBM_EINVAL, "NULL buffer");
+  hipError_t e = cmlbm::launch_init(s->q, s->prec, s->g, rho_dev, u_dev, make_force<double>(s),
+                                    make_force<float>(s), s->mask, f_dev, nullptr,
+                                    static_cast<hipStream_t>(stream));
+  return check_hip(s, e, "init_equilibrium_inplace");
+}
+
 namespace {
 
 cmlbm_status step_common(cmlbm_sim* s, const void* f_in, void* f_out, double* totals_dev, void* stream) {

@@ -683,9 +683,12 @@ __global__ __launch_bounds__(256) void k_reduce_chunks(const double* rows, uint6
 // Initial condition: fbar(x, 0) = f^eq(rho0, u0) - S/2, then the inverse pull
 // into the post-collision buffer so that the first step's pull reproduces it.
 // ---------------------------------------------------------------------------
-template <int Q, typename R, typename FT>
-__global__ __launch_bounds__(256) void k_initial_pre(Geom g, const R* rho0, const R* u0, ForceArgs<FT> force,
-                                                     const uint8_t* mask, R* fpre) {
+// fpre: with BLOCKED, a population buffer (storage type, blocked rows: phase 0
+// of the in-place step); otherwise "real" structure of arrays [Q][N].
+template <int Q, class ST, bool BLOCKED, typename FT>
+__global__ __launch_bounds__(256) void k_initial_pre(Geom g, const typename ST::R* rho0, const typename ST::R* u0,
+                                                     ForceArgs<FT> force, const uint8_t* mask, void* fpre) {
+  using R = typename ST::R;
   for (uint32_t n = blockIdx.x * blockDim.x + threadIdx.x; n < g.N; n += gridDim.x * blockDim.x) {
     R f[Q];
     if (mask && mask[n]) {
@@ -718,8 +721,15 @@ __global__ __launch_bounds__(256) void k_initial_pre(Geom g, const R* rho0, cons
         initial15(rho, ux, uy, uz, Fx, Fy, Fz, f);
       }
     }
+    if constexpr (BLOCKED) {
+      const uint32_t row = n / uint32_t(g.nx), x = n - row * uint32_t(g.nx);
+      typename ST::T* rp = static_cast<typename ST::T*>(fpre) + uint64_t(row) * uint64_t(g.nx) * Q;
 #pragma unroll
-    for (int a = 0; a < Q; ++a) fpre[uint64_t(a) * g.N + n] = f[a];
+      for (int a = 0; a < Q; ++a) rp[in_row<Q>(uint32_t(g.nx), a, x)] = encode<ST, Q>(f[a], a);
+    } else {
+#pragma unroll
+      for (int a = 0; a < Q; ++a) static_cast<R*>(fpre)[uint64_t(a) * g.N + n] = f[a];
+    }
   }
 }
 
@@ -1154,8 +1164,13 @@ template <int Q, class ST>
 hipError_t init_impl(const Geom& g, const void* rho0, const void* u0, const ForceArgs<typename ST::R>& force,
                      const uint8_t* mask, void* fpre, void* fpost, hipStream_t st) {
   using R = typename ST::R;
-  hipLaunchKernelGGL((k_initial_pre<Q, R, R>), dim3(aux_grid(g)), dim3(kBlock), 0, st, g,
-                     static_cast<const R*>(rho0), static_cast<const R*>(u0), force, mask, static_cast<R*>(fpre));
+  if (!fpost) {      // phase-0 in-place buffer only
+    hipLaunchKernelGGL((k_initial_pre<Q, ST, true, R>), dim3(aux_grid(g)), dim3(kBlock), 0, st, g,
+                       static_cast<const R*>(rho0), static_cast<const R*>(u0), force, mask, fpre);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL((k_initial_pre<Q, ST, false, R>), dim3(aux_grid(g)), dim3(kBlock), 0, st, g,
+                     static_cast<const R*>(rho0), static_cast<const R*>(u0), force, mask, fpre);
   if (mask)
     hipLaunchKernelGGL((k_scatter_post<Q, ST, true>), dim3(aux_grid(g)), dim3(kBlock), 0, st, g,
                        static_cast<const R*>(fpre), mask, static_cast<typename ST::T*>(fpost));

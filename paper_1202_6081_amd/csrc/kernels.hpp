@@ -78,6 +78,7 @@ hipError_t launch_totals(int q, int prec, const AuxArgs<double>& a64, const AuxA
 // buffer on entry (0 or 1).
 hipError_t launch_step_inplace(int q, int prec, const StepArgs<double>& a64, const StepArgs<float>& a32, int parity,
                                hipStream_t st);
+// fpost == nullptr: fpre is an in-place buffer in phase 0 (storage type, blocked rows).
 hipError_t launch_init(int q, int prec, const Geom& g, const void* rho0, const void* u0, const ForceArgs<double>& f64,
                        const ForceArgs<float>& f32, const uint8_t* mask, void* fpre, void* fpost, hipStream_t st);
 hipError_t launch_adjoint(int q, int prec, const AdjArgs<double>& a64, const AdjArgs<float>& a32, double* partials,

@@ -13,7 +13,7 @@ import torch
 
 import lbm_inputs as inp
 from gpu_helpers import gpu_setup, lib, oracle_run, rel_err, to_dev
-from oracle import lbm
+from oracle import collision, lbm
 from oracle.lattice import LATTICES
 
 pytestmark = pytest.mark.gpu
@@ -188,3 +188,94 @@ def test_inplace_errors_and_zero_steps():
     assert lib_.cmlbm_run_inplace(sim.h, None, 2, None) == -1
     assert lib_.cmlbm_macroscopic_pre(sim.h, None, None, None, None) == -1
     assert torch.equal(buf, before)
+
+
+@pytest.mark.parametrize("q,prec,mkind", [(27, F64, "walls"), (27, F32, None), (27, BF16, "duct"), (15, F16, "walls"),
+                                          (15, F64, None)])
+def test_init_inplace_equals_import(q, prec, mkind):
+    shape = (9, 8, 66)
+    print(f"case init q{q} p{prec} {mkind}", flush=True)
+    solid = _mask(mkind, shape)
+    sim = gpu_setup(q, shape, prec, [1.3] * (q - 4), _force("field", shape), solid)
+    rho0, u0 = _fields(shape, 4)
+    want, _ = _inplace_buffer(sim, rho0, u0)
+    got = sim.init_equilibrium_inplace(to_dev(rho0, sim.real), to_dev(u0, sim.real))
+    assert torch.equal(got, want)
+
+
+def _blocked_index(q, n, z, y, x, a):
+    """Element index of slot a of node (z, y, x) in a population buffer of an
+    n^3 lattice (blocked rows, n a multiple of 64)."""
+    b = x // 64
+    return ((z * n + y) * n * q + b * 64 * q + a * 64 + (x - 64 * b)).astype(np.int64)
+
+
+def test_inplace_1024_fp64_sampled_nodes():
+    """1024^3 D3Q27 FP64 stepped in place: 216 GiB of state, a lattice whose two
+    ping-pong buffers (432 GiB) do not fit on one MI355X.  Random density and
+    velocity, uniform force, shear rate 1.9.  Checks at sampled nodes (corners
+    of the periodic box included), against the oracle: the initial state; the
+    collide phase (reversed slots = collision of the initial state); the
+    scatter phase (pre-collision state two steps on, recomputed by the oracle
+    from the phase-1 buffer around each node)."""
+    n, q = 1024, 27
+    need = q * 8 * n**3 + 4 * 8 * n**3
+    torch.cuda.empty_cache()           # blocks cached by earlier tests
+    free, _ = torch.cuda.mem_get_info()
+    if free < need + (2 << 30):
+        pytest.skip(f"needs {need / 2**30:.0f} GiB of free device memory, {free / 2**30:.0f} GiB free")
+    print("case 1024^3 D3Q27 FP64 in place", flush=True)
+    lat = LATTICES[q]
+    omega = [1.9] * 5 + [1.0] * 18
+    Fv = np.array([1e-6, -2e-7, 3e-7])
+    sim = gpu_setup(q, (n, n, n), F64, omega, Fv)
+    buf = sim.populations()
+    g = torch.Generator(device="cuda").manual_seed(5)
+    rho0 = torch.rand((n, n, n), device="cuda", dtype=torch.float64, generator=g).sub_(0.5).mul_(0.02).add_(1.0)
+    u0 = torch.rand((3, n, n, n), device="cuda", dtype=torch.float64, generator=g).sub_(0.5).mul_(0.1)
+    sim.init_equilibrium_inplace(rho0, u0, buf)
+    rng = np.random.default_rng(17)
+    pts = rng.integers(0, n, (120, 3))
+    corners = np.array([[z, y, x] for z in (0, n - 1) for y in (0, n - 1) for x in (0, n - 1)])
+    pts = np.concatenate([corners, pts, [[5, 63, 64], [700, 1, 127], [1023, 512, 191]]])
+    Z, Y, X = pts.T
+    flat = buf.view(-1)
+
+    def read(zz, yy, xx, slots):
+        idx = np.stack([_blocked_index(q, n, zz, yy, xx, a) for a in slots], axis=-1)
+        return flat[torch.from_numpy(idx.reshape(-1)).cuda()].cpu().numpy().reshape(idx.shape)
+
+    zt, yt, xt = [torch.from_numpy(c).cuda() for c in (Z, Y, X)]
+    r_s = rho0[zt, yt, xt].cpu().numpy()
+    u_s = u0[:, zt, yt, xt].cpu().numpy()
+    del rho0, u0
+    Fn = np.tile(Fv, (len(pts), 1))
+    f0 = read(Z, Y, X, range(q))
+    want0 = lbm.initial_state(lat, r_s[None, None, :], u_s[:, None, None, :], Fv)[:, 0, 0, :].T
+    assert np.abs(f0 - want0).max() < 1e-13
+    # collide phase
+    sim.step_inplace(buf, 0)
+    torch.cuda.synchronize()
+    post0 = read(Z, Y, X, [lat.opp[a] for a in range(q)])
+    want = collision.collide(lat, f0, Fn, omega)
+    scale = np.abs(want).max()
+    assert np.abs(post0 - want).max() / scale < 1e-12
+    # phase-1 buffer around every sample: post-collision populations at t = 0
+    d = np.arange(-2, 3)
+    DZ, DY, DX = np.meshgrid(d, d, d, indexing="ij")
+    nz_, ny_, nx_ = [(c[:, None] + D.reshape(-1)[None, :]) % n for c, D in ((Z, DZ), (Y, DY), (X, DX))]
+    around = read(nz_, ny_, nx_, [lat.opp[a] for a in range(q)])      # [sample, 125, a]: fbar~_a(z, 0)
+    sim.step_inplace(buf, 1)
+    torch.cuda.synchronize()
+    got = read(Z, Y, X, range(q))                                      # fbar_a(x, 2)
+    E = lat.E.astype(int)
+
+    def pos(v):
+        return (v[..., 0] + 2) * 25 + (v[..., 1] + 2) * 5 + (v[..., 2] + 2)   # offset (dz, dy, dx) -> 0..124
+
+    want2 = np.empty_like(got)
+    for a in range(q):
+        ya = -E[a][::-1]                                 # y = x - e_a, as (dz, dy, dx)
+        pre1 = np.stack([around[:, pos(ya - E[b][::-1]), b] for b in range(q)], axis=-1)   # fbar_b(y, 1)
+        want2[:, a] = collision.collide(lat, pre1, Fn, omega)[:, a]
+    assert np.abs(got - want2).max() / scale < 1e-12
