@@ -238,6 +238,12 @@ __device__ __forceinline__ void collide(R (&f)[Q], R Fx, R Fy, R Fz, const Rates
 #ifndef CMLBM_NT_STORE
 #define CMLBM_NT_STORE 1
 #endif
+// In-place scatter phase without walls: 0 = shifted stores, 1 = aligned stores
+// for 16-bit storage only (measured: 16-bit 2-5% faster aligned, FP32 2% slower
+// from the block barrier, FP64 even), 2 = aligned stores always.
+#ifndef CMLBM_ALIGNED_SCATTER
+#define CMLBM_ALIGNED_SCATTER 1
+#endif
 
 __device__ __forceinline__ uint32_t step_block_id() {
   uint32_t L = blockIdx.x;
@@ -458,29 +464,147 @@ __global__ __launch_bounds__(CMLBM_STEP_BLOCK) void k_step_inplace(StepArgs<type
     R Fx, Fy, Fz;
     force_row(args, g, row, x, Fx, Fy, Fz);
     collide<Q>(f, Fx, Fy, Fz, args.rates);
+    T v[Q];
+#pragma unroll
+    for (int a = 0; a < Q; ++a) v[a] = encode<ST, Q>(f[a], a);
     if constexpr (MASK) {
       // Finish the collision before the per-lane store branches: otherwise the
       // compiler sinks its last operations into them, where multiplies and adds
       // in different blocks are not fused, and the rounding departs from the
       // two-buffer step's.  (Empty statements: no instruction is emitted.)
 #pragma unroll
-      for (int a = 0; a < Q; ++a) asm volatile("" : "+v"(f[a]));
+      for (int a = 0; a < Q; ++a) asm volatile("" : "+v"(v[a]));
     }
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
       const Vel e = Lattice<Q>::e(a);
       const int ab = opposite<Q>(a);
-      const T v = encode<ST, Q>(f[a], a);
       if (MASK && ((solid >> ab) & 1u)) {            // x + e_a = x - e_abar is solid
-        buf_store<kInplaceAux>(v, array_rsrc(buf + uint64_t(row) * rowQ, rowQ * sz), cbase, uint32_t(ab) * lenB);
+        buf_store<kInplaceAux>(v[a], array_rsrc(buf + uint64_t(row) * rowQ, rowQ * sz), cbase, uint32_t(ab) * lenB);
       } else {
         const __amdgpu_buffer_rsrc_t rt =
             array_rsrc(buf + uint64_t(st.row[1 - e.y][1 - e.z]) * rowQ, rowQ * sz);
         if (e.x == 0)
-          buf_store<kInplaceAux>(v, rt, cbase, uint32_t(a) * lenB);
+          buf_store<kInplaceAux>(v[a], rt, cbase, uint32_t(a) * lenB);
         else
-          buf_store<kInplaceAux>(v, rt, nbase[1 - e.x] + uint32_t(a) * nlen[1 - e.x], 0u);
+          buf_store<kInplaceAux>(v[a], rt, nbase[1 - e.x] + uint32_t(a) * nlen[1 - e.x], 0u);
       }
+    }
+  }
+}
+
+// Value of `v` held by lane `src` of the wavefront (cross-lane permute; a
+// source outside 0..63 wraps, and the caller discards what it returns there).
+template <typename T>
+__device__ __forceinline__ T lane_value(T v, int src) {
+  const int addr = src << 2;
+  if constexpr (sizeof(T) == 8) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = uint32_t(__builtin_amdgcn_ds_bpermute(addr, int(uint32_t(u))));
+    const uint32_t hi = uint32_t(__builtin_amdgcn_ds_bpermute(addr, int(uint32_t(u >> 32))));
+    return __builtin_bit_cast(T, (uint64_t(hi) << 32) | lo);
+  } else if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_ds_bpermute(addr, __builtin_bit_cast(int, v)));
+  } else {
+    const int r = __builtin_amdgcn_ds_bpermute(addr, int(__builtin_bit_cast(uint16_t, v)));
+    return __builtin_bit_cast(T, uint16_t(r));
+  }
+}
+
+// Scatter phase of the in-place step on a lattice without walls, with aligned
+// stores.  The scatter writes fbar~_a(x) one node over in x for the directions
+// with e_x = +-1; stored as is, every wavefront store of those directions would
+// straddle one more cache line than it fills.  Here the lane of node x writes,
+// at its own (aligned) position in the target row, the value of its x -+ 1
+// neighbour instead: taken from the neighbouring lane, across a wavefront edge
+// from the neighbouring wavefront through LDS, and, at the two ends of the
+// block's row segment, written by the end node itself with one shifted store
+// (to the next segment's first node or the previous one's last, periodic).  Same
+// slots, same values as k_step_inplace<Q, ST, false, true>.
+template <int Q, class ST>
+__global__ __launch_bounds__(CMLBM_STEP_BLOCK) void k_scatter_periodic(StepArgs<typename ST::R> args) {
+  using R = typename ST::R;
+  using T = typename ST::T;
+  constexpr uint32_t sz = uint32_t(sizeof(T));
+  constexpr int kWaves = CMLBM_STEP_BLOCK / 64;
+  __shared__ T edge_up[kWaves][Q];   // lane 63 of each wavefront (e_x = +1 directions)
+  __shared__ T edge_dn[kWaves][Q];   // lane 0 of each wavefront (e_x = -1 directions)
+  const Geom g = args.g;
+  const uint32_t nx = uint32_t(g.nx);
+  const uint32_t nseg = (nx + blockDim.x - 1) / blockDim.x;
+  const uint32_t L = step_block_id();
+  const uint32_t row = L / nseg;                         // uniform over the block
+  const uint32_t x0 = (L - row * nseg) * blockDim.x;     // the block's row segment [x0, xend)
+  const uint32_t xend = min(x0 + blockDim.x, nx);
+  const uint32_t x = x0 + threadIdx.x;
+  const bool active = x < nx;
+  const int lane = int(threadIdx.x & 63u), wave = int(threadIdx.x >> 6);
+  T* const buf = static_cast<T*>(args.fout);
+  const uint32_t rowQ = nx * uint32_t(Q);
+  const uint32_t b0 = __builtin_amdgcn_readfirstlane(x & ~63u);
+  const uint32_t lenB = (b0 < nx ? min(64u, nx - b0) : 64u) * sz;
+  const uint32_t cbase = (b0 * uint32_t(Q) + (x - b0)) * sz;
+  const Coord c{int(active ? x : nx - 1), int(row % uint32_t(g.ny)), int(row / uint32_t(g.ny))};
+  const Stencil st(g, c, +1);
+  uint32_t nbase[3], nlen[3];
+#pragma unroll
+  for (int i = 0; i < 3; i += 2) {
+    const uint32_t xs = st.xs[i];
+    const uint32_t bb = xs & ~63u;
+    nbase[i] = (bb * uint32_t(Q) + (xs - bb)) * sz;
+    nlen[i] = min(64u, nx - bb) * sz;
+  }
+  T v[Q];
+#pragma unroll
+  for (int a = 0; a < Q; ++a) v[a] = T(0);
+  if (active) {
+    R f[Q];
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      const Vel e = Lattice<Q>::e(a);
+      const char* rp = reinterpret_cast<const char*>(buf + uint64_t(st.row[e.y + 1][e.z + 1]) * rowQ);
+      const uint32_t ab = uint32_t(opposite<Q>(a));
+      f[a] = decode<ST, Q>(e.x == 0 ? ldb<T>(rp + ab * lenB, cbase) : ldb<T>(rp, nbase[e.x + 1] + ab * nlen[e.x + 1]),
+                           a);
+    }
+    R Fx, Fy, Fz;
+    force_row(args, g, row, x, Fx, Fy, Fz);
+    collide<Q>(f, Fx, Fy, Fz, args.rates);
+#pragma unroll
+    for (int a = 0; a < Q; ++a) v[a] = encode<ST, Q>(f[a], a);
+    // Finish the collision here, ahead of the barrier and the store branches
+    // (same contraction as the two-buffer step; no instruction is emitted).
+#pragma unroll
+    for (int a = 0; a < Q; ++a) asm volatile("" : "+v"(v[a]));
+  }
+  if (lane == 63) {
+#pragma unroll
+    for (int a = 0; a < Q; ++a)
+      if (Lattice<Q>::e(a).x > 0) edge_up[wave][a] = v[a];
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int a = 0; a < Q; ++a)
+      if (Lattice<Q>::e(a).x < 0) edge_dn[wave][a] = v[a];
+  }
+  __syncthreads();
+  if (!active) return;
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    const Vel e = Lattice<Q>::e(a);
+    const __amdgpu_buffer_rsrc_t rt = array_rsrc(buf + uint64_t(st.row[1 - e.y][1 - e.z]) * rowQ, rowQ * sz);
+    if (e.x == 0) {
+      buf_store<kInplaceAux>(v[a], rt, cbase, uint32_t(a) * lenB);
+    } else if (e.x > 0) {            // slot a of x receives fbar~_a(x - 1)
+      T s = lane_value(v[a], lane - 1);
+      if (lane == 0 && wave > 0) s = edge_up[wave - 1][a];
+      if (x > x0) buf_store<kInplaceAux>(s, rt, cbase, uint32_t(a) * lenB);
+      if (x == xend - 1) buf_store<kInplaceAux>(v[a], rt, nbase[0] + uint32_t(a) * nlen[0], 0u);   // to x + 1
+    } else {                         // slot a of x receives fbar~_a(x + 1)
+      T s = lane_value(v[a], lane + 1);
+      if (lane == 63 && x + 1 < xend) s = edge_dn[wave + 1][a];
+      if (x + 1 < xend) buf_store<kInplaceAux>(s, rt, cbase, uint32_t(a) * lenB);
+      if (x == x0) buf_store<kInplaceAux>(v[a], rt, nbase[2] + uint32_t(a) * nlen[2], 0u);          // to x - 1
     }
   }
 }
@@ -1107,6 +1231,8 @@ hipError_t inplace_impl(const StepArgs<typename ST::R>& a, int parity, hipStream
   } else {
     if (a.mask)
       hipLaunchKernelGGL((k_step_inplace<Q, ST, true, true>), grid, dim3(bx), 0, st, a);
+    else if (CMLBM_ALIGNED_SCATTER == 2 || (CMLBM_ALIGNED_SCATTER == 1 && sizeof(typename ST::T) == 2))
+      hipLaunchKernelGGL((k_scatter_periodic<Q, ST>), grid, dim3(bx), 0, st, a);
     else
       hipLaunchKernelGGL((k_step_inplace<Q, ST, false, true>), grid, dim3(bx), 0, st, a);
   }

@@ -117,6 +117,12 @@ EXACT = [
     (15, F16, (4, 3, 300), "field", None, 6),
     (15, BF16, (9, 8, 66), "uniform", "duct", 6),
     (27, F32, (9, 8, 66), "uniform", "duct", 6),
+    # 16-bit storage without walls takes the aligned-store scatter phase: rows
+    # of one node, a one-node tail block, a one-node last segment, two full segments
+    (27, F16, (3, 4, 1), "field", None, 4),
+    (15, F16, (3, 2, 65), "field", None, 4),
+    (27, BF16, (2, 3, 257), "uniform", None, 4),
+    (27, F16, (2, 2, 512), "uniform", None, 4),
 ]
 
 
