@@ -904,6 +904,21 @@ __device__ __forceinline__ void st32(T* base, uint32_t idx, T v) {
   *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + idx * uint32_t(sizeof(T))) = v;
 }
 
+// The adjoint's output stores (lambda, dL/dF): CMLBM_ADJ_NT = 1 streams them
+// past the caches, as the step's population stores, so that they do not evict
+// the neighbour rows the gathers reuse.
+#ifndef CMLBM_ADJ_NT
+#define CMLBM_ADJ_NT 1
+#endif
+template <typename T>
+__device__ __forceinline__ void st32_out(T* base, uint32_t idx, T v) {
+  T* p = reinterpret_cast<T*>(reinterpret_cast<char*>(base) + idx * uint32_t(sizeof(T)));
+  if constexpr (CMLBM_ADJ_NT)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
+
 constexpr int kAdjBlock = 256;   // largest adjoint block (smaller for nx < 256)
 
 // Register slot of direction a in the adjoint's population vectors: cube
@@ -1003,13 +1018,13 @@ __global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(adjoi
       collide15_adj<PM>(f, Fx, Fy, Fz, args.rates, gm, gFx, gFy, gFz, wacc);
     }
 #pragma unroll
-    for (int a = 0; a < Q; ++a) st32(args.lam + uint64_t(a) * g.N + uint64_t(row) * nx, x, gm[slot<Q>(a)]);
+    for (int a = 0; a < Q; ++a) st32_out(args.lam + uint64_t(a) * g.N + uint64_t(row) * nx, x, gm[slot<Q>(a)]);
     if (args.force.field) {
       const double sc = double(args.force.scale);
       double* d = args.dLdF + uint64_t(row) * nx;
-      st32(d, x, ld32(d, x) + sc * double(gFx));
-      st32(d + g.N, x, ld32(d + g.N, x) + sc * double(gFy));
-      st32(d + 2 * g.N, x, ld32(d + 2 * g.N, x) + sc * double(gFz));
+      st32_out(d, x, ld32(d, x) + sc * double(gFx));
+      st32_out(d + g.N, x, ld32(d + g.N, x) + sc * double(gFy));
+      st32_out(d + 2 * g.N, x, ld32(d + 2 * g.N, x) + sc * double(gFz));
     } else {
       uF[0] += gFx;
       uF[1] += gFy;
