@@ -22,7 +22,12 @@
  *             64 KiB), all allocated by cmlbm_create: no other call allocates.
  *             Device pointers must be 256-byte aligned.
  * Streams:    `stream` is a hipStream_t (NULL = the default stream).  Work is
- *             enqueued asynchronously; only cmlbm_totals synchronizes.
+ *             enqueued asynchronously; only the calls with host outputs
+ *             (cmlbm_totals, cmlbm_totals_pre, cmlbm_kinetic_energy_sum)
+ *             synchronize.
+ * Devices:    a handle belongs to the device current at cmlbm_create; every
+ *             call that launches work returns EINVAL when another device is
+ *             current.
  * Threads:    a handle must not be used by two host threads at once.
  * Layout:     fields are structure of arrays, x fastest: vector fields
  *             (velocity, force, force gradient) [3][nz][ny][nx], scalars

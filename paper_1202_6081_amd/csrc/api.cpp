@@ -49,6 +49,23 @@ cmlbm_status check_hip(cmlbm_sim* s, hipError_t e, const char* what) {
   return fail(s, CMLBM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// Work is launched on the current device: it must be the handle's.
+cmlbm_status on_device(cmlbm_sim* s) {
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return fail(s, CMLBM_EDEVICE, "hipGetDevice failed");
+  if (cur != s->device)
+    return fail(s, CMLBM_EINVAL, "current HIP device " + std::to_string(cur) + " is not the handle's device " +
+                                     std::to_string(s->device));
+  return CMLBM_OK;
+}
+
+#define CMLBM_WORK_ENTRY(s)                   \
+  do {                                        \
+    if (!(s)) return CMLBM_EINVAL;            \
+    const cmlbm_status dev_ = on_device(s);   \
+    if (dev_ != CMLBM_OK) return dev_;        \
+  } while (0)
+
 template <typename R>
 cmlbm::Rates<R> make_rates(const cmlbm_sim* s) {
   cmlbm::Rates<R> r{};
@@ -222,7 +239,7 @@ cmlbm_status cmlbm_set_mask(cmlbm_sim* s, const uint8_t* mask_dev) {
 
 cmlbm_status cmlbm_init_equilibrium(cmlbm_sim* s, const void* rho_dev, const void* u_dev, void* f_pre_dev,
                                     void* f_post_dev, void* stream) {
-  if (!s) return CMLBM_EINVAL;
+  CMLBM_WORK_ENTRY(s);
   if (!rho_dev || !u_dev || !f_pre_dev || !f_post_dev) return fail(s, CMLBM_EINVAL, "NULL buffer");
   if (f_pre_dev == f_post_dev) return fail(s, CMLBM_EINVAL, "f_pre and f_post must differ");
   hipError_t e = cmlbm::launch_init(s->q, s->prec, s->g, rho_dev, u_dev, make_force<double>(s),
@@ -233,7 +250,7 @@ cmlbm_status cmlbm_init_equilibrium(cmlbm_sim* s, const void* rho_dev, const voi
 
 cmlbm_status cmlbm_init_equilibrium_inplace(cmlbm_sim* s, const void* rho_dev, const void* u_dev, void* f_dev,
                                             void* stream) {
-  if (!s) return CMLBM_EINVAL;
+  CMLBM_WORK_ENTRY(s);
   if (!rho_dev || !u_dev || !f_dev) return fail(s, CMLBM_EINVAL, "NULL buffer");
   hipError_t e = cmlbm::launch_init(s->q, s->prec, s->g, rho_dev, u_dev, make_force<double>(s),
                                     make_force<float>(s), s->mask, f_dev, nullptr,
@@ -281,18 +298,18 @@ cmlbm_status step_common(cmlbm_sim* s, const void* f_in, void* f_out, double* to
 }  // namespace
 
 cmlbm_status cmlbm_step(cmlbm_sim* s, const void* f_in, void* f_out, void* stream) {
-  if (!s) return CMLBM_EINVAL;
+  CMLBM_WORK_ENTRY(s);
   return step_common(s, f_in, f_out, nullptr, stream);
 }
 
 cmlbm_status cmlbm_step_totals(cmlbm_sim* s, const void* f_in, void* f_out, double* totals_dev, void* stream) {
-  if (!s) return CMLBM_EINVAL;
+  CMLBM_WORK_ENTRY(s);
   if (!totals_dev) return fail(s, CMLBM_EINVAL, "totals_dev is NULL");
   return step_common(s, f_in, f_out, totals_dev, stream);
 }
 
 cmlbm_status cmlbm_run(cmlbm_sim* s, void* f_a, void* f_b, int nsteps, void* stream, int* result_in_b) {
-  if (!s) return CMLBM_EINVAL;
+  CMLBM_WORK_ENTRY(s);
   if (nsteps < 0) return fail(s, CMLBM_EINVAL, "nsteps < 0");
   if (!f_a || !f_b) return fail(s, CMLBM_EINVAL, "NULL population buffer");
   if (f_a == f_b) return fail(s, CMLBM_EINVAL, "f_a and f_b must differ");
@@ -306,7 +323,7 @@ cmlbm_status cmlbm_run(cmlbm_sim* s, void* f_a, void* f_b, int nsteps, void* str
 }
 
 cmlbm_status cmlbm_gather_precollision(cmlbm_sim* s, const void* f_post, void* f_pre, void* stream) {
-  if (!s) return CMLBM_EINVAL;
+  CMLBM_WORK_ENTRY(s);
   if (!f_post || !f_pre) return fail(s, CMLBM_EINVAL, "NULL buffer");
   if (f_post == f_pre) return fail(s, CMLBM_EINVAL, "f_post and f_pre must differ");
   hipError_t e = cmlbm::launch_gather(s->q, s->prec, make_aux<double>(s, f_post, f_pre, nullptr),
@@ -315,7 +332,7 @@ cmlbm_status cmlbm_gather_precollision(cmlbm_sim* s, const void* f_post, void* f
 }
 
 cmlbm_status cmlbm_export_populations(cmlbm_sim* s, const void* f_buf, void* f_soa, void* stream) {
-  if (!s) return CMLBM_EINVAL;
+  CMLBM_WORK_ENTRY(s);
   if (!f_buf || !f_soa) return fail(s, CMLBM_EINVAL, "NULL buffer");
   if (f_buf == f_soa) return fail(s, CMLBM_EINVAL, "f_buf and f_soa must differ");
   hipError_t e = cmlbm::launch_convert(s->q, s->prec, s->g, f_buf, f_soa, true, static_cast<hipStream_t>(stream));
@@ -323,7 +340,7 @@ cmlbm_status cmlbm_export_populations(cmlbm_sim* s, const void* f_buf, void* f_s
 }
 
 cmlbm_status cmlbm_import_populations(cmlbm_sim* s, const void* f_soa, void* f_buf, void* stream) {
-  if (!s) return CMLBM_EINVAL;
+  CMLBM_WORK_ENTRY(s);
   if (!f_buf || !f_soa) return fail(s, CMLBM_EINVAL, "NULL buffer");
   if (f_buf == f_soa) return fail(s, CMLBM_EINVAL, "f_buf and f_soa must differ");
   hipError_t e = cmlbm::launch_convert(s->q, s->prec, s->g, f_soa, f_buf, false, static_cast<hipStream_t>(stream));
@@ -354,17 +371,17 @@ cmlbm_status totals_common(cmlbm_sim* s, const void* f, double out4[4], bool pre
 }  // namespace
 
 cmlbm_status cmlbm_macroscopic(cmlbm_sim* s, const void* f_post, void* rho, void* u, void* stream) {
-  if (!s) return CMLBM_EINVAL;
+  CMLBM_WORK_ENTRY(s);
   return macro_common(s, f_post, rho, u, false, stream);
 }
 
 cmlbm_status cmlbm_totals(cmlbm_sim* s, const void* f_post, double out4[4], void* stream) {
-  if (!s) return CMLBM_EINVAL;
+  CMLBM_WORK_ENTRY(s);
   return totals_common(s, f_post, out4, false, stream);
 }
 
 cmlbm_status cmlbm_step_inplace(cmlbm_sim* s, void* f, int parity, void* stream) {
-  if (!s) return CMLBM_EINVAL;
+  CMLBM_WORK_ENTRY(s);
   if (!f) return fail(s, CMLBM_EINVAL, "NULL population buffer");
   if (parity != 0 && parity != 1) return fail(s, CMLBM_EINVAL, "parity must be 0 or 1");
   cmlbm::StepArgs<double> a64{};
@@ -387,7 +404,7 @@ cmlbm_status cmlbm_step_inplace(cmlbm_sim* s, void* f, int parity, void* stream)
 }
 
 cmlbm_status cmlbm_run_inplace(cmlbm_sim* s, void* f, int nsteps, void* stream) {
-  if (!s) return CMLBM_EINVAL;
+  CMLBM_WORK_ENTRY(s);
   if (!f) return fail(s, CMLBM_EINVAL, "NULL population buffer");
   if (nsteps < 0 || (nsteps & 1)) return fail(s, CMLBM_EINVAL, "nsteps must be even and >= 0");
   for (int n = 0; n < nsteps; ++n) {
@@ -398,18 +415,18 @@ cmlbm_status cmlbm_run_inplace(cmlbm_sim* s, void* f, int nsteps, void* stream) 
 }
 
 cmlbm_status cmlbm_macroscopic_pre(cmlbm_sim* s, const void* f_pre_buf, void* rho, void* u, void* stream) {
-  if (!s) return CMLBM_EINVAL;
+  CMLBM_WORK_ENTRY(s);
   return macro_common(s, f_pre_buf, rho, u, true, stream);
 }
 
 cmlbm_status cmlbm_totals_pre(cmlbm_sim* s, const void* f_pre_buf, double out4[4], void* stream) {
-  if (!s) return CMLBM_EINVAL;
+  CMLBM_WORK_ENTRY(s);
   return totals_common(s, f_pre_buf, out4, true, stream);
 }
 
 cmlbm_status cmlbm_adjoint_step(cmlbm_sim* s, const void* f_post_prev, const void* lam_next, void* lam,
                                 double* dLdF_dev, double* dLdomega_dev, void* stream) {
-  if (!s) return CMLBM_EINVAL;
+  CMLBM_WORK_ENTRY(s);
   if (!f_post_prev || !lam_next || !lam || !dLdF_dev || !dLdomega_dev) return fail(s, CMLBM_EINVAL, "NULL buffer");
   if (lam == lam_next || lam == f_post_prev || lam_next == f_post_prev)
     return fail(s, CMLBM_EINVAL, "lam, lam_next and f_post_prev must differ");
@@ -442,7 +459,7 @@ cmlbm_status cmlbm_adjoint_step(cmlbm_sim* s, const void* f_post_prev, const voi
 }
 
 cmlbm_status cmlbm_kinetic_energy_sum(cmlbm_sim* s, const void* f_pre, double* out, void* stream) {
-  if (!s) return CMLBM_EINVAL;
+  CMLBM_WORK_ENTRY(s);
   if (!f_pre || !out) return fail(s, CMLBM_EINVAL, "NULL buffer");
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipError_t e = cmlbm::launch_ke_sum(s->q, s->prec, s->g, f_pre, s->mask, make_force<double>(s), make_force<float>(s),
@@ -455,7 +472,7 @@ cmlbm_status cmlbm_kinetic_energy_sum(cmlbm_sim* s, const void* f_pre, double* o
 
 cmlbm_status cmlbm_kinetic_energy_seed(cmlbm_sim* s, const void* f_pre, double scale, void* lam, double* dLdF_dev,
                                        void* stream) {
-  if (!s) return CMLBM_EINVAL;
+  CMLBM_WORK_ENTRY(s);
   if (!f_pre || !lam || !dLdF_dev) return fail(s, CMLBM_EINVAL, "NULL buffer");
   if (f_pre == lam) return fail(s, CMLBM_EINVAL, "f_pre and lam must differ");
   hipError_t e = cmlbm::launch_ke_seed(s->q, s->prec, s->g, f_pre, s->mask, make_force<double>(s),
@@ -466,7 +483,7 @@ cmlbm_status cmlbm_kinetic_energy_seed(cmlbm_sim* s, const void* f_pre, double s
 
 cmlbm_status cmlbm_init_adjoint(cmlbm_sim* s, const void* u0_dev, const void* lam0_dev, double* dLdF_dev,
                                 void* stream) {
-  if (!s) return CMLBM_EINVAL;
+  CMLBM_WORK_ENTRY(s);
   if (!u0_dev || !lam0_dev || !dLdF_dev) return fail(s, CMLBM_EINVAL, "NULL buffer");
   hipError_t e = cmlbm::launch_init_adjoint(s->q, s->prec, s->g, u0_dev, lam0_dev, s->mask, make_force<double>(s),
                                             make_force<float>(s), dLdF_dev, s->totals_partials,
