@@ -12,7 +12,7 @@ Prints ONE JSON line: MLUPS (whole job), the HBM roofline of the step kernel
 force loads), the FP64 CPU oracle timed on a bounded sample, the
 adjoint/forward time ratio of a 100-step checkpointed adjoint, and the
 per-launch step time of every lattice/storage variant on the same workload,
-two-buffer and in-place.
+two-buffer and in-place, and of the FP32 adjoint step of both lattices.
 """
 import argparse
 import hashlib
@@ -123,6 +123,38 @@ def variant_sweep(n, steps=30, warmup=3):
                                     "state_GiB": round(q * tb * n**3 / 2**30, 2)}})
             del a, b, bufs, sim
             torch.cuda.empty_cache()
+    return out
+
+
+def adjoint_sweep(n, launches=6):
+    """Per-call time of one FP32 adjoint step (the adjoint kernel and its two
+    small reductions) for both lattices on the 512^3 workload: algorithmic
+    bytes per node 3 Q 4 (pull of the forward state, reverse gather of lambda,
+    store of lambda) + 12 (force field) + 48 (FP64 dL/dF read-modify-write)."""
+    import torch
+    import lbm_inputs as inp
+    from paper_1202_6081_amd import cmlbm
+    dev = torch.device("cuda", 0)
+    out = []
+    for q in (27, 15):
+        sim = cmlbm.Sim(q, n, n, n, cmlbm.F32)
+        sim.set_rates([1.9] * 5 + [1.0] * (q - 9))
+        sim.set_force(torch.from_numpy(inp.kolmogorov_force(n, amplitude=1e-6, waves=4)).to(dev, torch.float32))
+        x = sim.populations()
+        lam_a, lam_b = sim.real_populations(), sim.real_populations()
+        sim.init_equilibrium(torch.ones((n, n, n), device=dev), torch.zeros((3, n, n, n), device=dev),
+                             f_post=x, f_pre=lam_a)
+        dLdF = torch.zeros((3, n, n, n), dtype=torch.float64, device=dev)
+        dLdw = torch.zeros(q - 4, dtype=torch.float64, device=dev)
+        bufs = [lam_a, lam_b]
+        sim.adjoint_step(x, lam_a, lam_b, dLdF, dLdw)
+        ms = _launch_ms(lambda i: sim.adjoint_step(x, bufs[i & 1], bufs[(i + 1) & 1], dLdF, dLdw), launches)
+        bpn = 3 * q * 4 + 12 + 48
+        gbs = bpn * n**3 / (ms * 1e-3) / 1e9
+        out.append({"lattice": f"D3Q{q}", "storage": "f32", "ms": round(ms, 4), "bytes_per_node": bpn,
+                    "GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)})
+        del sim, x, lam_a, lam_b, bufs, dLdF
+        torch.cuda.empty_cache()
     return out
 
 
@@ -246,6 +278,7 @@ def main():
         result["adjoint_forward_ratio"] = None
     torch.cuda.empty_cache()
     result["variants"] = None if args.no_variants else variant_sweep(n)
+    result["adjoint_variants"] = None if args.no_variants else adjoint_sweep(n)
     # the same workload stepped in place (one population buffer)
     result["inplace"] = None if args.no_variants else next(
         v["inplace"] for v in result["variants"] if v["lattice"] == "D3Q27" and v["storage"] == "f32")
