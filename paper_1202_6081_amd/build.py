@@ -40,5 +40,33 @@ def build(verbose=False):
     return LIB
 
 
+C_TEST_SRC = os.path.join(ROOT, "tests", "c", "abi_from_c.c")
+C_TEST_BIN = os.path.join(ROOT, "tests", "c", "abi_from_c")
+
+
+def build_c_test(verbose=False):
+    """The C program that drives the library's C ABI from C alone (a GPU test
+    runs it): plain C11 against include/cmlbm.h and the HIP runtime, linked to
+    the in-tree libcmlbm.so."""
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        raise RuntimeError("no C compiler found for the C ABI test program")
+    rocm = os.path.dirname(os.path.dirname(os.path.realpath(hipcc())))
+    tmp = C_TEST_BIN + ".tmp"
+    cmd = [cc, "-std=c11", "-O2", "-Wall", "-Wextra", "-Werror", "-D__HIP_PLATFORM_AMD__",
+           "-I", os.path.join(rocm, "include"), "-I", os.path.join(ROOT, "include"), C_TEST_SRC,
+           "-L", HERE, "-lcmlbm", "-L", os.path.join(rocm, "lib"), "-lamdhip64", "-lm",
+           "-Wl,-rpath,$ORIGIN/../../paper_1202_6081_amd", "-Wl,-rpath," + os.path.join(rocm, "lib"), "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("building the C ABI test program failed")
+    os.replace(tmp, C_TEST_BIN)
+    return C_TEST_BIN
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build_c_test(verbose=True))
