@@ -20,7 +20,8 @@
  *             (nx*ny*nz/8 bytes for the fused step totals, about
  *             26*ceil(nx/256)*ny*nz bytes for the adjoint's partial sums, and
  *             64 KiB), all allocated by cmlbm_create: no other call allocates.
- *             Device pointers must be 256-byte aligned.
+ *             Device pointers must be aligned to their element size
+ *             (hipMalloc and torch allocations are).
  * Streams:    `stream` is a hipStream_t (NULL = the default stream).  Work is
  *             enqueued asynchronously; only the calls with host outputs
  *             (cmlbm_totals, cmlbm_totals_pre, cmlbm_kinetic_energy_sum)
@@ -46,7 +47,9 @@
  * State:      the population buffers passed to cmlbm_step / cmlbm_run hold the
  *             post-collision, not yet streamed populations fbar~ (Eq.
  *             cascadedcollision1).  The paper's state, the pre-collision
- *             fbar(x, t), is read out by cmlbm_gather_precollision.
+ *             fbar(x, t), is read out by cmlbm_gather_precollision.  The
+ *             in-place calls (cmlbm_step_inplace and the calls after it) keep
+ *             one buffer of the same layout in two phases, described there.
  * Types:      "real" means double for CMLBM_F64 and float for the other three
  *             precisions.  Population buffers are double (F64), float (F32),
  *             IEEE binary16 (F32_F16DEV) or bfloat16 (F32_BF16DEV); the 16-bit
@@ -85,7 +88,7 @@ typedef struct cmlbm_sim cmlbm_sim; /* opaque; host memory owned by the library 
 
 /* Create a handle for a nx * ny * nz lattice, periodic in all directions until
  * a mask is set.  q: 15 or 27 (Eq. velocityd3qq27, Appendix G).  All rates
- * start at 1, the force at zero, the force scale at 1.  Limits: 1 <= n*,
+ * start at 1, the force at zero, the force scale at 1.  Limits: 1 <= nx,
  * ny, nz <= 65535, nx * ny * nz < 2^31.  Errors: EINVAL (sizes, q, precision,
  * out == NULL), EDEVICE (no HIP device), ENOMEM. */
 cmlbm_status cmlbm_create(int q, int nx, int ny, int nz, int precision, cmlbm_sim **out);
