@@ -147,10 +147,12 @@ class _Sweep:
             self.pool.put(x)
 
 
-def forward_sweep(sim, pool, x0, nsteps, keep):
+def forward_sweep(sim, pool, x0, nsteps, keep, keep_x0=True):
     """Advance x0 by nsteps, keeping the states at the positions in `keep`.
-    Returns ({position: buffer} with 0 -> x0, final buffer)."""
-    stored = {0: x0}
+    Returns ({position: buffer}, final buffer).  With keep_x0 the map holds
+    0 -> x0; without, x0 goes back to the pool after the first step (the
+    backward sweep then rebuilds x(0) from the initial fields)."""
+    stored = {0: x0} if keep_x0 else {}
     cur = x0
     for n in range(nsteps):
         nxt = pool.get()
@@ -163,23 +165,37 @@ def forward_sweep(sim, pool, x0, nsteps, keep):
     return stored, cur
 
 
-def backward_sweep(sw, stored, nsteps, every, snapshots):
-    """Run the adjoint steps N-1 .. 0 with recomputation from `stored`."""
+def backward_sweep(sw, stored, nsteps, every, snapshots, rebuild_x0=None):
+    """Run the adjoint steps N-1 .. 0 with recomputation from `stored`.
+    When x(0) is not stored, rebuild_x0() returns a pool buffer holding it,
+    called once, when the first interval is reached."""
+    def start(l):
+        if l in stored:
+            return stored[l], False
+        assert l == 0 and rebuild_x0 is not None
+        return rebuild_x0(), True
+
     if every:
-        starts = sorted(stored)
+        starts = sorted(set(stored) | {0})
         for i in range(len(starts) - 1, -1, -1):
             l = starts[i]
             r = starts[i + 1] if i + 1 < len(starts) else nsteps
-            sw.segment(l, r, stored[l])
+            xl, rebuilt = start(l)
+            sw.segment(l, r, xl)
+            if rebuilt:
+                sw.pool.put(xl)
         return
     chain = sorted(k for k in stored if k > 0)
     bounds = [0] + chain + [nsteps]
     for i in range(len(bounds) - 2, -1, -1):
         l, r = bounds[i], bounds[i + 1]
+        xl, rebuilt = start(l)
         # interval i is reversed while the snapshots at m_1..m_i are still held
-        sw.binomial(l, r, stored[l], max(snapshots - i, 0))
+        sw.binomial(l, r, xl, max(snapshots - i, 0))
         if l > 0:
             sw.pool.put(stored.pop(l))
+        elif rebuilt:
+            sw.pool.put(xl)
 
 
 def keep_positions(nsteps, every, snapshots):
@@ -198,12 +214,17 @@ class _Run(torch.autograd.Function):
         x0 = pool.get()
         pre = sim.real_populations()
         u0r = u0.to(device=sim.device, dtype=sim.real).contiguous()
-        sim.init_equilibrium(rho0.to(device=sim.device, dtype=sim.real).contiguous(), u0r, f_post=x0, f_pre=pre)
-        stored, last = forward_sweep(sim, pool, x0, nsteps, keep_positions(nsteps, every, snapshots))
+        rho0r = rho0.to(device=sim.device, dtype=sim.real).contiguous()
+        sim.init_equilibrium(rho0r, u0r, f_post=x0, f_pre=pre)
+        # x(0) is not kept: the backward sweep rebuilds it from (rho0, u0), the
+        # same kernels on the same inputs, so the memory holds one more snapshot
+        stored, last = forward_sweep(sim, pool, x0, nsteps, keep_positions(nsteps, every, snapshots),
+                                     keep_x0=nsteps == 0)
         sim.gather(last, out=pre)
         if not any(last is v for v in stored.values()):
             pool.put(last)
         ctx.sim, ctx.pool, ctx.stored = sim, pool, stored
+        ctx.rho0 = rho0r
         ctx.u0, ctx.nsteps, ctx.every, ctx.snapshots = u0r, nsteps, every, snapshots
         ctx.F_dtype, ctx.w_dtype, ctx.F_shape = F.dtype, omega.dtype, F.shape
         ctx.F_device, ctx.w_device = F.device, omega.device
@@ -219,7 +240,14 @@ class _Run(torch.autograd.Function):
         dLdF = torch.zeros(ctx.F_shape, dtype=torch.float64, device=sim.device)
         dLdw = torch.zeros(sim.q - 4, dtype=torch.float64, device=sim.device)
         sw = _Sweep(sim, pool, lam, lam_tmp, dLdF, dLdw)
-        backward_sweep(sw, stored, ctx.nsteps, ctx.every, ctx.snapshots)
+
+        def rebuild_x0():
+            # lam_tmp is free between adjoint steps: scratch for the pre-collision state
+            x0 = pool.get()
+            sim.init_equilibrium(ctx.rho0, ctx.u0, f_post=x0, f_pre=sw.lam_tmp)
+            return x0
+
+        backward_sweep(sw, stored, ctx.nsteps, ctx.every, ctx.snapshots, rebuild_x0)
         sim.init_adjoint(ctx.u0, sw.lam, dLdF)
         ctx.stats = {"recomputed": sw.recomputed, "adjoint_steps": sw.adjoint_steps, "buffers": pool.allocated}
         _last_stats.update(ctx.stats)
@@ -289,20 +317,20 @@ def benchmark_adjoint_ratio(sim, nsteps, forward_ms_per_step, budget_gib=None):
     the backward sweep (adjoint steps, recomputation, loss seed and
     initial-state adjoint) over `nsteps` plain forward steps.
 
-    Loss: mean kinetic energy of fbar(N).  Fixed memory: x(0) and two work
-    buffers (storage precision); the pre-collision output, the incoming
-    gradient, the two adjoint buffers (arithmetic precision); the force field,
-    its FP64 accumulator and FP32 gradient, u0 and rho0.  What is already
-    allocated on the device counts against the budget too; the rest holds
-    snapshots.  The default budget is 80% of the device memory.  The returned
-    peak is torch's own allocator high-water mark over the run."""
+    Loss: mean kinetic energy of fbar(N).  Fixed memory: two work buffers
+    (storage precision; x(0) is rebuilt, not kept); the pre-collision output,
+    the incoming gradient, the two adjoint buffers (arithmetic precision); the
+    force field, its FP64 accumulator and FP32 gradient, u0 and rho0.  What is
+    already allocated on the device counts against the budget too; the rest
+    holds snapshots.  The default budget is 90% of the device memory.  The
+    returned peak is torch's own allocator high-water mark over the run."""
     dev = sim.device
     n = sim.nx * sim.ny * sim.nz
     state = n * 27 * torch.tensor([], dtype=sim.store).element_size()
     real_state = n * 27 * torch.tensor([], dtype=sim.real).element_size()
-    fixed = 3 * state + 4 * real_state + n * (3 * (8 + 4 * 4) + 4)
+    fixed = 2 * state + 4 * real_state + n * (3 * (8 + 4 * 4) + 4)
     if budget_gib is None:
-        budget_gib = 0.8 * torch.cuda.get_device_properties(dev).total_memory / 2**30
+        budget_gib = 0.9 * torch.cuda.get_device_properties(dev).total_memory / 2**30
     budget = budget_gib * 2**30
     torch.cuda.reset_peak_memory_stats(dev)
     base = torch.cuda.memory_allocated(dev)

@@ -29,19 +29,32 @@ class FakeSim:
         self.seen.append(x.t)
 
 
-def _run(nsteps, every=None, snapshots=None):
+def _run(nsteps, every=None, snapshots=None, keep_x0=True):
     sim = FakeSim()
     pool = ag._Pool(sim)
     x0 = pool.get()
     x0.t = 0
-    stored, last = ag.forward_sweep(sim, pool, x0, nsteps, ag.keep_positions(nsteps, every, snapshots))
+    stored, last = ag.forward_sweep(sim, pool, x0, nsteps, ag.keep_positions(nsteps, every, snapshots),
+                                    keep_x0=keep_x0)
     assert last.t == nsteps and sim.steps == nsteps
+    assert (0 in stored) == keep_x0
+    forward_buffers = pool.allocated
     if not any(last is v for v in stored.values()):
         pool.put(last)
     sim.steps = 0
     sw = ag._Sweep(sim, pool, None, None, None, None)
-    ag.backward_sweep(sw, stored, nsteps, every, snapshots)
+    rebuilt = []
+
+    def rebuild_x0():
+        b = pool.get()
+        b.t = 0
+        rebuilt.append(b)
+        return b
+
+    ag.backward_sweep(sw, stored, nsteps, every, snapshots, None if keep_x0 else rebuild_x0)
     assert sim.seen == list(range(nsteps - 1, -1, -1))
+    assert len(rebuilt) == (0 if keep_x0 or nsteps == 0 else 1)
+    sim.forward_buffers = forward_buffers
     return sim, sw, pool, stored
 
 
@@ -70,3 +83,22 @@ def test_binomial_cost_closed_cases():
     for n in (20, 60, 100):
         costs = [ag._cost(n, s)[0] for s in range(0, 12)]
         assert all(a >= b for a, b in zip(costs, costs[1:]))
+
+
+@pytest.mark.parametrize("nsteps,s", [(100, 10), (100, 4), (50, 1), (30, 0), (12, 20), (1, 2), (2, 1)])
+def test_binomial_schedule_rebuilding_x0(nsteps, s):
+    """x(0) released after the first forward step and rebuilt once for the
+    first interval: the same adjoint order and recompute count, and the
+    forward pass holds one buffer fewer."""
+    sim, sw, pool, stored = _run(nsteps, snapshots=s, keep_x0=False)
+    assert sw.recomputed == sim.steps == ag.recompute_steps(nsteps, s)
+    kept = _run(nsteps, snapshots=s)[0]
+    if nsteps > 1 and s > 0:
+        assert sim.forward_buffers == kept.forward_buffers - 1
+    assert pool.allocated <= s + 3
+
+
+@pytest.mark.parametrize("nsteps,every", [(200, 20), (37, 5), (10, 10), (7, 1), (1, 3)])
+def test_uniform_checkpoints_rebuilding_x0(nsteps, every):
+    sim, sw, pool, stored = _run(nsteps, every=every, keep_x0=False)
+    assert sw.recomputed == sim.steps == nsteps - (-(-nsteps // every))
