@@ -285,3 +285,26 @@ def test_inplace_1024_fp64_sampled_nodes():
         pre1 = np.stack([around[:, pos(ya - E[b][::-1]), b] for b in range(q)], axis=-1)   # fbar_b(y, 1)
         want2[:, a] = collision.collide(lat, pre1, Fn, omega)[:, a]
     assert np.abs(got - want2).max() / scale < 1e-12
+
+
+@pytest.mark.parametrize("q,prec", [(27, F32), (15, F64), (27, BF16)])
+def test_inplace_time_dependent_force_and_per_mass(q, prec):
+    """Per-unit-mass attractors and a force scale set before every step (the
+    time-periodic forcing of Sec. 9): the in-place run stays bit-identical to
+    the two-buffer run."""
+    shape = (6, 5, 67)
+    print(f"case q{q} p{prec} force scale per step, per-mass", flush=True)
+    solid = _mask("walls", shape)
+    sim = gpu_setup(q, shape, prec, list(np.random.default_rng(3).uniform(0.8, 1.9, q - 4)), _force("field", shape),
+                    solid, per_mass=True)
+    rho0, u0 = _fields(shape, 12)
+    buf, f_post = _inplace_buffer(sim, rho0, u0)
+    other = sim.populations()
+    steps = 8
+    for n in range(steps):
+        sim.set_force_scale(np.cos(2 * np.pi * n / 5))
+        sim.step(f_post, other)
+        f_post, other = other, f_post
+        sim.step_inplace(buf, n & 1)
+    fl = torch.from_numpy(~solid).cuda()
+    assert torch.equal(sim.gather(f_post)[:, fl], sim.export_populations(buf)[:, fl])
