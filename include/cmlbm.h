@@ -19,7 +19,8 @@
  *             owns only the opaque handle and device scratch for reductions
  *             (nx*ny*nz/8 bytes for the fused step totals, about
  *             26*ceil(nx/256)*ny*nz bytes for the adjoint's partial sums, and
- *             64 KiB), all allocated by cmlbm_create: no other call allocates.
+ *             about 120 KiB), all allocated by cmlbm_create: no other call
+ *             allocates.
  *             Device pointers must be aligned to their element size
  *             (hipMalloc and torch allocations are).
  * Streams:    `stream` is a hipStream_t (NULL = the default stream).  Work is

@@ -24,7 +24,7 @@ struct cmlbm_sim {
   const uint8_t* mask = nullptr;
   double* totals_partials = nullptr;   // [kTotalsBlocks][4]
   double* totals_out = nullptr;        // [4]
-  double* adj_partials = nullptr;      // [adj_nblk][26], adjoint dL/domega and uniform dL/dF partials
+  double* adj_partials = nullptr;      // [adj_nblk][26] + [kReduceChunks][26]: adjoint dL/domega, uniform dL/dF
   int adj_nblk = 0;
   double* step_partials = nullptr;     // [step_blocks][4] + [kReduceChunks][4], fused step totals
   std::string err;
@@ -169,7 +169,7 @@ cmlbm_status cmlbm_create(int q, int nx, int ny, int nz, int precision, cmlbm_si
   if (hipMalloc(&s->totals_partials, sizeof(double) * 4 * cmlbm::kTotalsBlocks) != hipSuccess ||
       hipMalloc(&s->totals_out, sizeof(double) * 4) != hipSuccess ||
       hipMalloc(&s->step_partials, sizeof(double) * 4 * step_rows) != hipSuccess ||
-      hipMalloc(&s->adj_partials, sizeof(double) * 26 * size_t(s->adj_nblk)) != hipSuccess) {
+      hipMalloc(&s->adj_partials, sizeof(double) * 26 * (size_t(s->adj_nblk) + cmlbm::kReduceChunks)) != hipSuccess) {
     g_create_error = "device scratch allocation failed";
     cmlbm_destroy(s);
     return CMLBM_ENOMEM;

@@ -1336,9 +1336,13 @@ hipError_t adjoint_impl(const AdjArgs<typename ST::R>& a, double* partials, int 
     else
       hipLaunchKernelGGL((k_adjoint<Q, ST, false, 0>), grid, block, 0, st, a, partials);
   }
-  hipLaunchKernelGGL(k_reduce_rows, dim3(Q - 4), dim3(kBlock), 0, st, partials, nblk, 26, dLdomega, 1);
+  // two stages: kReduceChunks blocks sum contiguous runs of block rows (all 26
+  // columns), then one block per column adds the chunk sums into the outputs
+  double* stage = partials + uint64_t(26) * uint64_t(nblk);
+  hipLaunchKernelGGL(k_reduce_chunks<26>, dim3(kReduceChunks), dim3(kBlock), 0, st, partials, uint64_t(nblk), stage);
+  hipLaunchKernelGGL(k_reduce_rows, dim3(Q - 4), dim3(kBlock), 0, st, stage, kReduceChunks, 26, dLdomega, 1);
   if (dLdF_uniform)
-    hipLaunchKernelGGL(k_reduce_rows, dim3(3), dim3(kBlock), 0, st, partials + 23, nblk, 26, dLdF_uniform, 1);
+    hipLaunchKernelGGL(k_reduce_rows, dim3(3), dim3(kBlock), 0, st, stage + 23, kReduceChunks, 26, dLdF_uniform, 1);
   return hipGetLastError();
 }
 
