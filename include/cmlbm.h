@@ -208,6 +208,17 @@ cmlbm_status cmlbm_totals(cmlbm_sim *sim, const void *f_post, double out4[4], vo
  * on one buffer must be ordered (one stream). */
 cmlbm_status cmlbm_step_inplace(cmlbm_sim *sim, void *f, int parity, void *stream);
 
+/* One in-place step exactly as cmlbm_step_inplace, which also reduces the FP64
+ * totals of the pre-collision state it collides inside the same pass:
+ * totals_dev[0..3] = (sum rho, sum rho u_x, sum rho u_y, sum rho u_z) over
+ * fluid nodes, rho u including F/2 (Eqs. densitycalculation,
+ * velocitycalculation).  Parity 0 totals fbar(t), the state the buffer holds;
+ * parity 1 totals fbar(t + 1), the state it gathers.  The same values as
+ * cmlbm_step_totals at the same step of a two-buffer run.  totals_dev: 4
+ * doubles of device memory, overwritten asynchronously on `stream`.  Errors:
+ * as cmlbm_step_inplace; EINVAL if totals_dev is NULL. */
+cmlbm_status cmlbm_step_inplace_totals(cmlbm_sim *sim, void *f, int parity, double *totals_dev, void *stream);
+
 /* The initial state of cmlbm_init_equilibrium, fbar(x, 0), written straight
  * into an in-place buffer f_dev in phase 0 (population storage type, blocked
  * rows): the same values as cmlbm_import_populations of its f_pre, without

@@ -56,6 +56,7 @@ def load_library():
         "cmlbm_totals": (i, [vp, vp, ctypes.POINTER(d), vp]),
         "cmlbm_init_equilibrium_inplace": (i, [vp, vp, vp, vp, vp]),
         "cmlbm_step_inplace": (i, [vp, vp, i, vp]),
+        "cmlbm_step_inplace_totals": (i, [vp, vp, i, vp, vp]),
         "cmlbm_run_inplace": (i, [vp, vp, i, vp]),
         "cmlbm_macroscopic_pre": (i, [vp, vp, vp, vp, vp]),
         "cmlbm_totals_pre": (i, [vp, vp, ctypes.POINTER(d), vp]),
@@ -80,7 +81,8 @@ def exported_symbols():
             "cmlbm_set_force_field", "cmlbm_set_force_scale", "cmlbm_set_attractor_per_mass", "cmlbm_set_mask",
             "cmlbm_init_equilibrium", "cmlbm_step", "cmlbm_step_totals", "cmlbm_run", "cmlbm_gather_precollision",
             "cmlbm_export_populations", "cmlbm_import_populations", "cmlbm_macroscopic", "cmlbm_totals",
-            "cmlbm_init_equilibrium_inplace", "cmlbm_step_inplace", "cmlbm_run_inplace", "cmlbm_macroscopic_pre", "cmlbm_totals_pre",
+            "cmlbm_init_equilibrium_inplace", "cmlbm_step_inplace", "cmlbm_step_inplace_totals",
+            "cmlbm_run_inplace", "cmlbm_macroscopic_pre", "cmlbm_totals_pre",
             "cmlbm_adjoint_step", "cmlbm_kinetic_energy_sum", "cmlbm_kinetic_energy_seed", "cmlbm_init_adjoint",
             "cmlbm_status_string", "cmlbm_last_error", "cmlbm_version"]
 
@@ -216,6 +218,12 @@ def cmlbm_init_equilibrium_inplace(h, rho, u, f, stream=None):
 
 def cmlbm_step_inplace(h, f, parity, stream=None):
     _check(load_library().cmlbm_step_inplace(h, _ptr(f), int(parity), _stream(stream)), h)
+
+
+def cmlbm_step_inplace_totals(h, f, parity, totals, stream=None):
+    if totals.dtype != torch.float64 or totals.numel() < 4:
+        raise CmlbmError(-1, "totals must be a device tensor of at least 4 float64")
+    _check(load_library().cmlbm_step_inplace_totals(h, _ptr(f), int(parity), _ptr(totals), _stream(stream)), h)
 
 
 def cmlbm_run_inplace(h, f, nsteps, stream=None):
@@ -374,8 +382,13 @@ class Sim:
         cmlbm_init_equilibrium_inplace(self.h, rho, u, f, stream)
         return f
 
-    def step_inplace(self, f, parity, stream=None):
-        cmlbm_step_inplace(self.h, f, parity, stream)
+    def step_inplace(self, f, parity, stream=None, totals=None):
+        """One in-place step; with `totals` (4 float64 on the device), the same
+        pass also writes the FP64 (mass, momentum) of the state it collides."""
+        if totals is None:
+            cmlbm_step_inplace(self.h, f, parity, stream)
+        else:
+            cmlbm_step_inplace_totals(self.h, f, parity, totals, stream)
 
     def run_inplace(self, f, nsteps, stream=None):
         """nsteps (even) in-place steps; f holds the pre-collision state in

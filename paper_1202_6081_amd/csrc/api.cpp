@@ -380,10 +380,17 @@ cmlbm_status cmlbm_totals(cmlbm_sim* s, const void* f_post, double out4[4], void
   return totals_common(s, f_post, out4, false, stream);
 }
 
-cmlbm_status cmlbm_step_inplace(cmlbm_sim* s, void* f, int parity, void* stream) {
-  CMLBM_WORK_ENTRY(s);
+namespace {
+
+cmlbm_status inplace_common(cmlbm_sim* s, void* f, int parity, double* totals_dev, void* stream) {
   if (!f) return fail(s, CMLBM_EINVAL, "NULL population buffer");
   if (parity != 0 && parity != 1) return fail(s, CMLBM_EINVAL, "parity must be 0 or 1");
+  double* partials = nullptr;
+  double* stage = nullptr;
+  if (totals_dev) {
+    partials = s->step_partials;
+    stage = s->step_partials + 4 * cmlbm::step_blocks(s->g);
+  }
   cmlbm::StepArgs<double> a64{};
   cmlbm::StepArgs<float> a32{};
   if (s->prec == CMLBM_F64) {
@@ -392,15 +399,34 @@ cmlbm_status cmlbm_step_inplace(cmlbm_sim* s, void* f, int parity, void* stream)
     a64.mask = s->mask;
     a64.force = make_force<double>(s);
     a64.rates = make_rates<double>(s);
+    a64.partials = partials;
+    a64.stage = stage;
+    a64.totals = totals_dev;
   } else {
     a32.g = s->g;
     a32.fout = f;
     a32.mask = s->mask;
     a32.force = make_force<float>(s);
     a32.rates = make_rates<float>(s);
+    a32.partials = partials;
+    a32.stage = stage;
+    a32.totals = totals_dev;
   }
   return check_hip(s, cmlbm::launch_step_inplace(s->q, s->prec, a64, a32, parity, static_cast<hipStream_t>(stream)),
                    "step_inplace");
+}
+
+}  // namespace
+
+cmlbm_status cmlbm_step_inplace(cmlbm_sim* s, void* f, int parity, void* stream) {
+  CMLBM_WORK_ENTRY(s);
+  return inplace_common(s, f, parity, nullptr, stream);
+}
+
+cmlbm_status cmlbm_step_inplace_totals(cmlbm_sim* s, void* f, int parity, double* totals_dev, void* stream) {
+  CMLBM_WORK_ENTRY(s);
+  if (!totals_dev) return fail(s, CMLBM_EINVAL, "totals_dev is NULL");
+  return inplace_common(s, f, parity, totals_dev, stream);
 }
 
 cmlbm_status cmlbm_run_inplace(cmlbm_sim* s, void* f, int nsteps, void* stream) {

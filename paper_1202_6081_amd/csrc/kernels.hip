@@ -403,7 +403,9 @@ __global__ __launch_bounds__(CMLBM_STEP_BLOCK) void k_step(StepArgs<typename ST:
 // each line in two parts).
 constexpr int kInplaceAux = 0;
 
-template <int Q, class ST, bool MASK, bool ODD>
+// With TOT, the block's FP64 totals of the pre-collision state it collides go
+// to args.partials[blockIdx.x][0..3] (as in k_step).
+template <int Q, class ST, bool MASK, bool ODD, bool TOT>
 __global__ __launch_bounds__(CMLBM_STEP_BLOCK) void k_step_inplace(StepArgs<typename ST::R> args) {
   using R = typename ST::R;
   using T = typename ST::T;
@@ -414,81 +416,97 @@ __global__ __launch_bounds__(CMLBM_STEP_BLOCK) void k_step_inplace(StepArgs<type
   const uint32_t L = step_block_id();
   const uint32_t row = L / nseg;                  // uniform over the block
   const uint32_t x = (L - row * nseg) * blockDim.x + threadIdx.x;
-  if (x >= nx || (MASK && args.mask[row * nx + x])) return;
-  T* const buf = static_cast<T*>(args.fout);
-  const uint32_t rowQ = nx * uint32_t(Q);
-  const uint32_t b0 = __builtin_amdgcn_readfirstlane(x & ~63u);
-  const uint32_t lenB = min(64u, nx - b0) * sz;            // wave-uniform direction stride
-  const uint32_t cbase = (b0 * uint32_t(Q) + (x - b0)) * sz;
-  const char* own = reinterpret_cast<const char*>(buf + uint64_t(row) * rowQ);
-  R f[Q];
-  if constexpr (!ODD) {
+  const bool active = x < nx && !(MASK && args.mask[row * nx + x]);
+  double acc[4] = {0, 0, 0, 0};
+  if constexpr (!TOT) {
+    if (!active) return;
+  }
+  if (active) {
+    T* const buf = static_cast<T*>(args.fout);
+    const uint32_t rowQ = nx * uint32_t(Q);
+    const uint32_t b0 = __builtin_amdgcn_readfirstlane(x & ~63u);
+    const uint32_t lenB = min(64u, nx - b0) * sz;            // wave-uniform direction stride
+    const uint32_t cbase = (b0 * uint32_t(Q) + (x - b0)) * sz;
+    const char* own = reinterpret_cast<const char*>(buf + uint64_t(row) * rowQ);
+    R f[Q];
+    if constexpr (!ODD) {
 #pragma unroll
-    for (int a = 0; a < Q; ++a) f[a] = decode<ST, Q>(ldb<T>(own + uint32_t(a) * lenB, cbase), a);
-    R Fx, Fy, Fz;
-    force_row(args, g, row, x, Fx, Fy, Fz);
-    collide<Q>(f, Fx, Fy, Fz, args.rates);
-    const __amdgpu_buffer_rsrc_t rs = array_rsrc(buf + uint64_t(row) * rowQ, rowQ * sz);
+      for (int a = 0; a < Q; ++a) f[a] = decode<ST, Q>(ldb<T>(own + uint32_t(a) * lenB, cbase), a);
+      R Fx, Fy, Fz;
+      force_row(args, g, row, x, Fx, Fy, Fz);
+      if constexpr (TOT) add_node_totals<Q>(f, Fx, Fy, Fz, acc);
+      collide<Q>(f, Fx, Fy, Fz, args.rates);
+      const __amdgpu_buffer_rsrc_t rs = array_rsrc(buf + uint64_t(row) * rowQ, rowQ * sz);
 #pragma unroll
-    for (int a = 0; a < Q; ++a) buf_store<kInplaceAux>(encode<ST, Q>(f[a], a), rs, cbase, uint32_t(opposite<Q>(a)) * lenB);
-  } else {
-    const Coord c{int(x), int(row % uint32_t(g.ny)), int(row / uint32_t(g.ny))};
-    const Stencil st(g, c, +1);      // row[ey+1][ez+1], xs[ex+1]: x - e; index with -e for x + e
-    uint32_t nbase[3], nlen[3];      // blocked offsets of x - 1 ([2]) and x + 1 ([0]), and their block strides
+      for (int a = 0; a < Q; ++a) buf_store<kInplaceAux>(encode<ST, Q>(f[a], a), rs, cbase, uint32_t(opposite<Q>(a)) * lenB);
+    } else {
+      const Coord c{int(x), int(row % uint32_t(g.ny)), int(row / uint32_t(g.ny))};
+      const Stencil st(g, c, +1);      // row[ey+1][ez+1], xs[ex+1]: x - e; index with -e for x + e
+      uint32_t nbase[3], nlen[3];      // blocked offsets of x - 1 ([2]) and x + 1 ([0]), and their block strides
 #pragma unroll
-    for (int i = 0; i < 3; i += 2) {
-      const uint32_t xs = st.xs[i];
-      const uint32_t bb = xs & ~63u;
-      nbase[i] = (bb * uint32_t(Q) + (xs - bb)) * sz;
-      nlen[i] = min(64u, nx - bb) * sz;
-    }
-    uint32_t solid = 0;              // bit a: x - e_a is solid
-    if constexpr (MASK) {
-#pragma unroll
-      for (int a = 0; a < Q; ++a) solid |= uint32_t(args.mask[st.node(Lattice<Q>::e(a), nx)] != 0) << a;
-    }
-#pragma unroll
-    for (int a = 0; a < Q; ++a) {
-      const Vel e = Lattice<Q>::e(a);
-      const char* rp = reinterpret_cast<const char*>(buf + uint64_t(st.row[e.y + 1][e.z + 1]) * rowQ);
-      const uint32_t ab = uint32_t(opposite<Q>(a));
-      T v;
-      if (MASK && ((solid >> a) & 1u))
-        v = ldb<T>(own + uint32_t(a) * lenB, cbase);
-      else if (e.x == 0)
-        v = ldb<T>(rp + ab * lenB, cbase);
-      else
-        v = ldb<T>(rp, nbase[e.x + 1] + ab * nlen[e.x + 1]);
-      f[a] = decode<ST, Q>(v, a);
-    }
-    R Fx, Fy, Fz;
-    force_row(args, g, row, x, Fx, Fy, Fz);
-    collide<Q>(f, Fx, Fy, Fz, args.rates);
-    T v[Q];
-#pragma unroll
-    for (int a = 0; a < Q; ++a) v[a] = encode<ST, Q>(f[a], a);
-    if constexpr (MASK) {
-      // Finish the collision before the per-lane store branches: otherwise the
-      // compiler sinks its last operations into them, where multiplies and adds
-      // in different blocks are not fused, and the rounding departs from the
-      // two-buffer step's.  (Empty statements: no instruction is emitted.)
-#pragma unroll
-      for (int a = 0; a < Q; ++a) asm volatile("" : "+v"(v[a]));
-    }
-#pragma unroll
-    for (int a = 0; a < Q; ++a) {
-      const Vel e = Lattice<Q>::e(a);
-      const int ab = opposite<Q>(a);
-      if (MASK && ((solid >> ab) & 1u)) {            // x + e_a = x - e_abar is solid
-        buf_store<kInplaceAux>(v[a], array_rsrc(buf + uint64_t(row) * rowQ, rowQ * sz), cbase, uint32_t(ab) * lenB);
-      } else {
-        const __amdgpu_buffer_rsrc_t rt =
-            array_rsrc(buf + uint64_t(st.row[1 - e.y][1 - e.z]) * rowQ, rowQ * sz);
-        if (e.x == 0)
-          buf_store<kInplaceAux>(v[a], rt, cbase, uint32_t(a) * lenB);
-        else
-          buf_store<kInplaceAux>(v[a], rt, nbase[1 - e.x] + uint32_t(a) * nlen[1 - e.x], 0u);
+      for (int i = 0; i < 3; i += 2) {
+        const uint32_t xs = st.xs[i];
+        const uint32_t bb = xs & ~63u;
+        nbase[i] = (bb * uint32_t(Q) + (xs - bb)) * sz;
+        nlen[i] = min(64u, nx - bb) * sz;
       }
+      uint32_t solid = 0;              // bit a: x - e_a is solid
+      if constexpr (MASK) {
+#pragma unroll
+        for (int a = 0; a < Q; ++a) solid |= uint32_t(args.mask[st.node(Lattice<Q>::e(a), nx)] != 0) << a;
+      }
+#pragma unroll
+      for (int a = 0; a < Q; ++a) {
+        const Vel e = Lattice<Q>::e(a);
+        const char* rp = reinterpret_cast<const char*>(buf + uint64_t(st.row[e.y + 1][e.z + 1]) * rowQ);
+        const uint32_t ab = uint32_t(opposite<Q>(a));
+        T v;
+        if (MASK && ((solid >> a) & 1u))
+          v = ldb<T>(own + uint32_t(a) * lenB, cbase);
+        else if (e.x == 0)
+          v = ldb<T>(rp + ab * lenB, cbase);
+        else
+          v = ldb<T>(rp, nbase[e.x + 1] + ab * nlen[e.x + 1]);
+        f[a] = decode<ST, Q>(v, a);
+      }
+      R Fx, Fy, Fz;
+      force_row(args, g, row, x, Fx, Fy, Fz);
+      if constexpr (TOT) add_node_totals<Q>(f, Fx, Fy, Fz, acc);
+      collide<Q>(f, Fx, Fy, Fz, args.rates);
+      T v[Q];
+#pragma unroll
+      for (int a = 0; a < Q; ++a) v[a] = encode<ST, Q>(f[a], a);
+      if constexpr (MASK) {
+        // Finish the collision before the per-lane store branches: otherwise the
+        // compiler sinks its last operations into them, where multiplies and adds
+        // in different blocks are not fused, and the rounding departs from the
+        // two-buffer step's.  (Empty statements: no instruction is emitted.)
+#pragma unroll
+        for (int a = 0; a < Q; ++a) asm volatile("" : "+v"(v[a]));
+      }
+#pragma unroll
+      for (int a = 0; a < Q; ++a) {
+        const Vel e = Lattice<Q>::e(a);
+        const int ab = opposite<Q>(a);
+        if (MASK && ((solid >> ab) & 1u)) {            // x + e_a = x - e_abar is solid
+          buf_store<kInplaceAux>(v[a], array_rsrc(buf + uint64_t(row) * rowQ, rowQ * sz), cbase, uint32_t(ab) * lenB);
+        } else {
+          const __amdgpu_buffer_rsrc_t rt =
+              array_rsrc(buf + uint64_t(st.row[1 - e.y][1 - e.z]) * rowQ, rowQ * sz);
+          if (e.x == 0)
+            buf_store<kInplaceAux>(v[a], rt, cbase, uint32_t(a) * lenB);
+          else
+            buf_store<kInplaceAux>(v[a], rt, nbase[1 - e.x] + uint32_t(a) * nlen[1 - e.x], 0u);
+        }
+      }
+    }
+  }
+  if constexpr (TOT) {
+    __shared__ double sh[4 * 8];
+    block_sum<4>(acc, sh);
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) args.partials[uint64_t(blockIdx.x) * 4 + i] = acc[i];
     }
   }
 }
@@ -520,8 +538,8 @@ __device__ __forceinline__ T lane_value(T v, int src) {
 // from the neighbouring wavefront through LDS, and, at the two ends of the
 // block's row segment, written by the end node itself with one shifted store
 // (to the next segment's first node or the previous one's last, periodic).  Same
-// slots, same values as k_step_inplace<Q, ST, false, true>.
-template <int Q, class ST>
+// slots, same values as k_step_inplace<Q, ST, false, true, TOT>.
+template <int Q, class ST, bool TOT>
 __global__ __launch_bounds__(CMLBM_STEP_BLOCK) void k_scatter_periodic(StepArgs<typename ST::R> args) {
   using R = typename ST::R;
   using T = typename ST::T;
@@ -557,6 +575,7 @@ __global__ __launch_bounds__(CMLBM_STEP_BLOCK) void k_scatter_periodic(StepArgs<
   T v[Q];
 #pragma unroll
   for (int a = 0; a < Q; ++a) v[a] = T(0);
+  double acc[4] = {0, 0, 0, 0};
   if (active) {
     R f[Q];
 #pragma unroll
@@ -569,6 +588,7 @@ __global__ __launch_bounds__(CMLBM_STEP_BLOCK) void k_scatter_periodic(StepArgs<
     }
     R Fx, Fy, Fz;
     force_row(args, g, row, x, Fx, Fy, Fz);
+    if constexpr (TOT) add_node_totals<Q>(f, Fx, Fy, Fz, acc);
     collide<Q>(f, Fx, Fy, Fz, args.rates);
 #pragma unroll
     for (int a = 0; a < Q; ++a) v[a] = encode<ST, Q>(f[a], a);
@@ -588,23 +608,32 @@ __global__ __launch_bounds__(CMLBM_STEP_BLOCK) void k_scatter_periodic(StepArgs<
       if (Lattice<Q>::e(a).x < 0) edge_dn[wave][a] = v[a];
   }
   __syncthreads();
-  if (!active) return;
+  if (active) {
 #pragma unroll
-  for (int a = 0; a < Q; ++a) {
-    const Vel e = Lattice<Q>::e(a);
-    const __amdgpu_buffer_rsrc_t rt = array_rsrc(buf + uint64_t(st.row[1 - e.y][1 - e.z]) * rowQ, rowQ * sz);
-    if (e.x == 0) {
-      buf_store<kInplaceAux>(v[a], rt, cbase, uint32_t(a) * lenB);
-    } else if (e.x > 0) {            // slot a of x receives fbar~_a(x - 1)
-      T s = lane_value(v[a], lane - 1);
-      if (lane == 0 && wave > 0) s = edge_up[wave - 1][a];
-      if (x > x0) buf_store<kInplaceAux>(s, rt, cbase, uint32_t(a) * lenB);
-      if (x == xend - 1) buf_store<kInplaceAux>(v[a], rt, nbase[0] + uint32_t(a) * nlen[0], 0u);   // to x + 1
-    } else {                         // slot a of x receives fbar~_a(x + 1)
-      T s = lane_value(v[a], lane + 1);
-      if (lane == 63 && x + 1 < xend) s = edge_dn[wave + 1][a];
-      if (x + 1 < xend) buf_store<kInplaceAux>(s, rt, cbase, uint32_t(a) * lenB);
-      if (x == x0) buf_store<kInplaceAux>(v[a], rt, nbase[2] + uint32_t(a) * nlen[2], 0u);          // to x - 1
+    for (int a = 0; a < Q; ++a) {
+      const Vel e = Lattice<Q>::e(a);
+      const __amdgpu_buffer_rsrc_t rt = array_rsrc(buf + uint64_t(st.row[1 - e.y][1 - e.z]) * rowQ, rowQ * sz);
+      if (e.x == 0) {
+        buf_store<kInplaceAux>(v[a], rt, cbase, uint32_t(a) * lenB);
+      } else if (e.x > 0) {            // slot a of x receives fbar~_a(x - 1)
+        T s = lane_value(v[a], lane - 1);
+        if (lane == 0 && wave > 0) s = edge_up[wave - 1][a];
+        if (x > x0) buf_store<kInplaceAux>(s, rt, cbase, uint32_t(a) * lenB);
+        if (x == xend - 1) buf_store<kInplaceAux>(v[a], rt, nbase[0] + uint32_t(a) * nlen[0], 0u);   // to x + 1
+      } else {                         // slot a of x receives fbar~_a(x + 1)
+        T s = lane_value(v[a], lane + 1);
+        if (lane == 63 && x + 1 < xend) s = edge_dn[wave + 1][a];
+        if (x + 1 < xend) buf_store<kInplaceAux>(s, rt, cbase, uint32_t(a) * lenB);
+        if (x == x0) buf_store<kInplaceAux>(v[a], rt, nbase[2] + uint32_t(a) * nlen[2], 0u);          // to x - 1
+      }
+    }
+  }
+  if constexpr (TOT) {
+    __shared__ double sh[4 * 8];
+    block_sum<4>(acc, sh);
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) args.partials[uint64_t(blockIdx.x) * 4 + i] = acc[i];
     }
   }
 }
@@ -1234,23 +1263,35 @@ hipError_t step_impl(const StepArgs<typename ST::R>& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <int Q, class ST, bool TOT>
+void inplace_launch(const StepArgs<typename ST::R>& a, int parity, dim3 grid, int bx, hipStream_t st) {
+  if (parity == 0) {
+    if (a.mask)
+      hipLaunchKernelGGL((k_step_inplace<Q, ST, true, false, TOT>), grid, dim3(bx), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_step_inplace<Q, ST, false, false, TOT>), grid, dim3(bx), 0, st, a);
+  } else {
+    if (a.mask)
+      hipLaunchKernelGGL((k_step_inplace<Q, ST, true, true, TOT>), grid, dim3(bx), 0, st, a);
+    else if (CMLBM_ALIGNED_SCATTER == 2 || (CMLBM_ALIGNED_SCATTER == 1 && sizeof(typename ST::T) == 2))
+      hipLaunchKernelGGL((k_scatter_periodic<Q, ST, TOT>), grid, dim3(bx), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_step_inplace<Q, ST, false, true, TOT>), grid, dim3(bx), 0, st, a);
+  }
+}
+
 template <int Q, class ST>
 hipError_t inplace_impl(const StepArgs<typename ST::R>& a, int parity, hipStream_t st) {
   const int bx = step_block(a.g);
   const dim3 grid = step_grid(a.g, bx);
-  if (parity == 0) {
-    if (a.mask)
-      hipLaunchKernelGGL((k_step_inplace<Q, ST, true, false>), grid, dim3(bx), 0, st, a);
-    else
-      hipLaunchKernelGGL((k_step_inplace<Q, ST, false, false>), grid, dim3(bx), 0, st, a);
-  } else {
-    if (a.mask)
-      hipLaunchKernelGGL((k_step_inplace<Q, ST, true, true>), grid, dim3(bx), 0, st, a);
-    else if (CMLBM_ALIGNED_SCATTER == 2 || (CMLBM_ALIGNED_SCATTER == 1 && sizeof(typename ST::T) == 2))
-      hipLaunchKernelGGL((k_scatter_periodic<Q, ST>), grid, dim3(bx), 0, st, a);
-    else
-      hipLaunchKernelGGL((k_step_inplace<Q, ST, false, true>), grid, dim3(bx), 0, st, a);
+  if (!a.partials) {
+    inplace_launch<Q, ST, false>(a, parity, grid, bx, st);
+    return hipGetLastError();
   }
+  inplace_launch<Q, ST, true>(a, parity, grid, bx, st);
+  hipLaunchKernelGGL(k_reduce_chunks<4>, dim3(kReduceChunks), dim3(kBlock), 0, st, a.partials, uint64_t(grid.x),
+                     a.stage);
+  hipLaunchKernelGGL(k_reduce_rows, dim3(4), dim3(kBlock), 0, st, a.stage, kReduceChunks, 4, a.totals, 0);
   return hipGetLastError();
 }
 

@@ -308,3 +308,34 @@ def test_inplace_time_dependent_force_and_per_mass(q, prec):
         sim.step_inplace(buf, n & 1)
     fl = torch.from_numpy(~solid).cuda()
     assert torch.equal(sim.gather(f_post)[:, fl], sim.export_populations(buf)[:, fl])
+
+
+@pytest.mark.parametrize("q,prec,mkind", [(27, F64, "walls"), (27, F32, None), (15, F32, "walls"), (27, F16, None),
+                                          (15, BF16, None)])
+def test_inplace_fused_totals(q, prec, mkind):
+    """cmlbm_step_inplace_totals reduces, at every step, the same FP64 totals as
+    cmlbm_step_totals of the two-buffer run (both phases; 16-bit storage without
+    walls takes the aligned-store scatter phase)."""
+    shape = (6, 5, 67)
+    print(f"case fused totals q{q} p{prec} {mkind}", flush=True)
+    solid = _mask(mkind, shape)
+    sim = gpu_setup(q, shape, prec, list(np.random.default_rng(5).uniform(0.8, 1.9, q - 4)), _force("field", shape),
+                    solid)
+    rho0, u0 = _fields(shape, 8)
+    buf, f_post = _inplace_buffer(sim, rho0, u0)
+    other = sim.populations()
+    t_two = torch.zeros(4, dtype=torch.float64, device="cuda")
+    t_in = torch.full((4,), float("nan"), dtype=torch.float64, device="cuda")
+    for n in range(6):
+        sim.step(f_post, other, totals=t_two)
+        f_post, other = other, f_post
+        sim.step_inplace(buf, n & 1, totals=t_in)
+        assert torch.equal(t_two, t_in), (n, t_two.tolist(), t_in.tolist())
+    fl = slice(None) if solid is None else torch.from_numpy(~solid).cuda()
+    assert torch.equal(sim.gather(f_post)[:, fl], sim.export_populations(buf)[:, fl])
+    cm = lib()
+    assert cm.load_library().cmlbm_step_inplace_totals(sim.h, _ptr_of(buf), 0, None, None) == -1
+
+
+def _ptr_of(t):
+    return t.data_ptr()
