@@ -9,11 +9,13 @@ dependence of fbar(0) on F.  dL/dF and dL/domega accumulate in FP64 on the
 device.
 
 x(n) is recovered from stored snapshots by recomputation.  Two schedules:
-``every=k`` keeps x(0), x(k), x(2k), ... and replays one segment at a time with
-all its states stored; ``snapshots=s`` keeps at most s states and places them
-by the binomial (optimal offline) rule: reversing n steps from a stored state
-with s free slots costs min over m of [m + cost(n - m, s - 1) + cost(m, s)]
-recomputed steps, cost(1, s) = 0, cost(n, 0) = n(n - 1)/2.
+``every=k`` keeps x(k), x(2k), ... and replays one segment at a time with all
+its states stored; ``snapshots=s`` keeps at most s states and places them by
+the binomial (optimal offline) rule: reversing n steps from a stored state with
+s free slots costs min over m of [m + cost(n - m, s - 1) + cost(m, s)]
+recomputed steps, cost(1, s) = 0, cost(n, 0) = n(n - 1)/2.  x(0) itself is not
+kept: the backward sweep rebuilds it from (rho0, u0) with the initial-state
+kernels (bit-identical) when it reaches the first interval.
 """
 import functools
 import math
