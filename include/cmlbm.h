@@ -26,7 +26,10 @@
  * Streams:    `stream` is a hipStream_t (NULL = the default stream).  Work is
  *             enqueued asynchronously; only the calls with host outputs
  *             (cmlbm_totals, cmlbm_totals_pre, cmlbm_kinetic_energy_sum)
- *             synchronize.
+ *             synchronize.  The calls that reduce (the *_totals calls, the
+ *             adjoint and loss calls) use the handle's device scratch: work
+ *             from one handle must not overlap in time across streams (use one
+ *             stream per handle, or order the streams).
  * Devices:    a handle belongs to the device current at cmlbm_create; every
  *             call that launches work returns EINVAL when another device is
  *             current.
