@@ -220,6 +220,32 @@ def test_initial_state_velocity_is_u0():
         assert np.abs(rho - rho0).max() < 1e-14 and np.abs(u - u0).max() < 1e-14
 
 
+@pytest.mark.parametrize("walls", [False, True])
+def test_kinetic_energy_of_initial_state(walls):
+    # The loss of the differentiable runs (reading 15): for the initial state of
+    # (rho0, u0) under a force field, the velocity read back is u0 exactly, so
+    # the mean kinetic energy is the plain mean of rho0 |u0|^2 / 2 over the
+    # fluid nodes, and the totals are the sums of rho0 and rho0 u0.
+    rng = np.random.default_rng(6)
+    shape = (4, 5, 6)
+    rho0 = 1 + 0.01 * rng.standard_normal(shape)
+    u0 = 0.05 * rng.standard_normal((3,) + shape)
+    F = 1e-3 * rng.standard_normal((3,) + shape)
+    solid = None
+    fluid = np.ones(shape, dtype=bool)
+    if walls:
+        solid = np.zeros(shape, dtype=bool)
+        solid[0] = solid[:, 0] = True
+        fluid = ~solid
+    for lat in (D3Q27, D3Q15):
+        f = lbm.initial_state(lat, rho0, u0, F, solid)
+        want = (0.5 * rho0 * (u0**2).sum(axis=0))[fluid].mean()
+        assert abs(lbm.kinetic_energy(lat, f, F, solid) - want) < 1e-15
+        T = lbm.totals(lat, f, F, solid)
+        assert abs(T[0] - rho0[fluid].sum()) < 1e-12
+        assert np.abs(T[1:] - (rho0 * u0)[:, fluid].sum(axis=1)).max() < 1e-13
+
+
 def test_streaming_periodic_shift():
     # A single marked population travels one link per step along e_a.
     lat = D3Q27
