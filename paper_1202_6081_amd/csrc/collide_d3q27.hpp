@@ -151,31 +151,6 @@ CMLBM_HD void inv_pass_adj(const R (&m)[27], R u, R (&g)[27], R& gu) {
   }
 }
 
-// Density and velocity of cube-ordered populations (Eqs. densitycalculation,
-// velocitycalculation).
-template <typename R>
-CMLBM_HD void moments0_27(const R (&m)[27], R Fx, R Fy, R Fz, R& rho, R& ux, R& uy, R& uz) {
-  R s[3] = {R(0), R(0), R(0)};   // sums over the planes e_x = -1, 0, +1
-  R ty[3] = {R(0), R(0), R(0)};
-  R tz[3] = {R(0), R(0), R(0)};
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const R v = m[K3(a, b, c)];
-        s[a] += v;
-        ty[b] += v;
-        tz[c] += v;
-      }
-  rho = s[0] + s[1] + s[2];
-  const R inv = R(1) / rho;
-  ux = (s[2] - s[0] + R(0.5) * Fx) * inv;
-  uy = (ty[2] - ty[0] + R(0.5) * Fy) * inv;
-  uz = (tz[2] - tz[0] + R(0.5) * Fz) * inv;
-}
-
 // Relax the central moments in m (cube layout) in place.  PM: attractor form,
 // 0 literal, 1 per unit mass, -1 as p.per_mass says (run time).
 template <int PM = -1, typename R>

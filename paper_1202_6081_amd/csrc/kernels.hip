@@ -928,11 +928,6 @@ __global__ __launch_bounds__(256) void k_scatter_post(Geom g, const typename ST:
 // blockDim.x consecutive x of one row), so row bases are uniform and the
 // neighbour rows that one segment gathers from are reused by the next ones
 // from the same XCD's L2; block ids are permuted per XCD as in the step.
-template <typename T>
-__device__ __forceinline__ void st32(T* base, uint32_t idx, T v) {
-  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + idx * uint32_t(sizeof(T))) = v;
-}
-
 // The adjoint's output stores (lambda, dL/dF): CMLBM_ADJ_NT = 1 streams them
 // past the caches, as the step's population stores, so that they do not evict
 // the neighbour rows the gathers reuse.
