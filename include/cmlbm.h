@@ -22,7 +22,8 @@
  *             about 120 KiB), all allocated by cmlbm_create: no other call
  *             allocates.
  *             Device pointers must be aligned to their element size
- *             (hipMalloc and torch allocations are).
+ *             (hipMalloc and torch allocations are); a call given a
+ *             misaligned one returns EINVAL before launching anything.
  * Streams:    `stream` is a hipStream_t (NULL = the default stream).  Work is
  *             enqueued asynchronously; only the calls with host outputs
  *             (cmlbm_totals, cmlbm_totals_pre, cmlbm_kinetic_energy_sum)

@@ -6,7 +6,9 @@
 #include <hip/hip_runtime_api.h>
 
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
+#include <initializer_list>
 #include <string>
 
 #include "kernels.hpp"
@@ -58,6 +60,31 @@ cmlbm_status on_device(cmlbm_sim* s) {
                                      std::to_string(s->device));
   return CMLBM_OK;
 }
+
+// Element sizes: population buffers hold the storage type, "real" fields the
+// arithmetic type.
+size_t pop_bytes(const cmlbm_sim* s) { return s->prec == CMLBM_F64 ? 8 : (s->prec == CMLBM_F32 ? 4 : 2); }
+size_t real_bytes(const cmlbm_sim* s) { return s->prec == CMLBM_F64 ? 8 : 4; }
+
+struct DevBuf {
+  const void* p;
+  size_t elem;
+};
+
+// Every kernel reads and writes its buffers one element at a time, with loads
+// and stores of the element's size: each pointer must be aligned to it.
+cmlbm_status check_aligned(cmlbm_sim* s, std::initializer_list<DevBuf> bufs) {
+  for (const DevBuf& b : bufs)
+    if (reinterpret_cast<uintptr_t>(b.p) % b.elem != 0)
+      return fail(s, CMLBM_EINVAL, "device buffer not aligned to its element size (" + std::to_string(b.elem) + " B)");
+  return CMLBM_OK;
+}
+
+#define CMLBM_CHECK_ALIGNED(s, ...)                          \
+  do {                                                       \
+    const cmlbm_status al_ = check_aligned(s, {__VA_ARGS__}); \
+    if (al_ != CMLBM_OK) return al_;                         \
+  } while (0)
 
 #define CMLBM_WORK_ENTRY(s)                   \
   do {                                        \
@@ -212,6 +239,7 @@ cmlbm_status cmlbm_set_force_uniform(cmlbm_sim* s, double fx, double fy, double 
 
 cmlbm_status cmlbm_set_force_field(cmlbm_sim* s, const void* F_dev) {
   if (!s) return CMLBM_EINVAL;
+  CMLBM_CHECK_ALIGNED(s, {F_dev, real_bytes(s)});
   s->Ffield = F_dev;
   if (!F_dev) s->F[0] = s->F[1] = s->F[2] = 0.0;
   return ok(s);
@@ -242,6 +270,8 @@ cmlbm_status cmlbm_init_equilibrium(cmlbm_sim* s, const void* rho_dev, const voi
   CMLBM_WORK_ENTRY(s);
   if (!rho_dev || !u_dev || !f_pre_dev || !f_post_dev) return fail(s, CMLBM_EINVAL, "NULL buffer");
   if (f_pre_dev == f_post_dev) return fail(s, CMLBM_EINVAL, "f_pre and f_post must differ");
+  CMLBM_CHECK_ALIGNED(s, {rho_dev, real_bytes(s)}, {u_dev, real_bytes(s)}, {f_pre_dev, real_bytes(s)},
+                      {f_post_dev, pop_bytes(s)});
   hipError_t e = cmlbm::launch_init(s->q, s->prec, s->g, rho_dev, u_dev, make_force<double>(s),
                                     make_force<float>(s), s->mask, f_pre_dev, f_post_dev,
                                     static_cast<hipStream_t>(stream));
@@ -252,6 +282,7 @@ cmlbm_status cmlbm_init_equilibrium_inplace(cmlbm_sim* s, const void* rho_dev, c
                                             void* stream) {
   CMLBM_WORK_ENTRY(s);
   if (!rho_dev || !u_dev || !f_dev) return fail(s, CMLBM_EINVAL, "NULL buffer");
+  CMLBM_CHECK_ALIGNED(s, {rho_dev, real_bytes(s)}, {u_dev, real_bytes(s)}, {f_dev, pop_bytes(s)});
   hipError_t e = cmlbm::launch_init(s->q, s->prec, s->g, rho_dev, u_dev, make_force<double>(s),
                                     make_force<float>(s), s->mask, f_dev, nullptr,
                                     static_cast<hipStream_t>(stream));
@@ -263,6 +294,7 @@ namespace {
 cmlbm_status step_common(cmlbm_sim* s, const void* f_in, void* f_out, double* totals_dev, void* stream) {
   if (!f_in || !f_out) return fail(s, CMLBM_EINVAL, "NULL population buffer");
   if (f_in == f_out) return fail(s, CMLBM_EINVAL, "f_in and f_out must differ (pull streaming)");
+  CMLBM_CHECK_ALIGNED(s, {f_in, pop_bytes(s)}, {f_out, pop_bytes(s)}, {totals_dev, sizeof(double)});
   double* partials = nullptr;
   double* stage = nullptr;
   if (totals_dev) {
@@ -313,6 +345,7 @@ cmlbm_status cmlbm_run(cmlbm_sim* s, void* f_a, void* f_b, int nsteps, void* str
   if (nsteps < 0) return fail(s, CMLBM_EINVAL, "nsteps < 0");
   if (!f_a || !f_b) return fail(s, CMLBM_EINVAL, "NULL population buffer");
   if (f_a == f_b) return fail(s, CMLBM_EINVAL, "f_a and f_b must differ");
+  CMLBM_CHECK_ALIGNED(s, {f_a, pop_bytes(s)}, {f_b, pop_bytes(s)});
   void* bufs[2] = {f_a, f_b};
   for (int n = 0; n < nsteps; ++n) {
     cmlbm_status st = cmlbm_step(s, bufs[n & 1], bufs[(n + 1) & 1], stream);
@@ -326,6 +359,7 @@ cmlbm_status cmlbm_gather_precollision(cmlbm_sim* s, const void* f_post, void* f
   CMLBM_WORK_ENTRY(s);
   if (!f_post || !f_pre) return fail(s, CMLBM_EINVAL, "NULL buffer");
   if (f_post == f_pre) return fail(s, CMLBM_EINVAL, "f_post and f_pre must differ");
+  CMLBM_CHECK_ALIGNED(s, {f_post, pop_bytes(s)}, {f_pre, real_bytes(s)});
   hipError_t e = cmlbm::launch_gather(s->q, s->prec, make_aux<double>(s, f_post, f_pre, nullptr),
                                       make_aux<float>(s, f_post, f_pre, nullptr), static_cast<hipStream_t>(stream));
   return check_hip(s, e, "gather_precollision");
@@ -335,6 +369,7 @@ cmlbm_status cmlbm_export_populations(cmlbm_sim* s, const void* f_buf, void* f_s
   CMLBM_WORK_ENTRY(s);
   if (!f_buf || !f_soa) return fail(s, CMLBM_EINVAL, "NULL buffer");
   if (f_buf == f_soa) return fail(s, CMLBM_EINVAL, "f_buf and f_soa must differ");
+  CMLBM_CHECK_ALIGNED(s, {f_buf, pop_bytes(s)}, {f_soa, real_bytes(s)});
   hipError_t e = cmlbm::launch_convert(s->q, s->prec, s->g, f_buf, f_soa, true, static_cast<hipStream_t>(stream));
   return check_hip(s, e, "export_populations");
 }
@@ -343,6 +378,7 @@ cmlbm_status cmlbm_import_populations(cmlbm_sim* s, const void* f_soa, void* f_b
   CMLBM_WORK_ENTRY(s);
   if (!f_buf || !f_soa) return fail(s, CMLBM_EINVAL, "NULL buffer");
   if (f_buf == f_soa) return fail(s, CMLBM_EINVAL, "f_buf and f_soa must differ");
+  CMLBM_CHECK_ALIGNED(s, {f_buf, pop_bytes(s)}, {f_soa, real_bytes(s)});
   hipError_t e = cmlbm::launch_convert(s->q, s->prec, s->g, f_soa, f_buf, false, static_cast<hipStream_t>(stream));
   return check_hip(s, e, "import_populations");
 }
@@ -351,6 +387,7 @@ namespace {
 
 cmlbm_status macro_common(cmlbm_sim* s, const void* f, void* rho, void* u, bool pre, void* stream) {
   if (!f || !rho || !u) return fail(s, CMLBM_EINVAL, "NULL buffer");
+  CMLBM_CHECK_ALIGNED(s, {f, pop_bytes(s)}, {rho, real_bytes(s)}, {u, real_bytes(s)});
   hipError_t e = cmlbm::launch_macro(s->q, s->prec, make_aux<double>(s, f, rho, u), make_aux<float>(s, f, rho, u),
                                      pre, static_cast<hipStream_t>(stream));
   return check_hip(s, e, "macroscopic");
@@ -358,6 +395,7 @@ cmlbm_status macro_common(cmlbm_sim* s, const void* f, void* rho, void* u, bool 
 
 cmlbm_status totals_common(cmlbm_sim* s, const void* f, double out4[4], bool pre, void* stream) {
   if (!f || !out4) return fail(s, CMLBM_EINVAL, "NULL buffer");
+  CMLBM_CHECK_ALIGNED(s, {f, pop_bytes(s)});
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipError_t e = cmlbm::launch_totals(s->q, s->prec, make_aux<double>(s, f, nullptr, nullptr),
                                       make_aux<float>(s, f, nullptr, nullptr), pre, s->totals_partials,
@@ -385,6 +423,7 @@ namespace {
 cmlbm_status inplace_common(cmlbm_sim* s, void* f, int parity, double* totals_dev, void* stream) {
   if (!f) return fail(s, CMLBM_EINVAL, "NULL population buffer");
   if (parity != 0 && parity != 1) return fail(s, CMLBM_EINVAL, "parity must be 0 or 1");
+  CMLBM_CHECK_ALIGNED(s, {f, pop_bytes(s)}, {totals_dev, sizeof(double)});
   double* partials = nullptr;
   double* stage = nullptr;
   if (totals_dev) {
@@ -433,6 +472,7 @@ cmlbm_status cmlbm_run_inplace(cmlbm_sim* s, void* f, int nsteps, void* stream) 
   CMLBM_WORK_ENTRY(s);
   if (!f) return fail(s, CMLBM_EINVAL, "NULL population buffer");
   if (nsteps < 0 || (nsteps & 1)) return fail(s, CMLBM_EINVAL, "nsteps must be even and >= 0");
+  CMLBM_CHECK_ALIGNED(s, {f, pop_bytes(s)});
   for (int n = 0; n < nsteps; ++n) {
     cmlbm_status st = cmlbm_step_inplace(s, f, n & 1, stream);
     if (st != CMLBM_OK) return st;
@@ -456,6 +496,8 @@ cmlbm_status cmlbm_adjoint_step(cmlbm_sim* s, const void* f_post_prev, const voi
   if (!f_post_prev || !lam_next || !lam || !dLdF_dev || !dLdomega_dev) return fail(s, CMLBM_EINVAL, "NULL buffer");
   if (lam == lam_next || lam == f_post_prev || lam_next == f_post_prev)
     return fail(s, CMLBM_EINVAL, "lam, lam_next and f_post_prev must differ");
+  CMLBM_CHECK_ALIGNED(s, {f_post_prev, pop_bytes(s)}, {lam_next, real_bytes(s)}, {lam, real_bytes(s)},
+                      {dLdF_dev, sizeof(double)}, {dLdomega_dev, sizeof(double)});
   const int nblk = s->adj_nblk;
   cmlbm::AdjArgs<double> a64{};
   cmlbm::AdjArgs<float> a32{};
@@ -487,6 +529,7 @@ cmlbm_status cmlbm_adjoint_step(cmlbm_sim* s, const void* f_post_prev, const voi
 cmlbm_status cmlbm_kinetic_energy_sum(cmlbm_sim* s, const void* f_pre, double* out, void* stream) {
   CMLBM_WORK_ENTRY(s);
   if (!f_pre || !out) return fail(s, CMLBM_EINVAL, "NULL buffer");
+  CMLBM_CHECK_ALIGNED(s, {f_pre, real_bytes(s)});
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipError_t e = cmlbm::launch_ke_sum(s->q, s->prec, s->g, f_pre, s->mask, make_force<double>(s), make_force<float>(s),
                                       s->totals_partials, cmlbm::kTotalsBlocks, s->totals_out, st);
@@ -501,6 +544,7 @@ cmlbm_status cmlbm_kinetic_energy_seed(cmlbm_sim* s, const void* f_pre, double s
   CMLBM_WORK_ENTRY(s);
   if (!f_pre || !lam || !dLdF_dev) return fail(s, CMLBM_EINVAL, "NULL buffer");
   if (f_pre == lam) return fail(s, CMLBM_EINVAL, "f_pre and lam must differ");
+  CMLBM_CHECK_ALIGNED(s, {f_pre, real_bytes(s)}, {lam, real_bytes(s)}, {dLdF_dev, sizeof(double)});
   hipError_t e = cmlbm::launch_ke_seed(s->q, s->prec, s->g, f_pre, s->mask, make_force<double>(s),
                                        make_force<float>(s), scale, lam, dLdF_dev, s->totals_partials,
                                        cmlbm::kTotalsBlocks, static_cast<hipStream_t>(stream));
@@ -511,6 +555,7 @@ cmlbm_status cmlbm_init_adjoint(cmlbm_sim* s, const void* u0_dev, const void* la
                                 void* stream) {
   CMLBM_WORK_ENTRY(s);
   if (!u0_dev || !lam0_dev || !dLdF_dev) return fail(s, CMLBM_EINVAL, "NULL buffer");
+  CMLBM_CHECK_ALIGNED(s, {u0_dev, real_bytes(s)}, {lam0_dev, real_bytes(s)}, {dLdF_dev, sizeof(double)});
   hipError_t e = cmlbm::launch_init_adjoint(s->q, s->prec, s->g, u0_dev, lam0_dev, s->mask, make_force<double>(s),
                                             make_force<float>(s), dLdF_dev, s->totals_partials,
                                             cmlbm::kTotalsBlocks, static_cast<hipStream_t>(stream));
