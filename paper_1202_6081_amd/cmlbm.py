@@ -269,7 +269,9 @@ def cmlbm_version():
 # ----------------------------------------------------------------------------
 class Sim:
     """Owns one cmlbm handle.  Shapes: populations (Q, nz, ny, nx), scalars
-    (nz, ny, nx), vectors (3, nz, ny, nx)."""
+    (nz, ny, nx), vectors (3, nz, ny, nx).  The C calls take bare pointers, so
+    every tensor passed here is checked first for device, dtype and size: a
+    short buffer would otherwise be read or written past its end."""
 
     def __init__(self, q, nx, ny, nz, precision=F32, device=None):
         self.q, self.nx, self.ny, self.nz, self.precision = q, nx, ny, nz, precision
@@ -292,6 +294,28 @@ class Sim:
             pass
 
     # buffers -----------------------------------------------------------
+    @property
+    def nodes(self):
+        return self.nx * self.ny * self.nz
+
+    def _need(self, t, dtype, numel, name):
+        """Device, dtype and size check of a tensor argument (raw integer
+        pointers pass unchecked)."""
+        if isinstance(t, torch.Tensor):
+            if t.device != self.device or t.dtype != dtype or t.numel() < numel:
+                raise CmlbmError(-1, f"{name}: expected a {dtype} tensor of at least {numel} elements on "
+                                     f"{self.device}, got {t.dtype}, {t.numel()} elements on {t.device}")
+        return t
+
+    def _pop(self, t, name):
+        return self._need(t, self.store, self.q * self.nodes, name)
+
+    def _realpop(self, t, name):
+        return self._need(t, self.real, self.q * self.nodes, name)
+
+    def _dLdF(self, t):
+        return self._need(t, torch.float64, 3 * self.nodes if "force" in self._keep else 3, "dLdF")
+
     def populations(self):
         return torch.empty((self.q, self.nz, self.ny, self.nx), dtype=self.store, device=self.device)
 
@@ -306,6 +330,8 @@ class Sim:
         """F: 3 numbers (uniform) or a (3, nz, ny, nx) real tensor (field)."""
         if isinstance(F, torch.Tensor) and F.dim() == 4:
             F = F.to(device=self.device, dtype=self.real).contiguous()
+            if F.numel() != 3 * self.nodes:
+                raise CmlbmError(-1, f"force field: expected shape (3, {self.nz}, {self.ny}, {self.nx})")
             self._keep["force"] = F
             cmlbm_set_force_field(self.h, F)
         else:
@@ -325,6 +351,8 @@ class Sim:
             cmlbm_set_mask(self.h, None)
             return
         m = solid.to(device=self.device, dtype=torch.uint8).contiguous()
+        if m.numel() != self.nodes:
+            raise CmlbmError(-1, f"mask: expected shape ({self.nz}, {self.ny}, {self.nx})")
         self._keep["mask"] = m
         cmlbm_set_mask(self.h, m)
 
@@ -332,14 +360,18 @@ class Sim:
     def init_equilibrium(self, rho, u, f_post=None, f_pre=None, stream=None):
         rho = rho.to(device=self.device, dtype=self.real).contiguous()
         u = u.to(device=self.device, dtype=self.real).contiguous()
-        f_post = self.populations() if f_post is None else f_post
-        f_pre = self.real_populations() if f_pre is None else f_pre
+        f_post = self.populations() if f_post is None else self._pop(f_post, "f_post")
+        f_pre = self.real_populations() if f_pre is None else self._realpop(f_pre, "f_pre")
+        self._need(rho, self.real, self.nodes, "rho")
+        self._need(u, self.real, 3 * self.nodes, "u")
         cmlbm_init_equilibrium(self.h, rho, u, f_pre, f_post, stream)
         return f_post, f_pre
 
     def step(self, f_in, f_out, stream=None, totals=None):
         """One step f_in -> f_out.  With `totals` (4 float64 on the device), the
         same pass also writes the FP64 (mass, momentum) of f_in's state."""
+        self._pop(f_in, "f_in")
+        self._pop(f_out, "f_out")
         if totals is None:
             cmlbm_step(self.h, f_in, f_out, stream)
         else:
@@ -347,44 +379,50 @@ class Sim:
 
     def run(self, f_a, f_b, nsteps, stream=None):
         """Returns the buffer holding the last state."""
+        self._pop(f_a, "f_a")
+        self._pop(f_b, "f_b")
         return f_b if cmlbm_run(self.h, f_a, f_b, nsteps, stream) else f_a
 
     def gather(self, f_post, out=None, stream=None):
-        out = self.real_populations() if out is None else out
-        cmlbm_gather_precollision(self.h, f_post, out, stream)
+        out = self.real_populations() if out is None else self._realpop(out, "out")
+        cmlbm_gather_precollision(self.h, self._pop(f_post, "f_post"), out, stream)
         return out
 
     def export_populations(self, f_buf, out=None, stream=None):
-        out = self.real_populations() if out is None else out
-        cmlbm_export_populations(self.h, f_buf, out, stream)
+        out = self.real_populations() if out is None else self._realpop(out, "out")
+        cmlbm_export_populations(self.h, self._pop(f_buf, "f_buf"), out, stream)
         return out
 
     def import_populations(self, f_soa, f_buf=None, stream=None):
-        f_buf = self.populations() if f_buf is None else f_buf
-        cmlbm_import_populations(self.h, f_soa.to(device=self.device, dtype=self.real).contiguous(), f_buf, stream)
+        f_buf = self.populations() if f_buf is None else self._pop(f_buf, "f_buf")
+        f_soa = self._realpop(f_soa.to(device=self.device, dtype=self.real).contiguous(), "f_soa")
+        cmlbm_import_populations(self.h, f_soa, f_buf, stream)
         return f_buf
 
     def macroscopic(self, f_post, stream=None):
         rho = torch.empty((self.nz, self.ny, self.nx), dtype=self.real, device=self.device)
         u = torch.empty((3, self.nz, self.ny, self.nx), dtype=self.real, device=self.device)
-        cmlbm_macroscopic(self.h, f_post, rho, u, stream)
+        cmlbm_macroscopic(self.h, self._pop(f_post, "f_post"), rho, u, stream)
         return rho, u
 
     def totals(self, f_post, stream=None):
-        return cmlbm_totals(self.h, f_post, stream)
+        return cmlbm_totals(self.h, self._pop(f_post, "f_post"), stream)
 
     # in-place stepping (one buffer; phase 0 = pre-collision populations) --
     def init_equilibrium_inplace(self, rho, u, f=None, stream=None):
         """fbar(x, 0) into an in-place buffer (phase 0)."""
         rho = rho.to(device=self.device, dtype=self.real).contiguous()
         u = u.to(device=self.device, dtype=self.real).contiguous()
-        f = self.populations() if f is None else f
+        f = self.populations() if f is None else self._pop(f, "f")
+        self._need(rho, self.real, self.nodes, "rho")
+        self._need(u, self.real, 3 * self.nodes, "u")
         cmlbm_init_equilibrium_inplace(self.h, rho, u, f, stream)
         return f
 
     def step_inplace(self, f, parity, stream=None, totals=None):
         """One in-place step; with `totals` (4 float64 on the device), the same
         pass also writes the FP64 (mass, momentum) of the state it collides."""
+        self._pop(f, "f")
         if totals is None:
             cmlbm_step_inplace(self.h, f, parity, stream)
         else:
@@ -393,26 +431,37 @@ class Sim:
     def run_inplace(self, f, nsteps, stream=None):
         """nsteps (even) in-place steps; f holds the pre-collision state in
         phase 0 before and after."""
-        cmlbm_run_inplace(self.h, f, nsteps, stream)
+        cmlbm_run_inplace(self.h, self._pop(f, "f"), nsteps, stream)
         return f
 
     def macroscopic_pre(self, f_pre_buf, stream=None):
         rho = torch.empty((self.nz, self.ny, self.nx), dtype=self.real, device=self.device)
         u = torch.empty((3, self.nz, self.ny, self.nx), dtype=self.real, device=self.device)
-        cmlbm_macroscopic_pre(self.h, f_pre_buf, rho, u, stream)
+        cmlbm_macroscopic_pre(self.h, self._pop(f_pre_buf, "f_pre_buf"), rho, u, stream)
         return rho, u
 
     def totals_pre(self, f_pre_buf, stream=None):
-        return cmlbm_totals_pre(self.h, f_pre_buf, stream)
+        return cmlbm_totals_pre(self.h, self._pop(f_pre_buf, "f_pre_buf"), stream)
 
     def adjoint_step(self, f_post_prev, lam_next, lam, dLdF, dLdomega, stream=None):
+        self._pop(f_post_prev, "f_post_prev")
+        self._realpop(lam_next, "lam_next")
+        self._realpop(lam, "lam")
+        self._dLdF(dLdF)
+        self._need(dLdomega, torch.float64, self.q - 4, "dLdomega")
         cmlbm_adjoint_step(self.h, f_post_prev, lam_next, lam, dLdF, dLdomega, stream)
 
     def kinetic_energy_sum(self, f_pre, stream=None):
-        return cmlbm_kinetic_energy_sum(self.h, f_pre, stream)
+        return cmlbm_kinetic_energy_sum(self.h, self._realpop(f_pre, "f_pre"), stream)
 
     def kinetic_energy_seed(self, f_pre, scale, lam, dLdF, stream=None):
+        self._realpop(f_pre, "f_pre")
+        self._realpop(lam, "lam")
+        self._dLdF(dLdF)
         cmlbm_kinetic_energy_seed(self.h, f_pre, scale, lam, dLdF, stream)
 
     def init_adjoint(self, u0, lam0, dLdF, stream=None):
+        self._need(u0, self.real, 3 * self.nodes, "u0")
+        self._realpop(lam0, "lam0")
+        self._dLdF(dLdF)
         cmlbm_init_adjoint(self.h, u0, lam0, dLdF, stream)

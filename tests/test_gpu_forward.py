@@ -261,6 +261,17 @@ def test_misaligned_buffers_rejected():
     assert L.cmlbm_step_totals(sim.h, f_post.data_ptr(), base, base + 4, st) == -1   # FP64 totals on 4 B
     torch.cuda.synchronize()
     assert int(torch.count_nonzero(big)) == 0
+    # The binding checks each tensor's device, dtype and size before the call.
+    short = torch.zeros(f_post.numel() - 1, dtype=torch.float32, device="cuda")
+    for bad in (short, big.double(), big.cpu()):
+        with pytest.raises(lib().CmlbmError):
+            sim.step(f_post, bad)
+    with pytest.raises(lib().CmlbmError):
+        sim.set_force(torch.zeros((3, 4, 4, 63), device="cuda"))
+    with pytest.raises(lib().CmlbmError):
+        sim.macroscopic_pre(short)
+    torch.cuda.synchronize()
+    assert int(torch.count_nonzero(short)) == 0
 
 
 @pytest.mark.parametrize("q", [27, 15])
