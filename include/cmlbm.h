@@ -74,7 +74,7 @@ extern "C" {
 typedef enum {
   CMLBM_OK = 0,
   CMLBM_EINVAL = -1,       /* bad argument: null pointer, size, rate, aliasing */
-  CMLBM_EUNSUPPORTED = -2, /* valid request this build does not provide */
+  CMLBM_EUNSUPPORTED = -2, /* valid request this library does not provide */
   CMLBM_EDEVICE = -3,      /* HIP runtime error; message in cmlbm_last_error */
   CMLBM_ENOMEM = -4,       /* device scratch allocation failed */
   CMLBM_ESTATE = -5        /* call order violated */
