@@ -67,6 +67,29 @@ def build_c_test(verbose=False):
     return C_TEST_BIN
 
 
+PROBE_SRC = os.path.join(CSRC, "hbm_probe.hip")
+PROBE_BIN = os.path.join(HERE, "hbm_probe")
+
+
+def build_probe(verbose=False):
+    """The HBM rate probe (a standalone HIP program, no part of the library):
+    plain read, write and copy streams and the step's memory traffic without
+    its arithmetic, the ceilings the step's roofline fraction is read against."""
+    tmp = PROBE_BIN + ".tmp"
+    cmd = [hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-Wno-unused-command-line-argument", PROBE_SRC, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("hipcc failed building hbm_probe")
+    os.replace(tmp, PROBE_BIN)
+    return PROBE_BIN
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
     print(build_c_test(verbose=True))
+    print(build_probe(verbose=True))
