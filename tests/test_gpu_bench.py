@@ -36,3 +36,18 @@ def test_bench_small_lattice_json_line():
     adj = r["adjoint"]
     assert adj["adjoint_steps"] == 6 and adj["recomputed_steps"] >= 0
     assert r["adjoint_forward_ratio"] == adj["ratio_backward_over_forward_steps"] > 0
+
+
+def test_hbm_probe_runs():
+    # The HBM rate probe that the roofline is read against, on a 256^3 lattice.
+    print("case hbm_probe 256", flush=True)
+    exe = os.path.join(ROOT, "paper_1202_6081_amd", "hbm_probe")
+    assert os.path.exists(exe), "hbm_probe is built by __graft_entry__.build()"
+    res = subprocess.run([exe, "256"], capture_output=True, text=True, timeout=120)
+    assert res.returncode == 0, res.stderr[-2000:]
+    r = json.loads(res.stdout.strip().splitlines()[-1])
+    assert r["nodes"] == 256**3
+    for key in ("read_GBs", "write_GBs", "copy_GBs", "step_traffic_pull_GBs", "step_traffic_own_node_GBs"):
+        assert 100.0 < r[key] < 8000.0, (key, r[key])
+    bad = subprocess.run([exe, "100"], capture_output=True, text=True, timeout=60)
+    assert bad.returncode == 2                # sizes the probe's launch shape cannot cover are refused
