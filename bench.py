@@ -18,6 +18,7 @@ import argparse
 import hashlib
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -38,6 +39,23 @@ def kernel_source_hash():
         with open(os.path.join(ROOT, rel), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+PROBE = os.path.join(ROOT, "paper_1202_6081_amd", "hbm_probe")
+
+
+def hbm_ceiling(n):
+    """The rates this device sustains for the step's memory traffic with no
+    arithmetic, and for plain streams (paper_1202_6081_amd/hbm_probe, run in a
+    process of its own before this one allocates anything): the ceiling the
+    step's roofline fraction is read against.  None where the probe's launch
+    shape does not cover n or it is not built."""
+    if n % 256 != 0 or n > 1024 or not os.path.exists(PROBE):
+        return None
+    res = subprocess.run([PROBE, str(n)], capture_output=True, text=True, timeout=300)
+    if res.returncode != 0:
+        raise RuntimeError("hbm_probe failed: " + res.stderr[-500:])
+    return json.loads(res.stdout.strip().splitlines()[-1])
 
 
 def measured_traffic(n_nodes):
@@ -184,6 +202,7 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-ceiling", action="store_true", help="skip the HBM rate probe")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the per-variant step timings (both lattices, four storage types)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -193,6 +212,8 @@ def main():
         print("bench.py measures one GPU: the build targets single-GPU runs only "
               "(multi-GPU z-slab decomposition is a design note, not built).", file=sys.stderr)
         sys.exit(2)
+
+    ceiling = None if (args.no_ceiling or args.copy_calibration) else hbm_ceiling(args.n)
 
     import torch
     import lbm_inputs as inp
@@ -266,6 +287,13 @@ def main():
                      "algorithmic_bytes_per_node": BYTES_PER_NODE, "kernel": "k_step<27,StF32,false>",
                      "kernel_ms_avg": round(kernel_ms, 4)},
         "mass_total_fp64": tot[0],
+        "hbm_ceiling": None if ceiling is None else {
+            "step_traffic_GBs": ceiling["step_traffic_pull_GBs"],
+            "step_traffic_own_node_GBs": ceiling["step_traffic_own_node_GBs"],
+            "read_GBs": ceiling["read_GBs"], "write_GBs": ceiling["write_GBs"], "copy_GBs": ceiling["copy_GBs"],
+            "kernel_over_ceiling": round(achieved / ceiling["step_traffic_pull_GBs"], 4),
+            "probe": "paper_1202_6081_amd/hbm_probe: 27 pull loads, 3 force loads, 27 stores per node, "
+                     "no arithmetic, same layout and launch shape"},
     }
     del a, b, bufs, last
     torch.cuda.empty_cache()

@@ -31,6 +31,7 @@ def test_bench_small_lattice_json_line():
     assert roof["bound"] == "hbm" and roof["peak"] == 8000.0 and roof["unit"] == "GB/s"
     assert abs(roof["frac"] - roof["achieved"] / roof["peak"]) < 1e-3
     assert roof["traffic"] is None              # counters are recorded for the 512^3 workload only
+    assert r["hbm_ceiling"] is None             # the rate probe covers lattices of a multiple of 256 only
     assert len(r["variants"]) == 8 and all(v["ms"] > 0 and v["inplace"]["ms"] > 0 for v in r["variants"])
     assert [v["lattice"] for v in r["adjoint_variants"]] == ["D3Q27", "D3Q15"]
     adj = r["adjoint"]
