@@ -292,8 +292,10 @@ def main():
             "step_traffic_own_node_GBs": ceiling["step_traffic_own_node_GBs"],
             "read_GBs": ceiling["read_GBs"], "write_GBs": ceiling["write_GBs"], "copy_GBs": ceiling["copy_GBs"],
             "kernel_over_ceiling": round(achieved / ceiling["step_traffic_pull_GBs"], 4),
-            "probe": "paper_1202_6081_amd/hbm_probe: 27 pull loads, 3 force loads, 27 stores per node, "
-                     "no arithmetic, same layout and launch shape"},
+            "adjoint_traffic_GBs": ceiling.get("adjoint_traffic_GBs"),
+            "probe": "paper_1202_6081_amd/hbm_probe: the step's loads and stores (27 pull loads, 3 force "
+                     "loads, 27 stores per node) and the adjoint's (384 B per node), no arithmetic, same "
+                     "layouts, one node per thread"},
     }
     del a, b, bufs, last
     torch.cuda.empty_cache()
@@ -307,6 +309,10 @@ def main():
     torch.cuda.empty_cache()
     result["variants"] = None if args.no_variants else variant_sweep(n)
     result["adjoint_variants"] = None if args.no_variants else adjoint_sweep(n)
+    hc = result["hbm_ceiling"]
+    if hc is not None and hc["adjoint_traffic_GBs"] and result["adjoint_variants"]:
+        adj27 = next(v for v in result["adjoint_variants"] if v["lattice"] == "D3Q27")
+        hc["adjoint_over_ceiling"] = round(adj27["GBs"] / hc["adjoint_traffic_GBs"], 4)
     # the same workload stepped in place (one population buffer)
     result["inplace"] = None if args.no_variants else next(
         v["inplace"] for v in result["variants"] if v["lattice"] == "D3Q27" and v["storage"] == "f32")

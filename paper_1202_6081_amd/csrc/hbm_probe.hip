@@ -1,8 +1,11 @@
-// HBM rate probes for the step's roofline: the rates this device sustains for
-// plain streams and for streams with exactly the step's memory traffic (27
-// population loads in the blocked row layout, 3 force loads, 27 nontemporal
-// population stores per node), with no arithmetic of the method.  A standalone
-// program; prints one JSON line.
+// HBM rate probes for the roofline: the rates this device sustains for plain
+// streams, for streams with exactly the step's memory traffic (27 population
+// loads in the blocked row layout, 3 force loads, 27 nontemporal population
+// stores per node), and for the adjoint step's (the same pull, 27 adjoint
+// loads gathered from the downstream neighbours and 27 adjoint stores in
+// structure-of-arrays layout, the force, and a read-modify-write of the FP64
+// force gradient), with no arithmetic of the method.  A standalone program;
+// prints one JSON line.
 //
 //   hbm_probe [n]     n^3 nodes for the stencil probes (n a multiple of 256; default 512)
 #include <hip/hip_runtime.h>
@@ -91,6 +94,45 @@ __global__ __launch_bounds__(kBlock) void k_stencil(const float* fin, const floa
   for (int b = 0; b < kQ; ++b) __builtin_nontemporal_store(v[b] + s, &fout[slot(row, nx, b, x)]);
 }
 
+// The adjoint step's traffic: fpost pulled as in the step; lam_next[a] read
+// at x + e_a (structure of arrays [27][N]); lam[a] and the three FP64
+// gradient components written at x, the gradient read first.
+__global__ __launch_bounds__(kBlock) void k_adjoint_traffic(const float* fpost, const float* lam_next, float* lam,
+                                                           const float* force, double* dLdF, uint32_t nx, uint32_t ny,
+                                                           uint32_t nz) {
+  uint32_t L = blockIdx.x;
+  const uint32_t per = gridDim.x >> 3;
+  if (L < (per << 3)) L = (L & 7u) * per + (L >> 3);
+  const uint32_t nseg = nx / kBlock;
+  const uint32_t row = L / nseg;
+  const uint32_t x = (L - row * nseg) * kBlock + threadIdx.x;
+  const uint32_t y = row % ny, z = row / ny;
+  const uint64_t N = uint64_t(nx) * ny * nz;
+  const uint64_t node = uint64_t(row) * nx + x;
+  float f[kQ], g[kQ];
+  int a = 0;
+#pragma unroll
+  for (int ez = -1; ez <= 1; ++ez)
+#pragma unroll
+    for (int ey = -1; ey <= 1; ++ey)
+#pragma unroll
+      for (int ex = -1; ex <= 1; ++ex, ++a) {
+        const uint32_t up = wrap(int(z) - ez, nz) * ny + wrap(int(y) - ey, ny);
+        f[a] = fpost[slot(up, nx, a, wrap(int(x) - ex, nx))];
+        const uint32_t dn = wrap(int(z) + ez, nz) * ny + wrap(int(y) + ey, ny);
+        g[a] = lam_next[uint64_t(a) * N + uint64_t(dn) * nx + wrap(int(x) + ex, nx)];
+      }
+  const float s = force[node] + force[N + node] + force[2 * N + node];
+  float t = 0.f;
+#pragma unroll
+  for (int b = 0; b < kQ; ++b) t += f[b];
+#pragma unroll
+  for (int b = 0; b < kQ; ++b) __builtin_nontemporal_store(g[b] + t + s, &lam[uint64_t(b) * N + node]);
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    __builtin_nontemporal_store(dLdF[uint64_t(c) * N + node] + double(t), &dLdF[uint64_t(c) * N + node]);
+}
+
 template <class Launch>
 double time_ms(hipEvent_t e0, hipEvent_t e1, int reps, Launch launch) {
   for (int i = 0; i < 3; ++i) launch();
@@ -146,17 +188,45 @@ int main(int argc, char** argv) {
   const double ms_own = time_ms(e0, e1, 20, [&] {
     hipLaunchKernelGGL(k_stencil<false>, grid, block, 0, 0, fin, force, fout, nx, ny, nz);
   });
+  PROBE_CHECK(hipFree(fout));
+  fout = nullptr;
+
+  // the adjoint step's traffic: 384 bytes per node, where its buffers fit
+  float *lam_next = nullptr, *lam = nullptr;
+  double* dLdF = nullptr;
+  const size_t grad_bytes = size_t(3) * N * sizeof(double);
+  size_t free_b = 0, total_b = 0;
+  PROBE_CHECK(hipMemGetInfo(&free_b, &total_b));
+  char adj_json[128];
+  std::snprintf(adj_json, sizeof(adj_json), "\"adjoint_traffic_ms\": null, \"adjoint_traffic_GBs\": null");
+  if (2 * pop_bytes + grad_bytes + (size_t(1) << 30) < free_b) {
+    PROBE_CHECK(hipMalloc(&lam_next, pop_bytes));
+    PROBE_CHECK(hipMalloc(&lam, pop_bytes));
+    PROBE_CHECK(hipMalloc(&dLdF, grad_bytes));
+    PROBE_CHECK(hipMemset(lam_next, 0, pop_bytes));
+    PROBE_CHECK(hipMemset(lam, 0, pop_bytes));
+    PROBE_CHECK(hipMemset(dLdF, 0, grad_bytes));
+    const double ms_adj = time_ms(e0, e1, 20, [&] {
+      hipLaunchKernelGGL(k_adjoint_traffic, grid, block, 0, 0, fin, lam_next, lam, force, dLdF, nx, ny, nz);
+    });
+    const double adj_bytes = double(3 * kQ + 3) * sizeof(float) + 6.0 * sizeof(double);
+    std::snprintf(adj_json, sizeof(adj_json), "\"adjoint_traffic_ms\": %.4f, \"adjoint_traffic_GBs\": %.1f", ms_adj,
+                  adj_bytes * double(N) / (ms_adj * 1e-3) / 1e9);
+    PROBE_CHECK(hipFree(lam_next));
+    PROBE_CHECK(hipFree(lam));
+    PROBE_CHECK(hipFree(dLdF));
+  }
+
   const double node_bytes = double(2 * kQ + 3) * sizeof(float);
   auto gbs = [](double bytes, double ms) { return bytes / (ms * 1e-3) / 1e9; };
   std::printf(
       "{\"nodes\": %llu, \"read_GBs\": %.1f, \"write_GBs\": %.1f, \"copy_GBs\": %.1f, "
       "\"step_traffic_pull_ms\": %.4f, \"step_traffic_pull_GBs\": %.1f, "
-      "\"step_traffic_own_node_ms\": %.4f, \"step_traffic_own_node_GBs\": %.1f}\n",
+      "\"step_traffic_own_node_ms\": %.4f, \"step_traffic_own_node_GBs\": %.1f, %s}\n",
       static_cast<unsigned long long>(N), gbs(double(stream_bytes), ms_read), gbs(double(stream_bytes), ms_write),
       gbs(2.0 * double(stream_bytes), ms_copy), ms_pull, gbs(node_bytes * double(N), ms_pull), ms_own,
-      gbs(node_bytes * double(N), ms_own));
+      gbs(node_bytes * double(N), ms_own), adj_json);
   PROBE_CHECK(hipFree(fin));
-  PROBE_CHECK(hipFree(fout));
   PROBE_CHECK(hipFree(force));
   PROBE_CHECK(hipFree(sink));
   return 0;
