@@ -13,7 +13,10 @@ x(n) is recovered from stored snapshots by recomputation.  Two schedules:
 its states stored; ``snapshots=s`` keeps at most s states and places them by
 the binomial (optimal offline) rule: reversing n steps from a stored state with
 s free slots costs min over m of [m + cost(n - m, s - 1) + cost(m, s)]
-recomputed steps, cost(1, s) = 0, cost(n, 0) = n(n - 1)/2.  x(0) itself is not
+recomputed steps, cost(1, s) = 0, cost(n, 0) = n(n - 1)/2, which is Griewank and
+Walther's closed form r n - C(s + 1 + r, s + 2) with r the least integer such
+that C(s + 1 + r, s + 1) >= n (binomial checkpointing, "revolve", with s + 1
+checkpoints counting the stored state).  x(0) itself is not
 kept: the backward sweep rebuilds it from (rho0, u0) with the initial-state
 kernels (bit-identical) when it reaches the first interval.
 """
@@ -30,14 +33,32 @@ from . import cmlbm
 # binomial checkpoint schedule
 # ----------------------------------------------------------------------------
 @functools.lru_cache(maxsize=None)
+def _min_recompute(n, s):
+    """Fewest steps recomputed to reverse n steps from a stored state with s
+    free slots (the closed form above)."""
+    if n <= 1:
+        return 0
+    if s == 0:
+        return n * (n - 1) // 2
+    r = 1
+    while math.comb(s + 1 + r, s + 1) < n:
+        r += 1
+    return r * n - math.comb(s + 1 + r, s + 2)
+
+
+@functools.lru_cache(maxsize=None)
 def _cost(n, s):
+    """(fewest recomputed steps, first split m): advance m steps, store that
+    state, reverse the n - m steps after it with s - 1 slots, then the first m
+    with s.  The costs of the two parts come from the closed form, so a split
+    takes O(n) work instead of a table over every (n, s) below it."""
     if n <= 1:
         return 0, 0
     if s == 0:
         return n * (n - 1) // 2, 0
     best, arg = None, 1
     for m in range(1, n):
-        c = m + _cost(n - m, s - 1)[0] + _cost(m, s)[0]
+        c = m + _min_recompute(n - m, s - 1) + _min_recompute(m, s)
         if best is None or c < best:
             best, arg = c, m
     return best, arg

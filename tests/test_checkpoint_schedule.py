@@ -102,3 +102,37 @@ def test_binomial_schedule_rebuilding_x0(nsteps, s):
 def test_uniform_checkpoints_rebuilding_x0(nsteps, every):
     sim, sw, pool, stored = _run(nsteps, every=every, keep_x0=False)
     assert sw.recomputed == sim.steps == nsteps - (-(-nsteps // every))
+
+
+def test_binomial_cost_against_the_recursion_and_closed_form():
+    # The schedule's costs and splits use Griewank and Walther's closed form for
+    # the optimal recompute count; check it against the defining recursion,
+    # evaluated here by brute force over every split.
+    import functools
+
+    @functools.lru_cache(maxsize=None)
+    def rec(n, s):
+        if n <= 1:
+            return 0
+        if s == 0:
+            return n * (n - 1) // 2
+        return min(m + rec(n - m, s - 1) + rec(m, s) for m in range(1, n))
+
+    for s in range(0, 10):
+        for n in range(1, 160):
+            assert ag._min_recompute(n, s) == rec(n, s) == ag._cost(n, s)[0], (n, s)
+    # two values worked by hand from the closed form: 10 steps with 2
+    # checkpoints -> 3*10 - C(5, 3) = 20 (r = 3); 100 steps with 6 -> 4*100 -
+    # C(10, 7) = 280 (r = 4)
+    assert ag._min_recompute(10, 1) == 20 and ag._min_recompute(100, 5) == 280
+
+
+def test_binomial_schedule_long_run_is_cheap():
+    import time
+    t0 = time.perf_counter()
+    total = ag.recompute_steps(20000, 12)
+    assert time.perf_counter() - t0 < 20.0
+    # the forward pass places the first chain of snapshots for free: at most
+    # n steps below the bound for a reversal that starts from x(0) alone
+    bound = ag._min_recompute(20000, 12)
+    assert bound - 20000 <= total <= bound
