@@ -230,7 +230,8 @@ def keep_positions(nsteps, every, snapshots):
 class _Run(torch.autograd.Function):
     @staticmethod
     def forward(ctx, F, omega, sim, rho0, u0, nsteps, every, snapshots):
-        sim.set_rates([float(w) for w in omega.detach().cpu()])
+        rates = [float(w) for w in omega.detach().cpu()]
+        sim.set_rates(rates)
         Fr = F.detach().to(device=sim.device, dtype=sim.real).contiguous()
         sim.set_force(Fr)
         pool = _Pool(sim)
@@ -251,12 +252,19 @@ class _Run(torch.autograd.Function):
         ctx.u0, ctx.nsteps, ctx.every, ctx.snapshots = u0r, nsteps, every, snapshots
         ctx.F_dtype, ctx.w_dtype, ctx.F_shape = F.dtype, omega.dtype, F.shape
         ctx.F_device, ctx.w_device = F.device, omega.device
-        ctx.Fr = Fr
+        ctx.Fr, ctx.rates = Fr, rates
+        ctx.consumed = False
         return pre
 
     @staticmethod
     def backward(ctx, g):
+        if ctx.consumed:
+            raise RuntimeError("a checkpointed run can be differentiated once: its backward sweep consumes "
+                               "the stored states")
+        ctx.consumed = True
         sim, pool, stored = ctx.sim, ctx.pool, ctx.stored
+        # the handle may have run something else since the forward pass
+        sim.set_rates(ctx.rates)
         sim.set_force(ctx.Fr)
         lam = g.detach().to(dtype=sim.real).contiguous().clone()
         lam_tmp = sim.real_populations()
@@ -305,8 +313,10 @@ def run(sim, rho0, u0, F, omega, nsteps, every=None, snapshots=None):
 class _KineticEnergy(torch.autograd.Function):
     @staticmethod
     def forward(ctx, f_pre, F, sim, n_fluid):
+        sim.set_force(F.detach())
         total = sim.kinetic_energy_sum(f_pre.detach().contiguous())
         ctx.sim, ctx.n_fluid, ctx.F_dtype, ctx.F_shape = sim, n_fluid, F.dtype, F.shape
+        ctx.F, ctx.F_device = F.detach(), F.device
         ctx.save_for_backward(f_pre)
         return torch.tensor(total / n_fluid, dtype=torch.float64, device=f_pre.device)
 
@@ -314,18 +324,21 @@ class _KineticEnergy(torch.autograd.Function):
     def backward(ctx, g):
         (f_pre,) = ctx.saved_tensors
         sim = ctx.sim
+        sim.set_force(ctx.F)                 # the handle may have run something else since
         lam = torch.empty_like(f_pre)
         dLdF = torch.zeros(ctx.F_shape, dtype=torch.float64, device=f_pre.device)
         sim.kinetic_energy_seed(f_pre.detach().contiguous(), float(g) / ctx.n_fluid, lam, dLdF)
-        return lam, dLdF.to(ctx.F_dtype), None, None
+        return lam, dLdF.to(device=ctx.F_device, dtype=ctx.F_dtype), None, None
 
 
 def kinetic_energy(sim, f_pre, F, n_fluid=None):
     """Mean kinetic energy (1/N) sum |rho u|^2 / (2 rho) over the N fluid nodes
     of a pre-collision state, with rho u including F/2; differentiable in f_pre
-    and F.  The sim's force must be F (as set by `run`)."""
+    and F.  Sets the sim's force to F (the force of the run that made f_pre).
+    N defaults to the fluid nodes of the sim's mask (all nodes without one)."""
     if n_fluid is None:
-        n_fluid = sim.nx * sim.ny * sim.nz
+        mask = sim._keep.get("mask")
+        n_fluid = sim.nx * sim.ny * sim.nz if mask is None else int((mask == 0).sum())
     return _KineticEnergy.apply(f_pre, F, sim, int(n_fluid))
 
 

@@ -227,3 +227,39 @@ def test_config_64cubed_200_steps():
     fd = (Lp - Lm) / (2 * hw)
     print(f"config4 FD shear: fd {fd:.8e} adjoint {gw64[:5].sum():.8e}", flush=True)
     assert abs(fd - gw64[:5].sum()) <= 1e-5 * abs(fd)
+
+
+def test_backward_after_other_work_and_only_once():
+    # Gradients do not depend on what the handle ran between the forward pass
+    # and backward (rates and force are restored), and a second backward
+    # through the consumed checkpoints is refused.
+    from paper_1202_6081_amd import autograd as ag
+    print("case backward-after-other-work", flush=True)
+    shape = (4, 5, 66)
+    rng = np.random.default_rng(7)
+    om = np.array(rng.uniform(0.8, 1.9, 23))
+    F = inp.gaussian_force(shape, 1e-4, 3)
+    rho0 = torch.from_numpy(1 + 0.01 * rng.standard_normal(shape)).cuda()
+    u0 = torch.from_numpy(0.05 * rng.uniform(-1, 1, (3,) + shape)).cuda()
+
+    def grads(interfere):
+        sim = gpu_setup(27, shape, F64, list(om), None, None, False)
+        Ft = torch.from_numpy(F).cuda().requires_grad_(True)
+        wt = torch.from_numpy(om.copy()).requires_grad_(True)
+        out = ag.run(sim, rho0, u0, Ft, wt, 5, snapshots=2)
+        loss = ag.kinetic_energy(sim, out, Ft)
+        if interfere:
+            sim.set_rates([1.0] * 23)
+            sim.set_force([1e-3, 0.0, 0.0])
+            a, _ = sim.init_equilibrium(rho0, u0)
+            sim.run(a, sim.populations(), 3)
+        loss.backward(retain_graph=interfere)
+        got = Ft.grad.cpu().numpy().copy(), wt.grad.numpy().copy()
+        if interfere:
+            with pytest.raises(RuntimeError):
+                loss.backward()
+        return got
+
+    gF0, gw0 = grads(False)
+    gF1, gw1 = grads(True)
+    assert np.array_equal(gF0, gF1) and np.array_equal(gw0, gw1)
