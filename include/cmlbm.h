@@ -124,7 +124,8 @@ cmlbm_status cmlbm_set_attractor_per_mass(cmlbm_sim *sim, int per_mass);
 cmlbm_status cmlbm_set_force_uniform(cmlbm_sim *sim, double fx, double fy, double fz);
 
 /* Spatially varying body force, device array [3][nz][ny][nx] of "real",
- * borrowed until replaced.  NULL returns to the uniform force. */
+ * borrowed until replaced.  NULL removes the field and sets the uniform force
+ * to zero. */
 cmlbm_status cmlbm_set_force_field(cmlbm_sim *sim, const void *F_dev);
 
 /* Multiplier applied to the force (uniform or field) from the next call on,
