@@ -263,3 +263,60 @@ def test_backward_after_other_work_and_only_once():
     gF0, gw0 = grads(False)
     gF1, gw1 = grads(True)
     assert np.array_equal(gF0, gF1) and np.array_equal(gw0, gw1)
+
+
+@pytest.mark.parametrize("q", [27, 15])
+def test_full_size_adjoint_sampled_nodes(q):
+    # One adjoint step of the benchmark configuration (512^3 FP32, Kolmogorov
+    # force field, shear rate 1.9) in the launch configuration the benchmark
+    # times.  At 2048 sampled nodes (box corners included), lam(x) and dL/dF(x)
+    # against the transposed Jacobian of the oracle's collision, taken by the
+    # complex step at the pre-collision state the GPU pulled, applied to the
+    # reverse-streamed adjoint lam_next(x + e_a)_a.
+    from oracle import collision
+    print(f"case adjoint full512 q{q}", flush=True)
+    n = 512
+    lat = LATTICES[q]
+    om = shear_rates(q, 1.9)
+    sim = gpu_setup(q, (n, n, n), F32, om)
+    F = torch.from_numpy(inp.kolmogorov_force(n)).to("cuda", torch.float32)
+    sim.set_force(F)
+    g = torch.Generator(device="cuda").manual_seed(2)
+    rho0 = torch.ones((n, n, n), device="cuda", dtype=torch.float32)
+    u0 = 0.03 * (torch.rand((3, n, n, n), device="cuda", generator=g) - 0.5)
+    x, pre = sim.init_equilibrium(rho0, u0)
+    del rho0, u0
+    lam_next = torch.randn((q, n, n, n), device="cuda", generator=g)
+    lam = sim.real_populations()
+    dLdF = torch.zeros((3, n, n, n), dtype=torch.float64, device="cuda")
+    dLdw = torch.zeros(q - 4, dtype=torch.float64, device="cuda")
+    sim.adjoint_step(x, lam_next, lam, dLdF, dLdw)
+    pre = sim.gather(x, out=pre)
+    rng = np.random.default_rng(4)
+    idx = rng.integers(0, n**3, 2048)
+    idx[:4] = [0, n - 1, n * n - 1, n**3 - 1]
+    z, y, xx = idx // (n * n), (idx // n) % n, idx % n
+    idx_t = torch.from_numpy(idx).to("cuda")
+    f_in = pre.reshape(q, -1)[:, idx_t].double().cpu().numpy().T            # (nodes, q)
+    Fs = F.reshape(3, -1)[:, idx_t].double().cpu().numpy().T                 # (nodes, 3)
+    got = lam.reshape(q, -1)[:, idx_t].double().cpu().numpy().T
+    got_F = dLdF.reshape(3, -1)[:, idx_t].cpu().numpy().T
+    ln = lam_next.reshape(q, -1)
+    post = np.empty((len(idx), q))
+    for a in range(q):
+        ex, ey, ez = (int(c) for c in lat.E[a])
+        nb = ((z + ez) % n) * n * n + ((y + ey) % n) * n + (xx + ex) % n
+        post[:, a] = ln[a, torch.from_numpy(nb).to("cuda")].double().cpu().numpy()
+    del x, pre, lam, lam_next, dLdF
+    torch.cuda.empty_cache()
+    # lam_b = sum_a post_a dC_a/dfbar_b: every b at once, one complex-step column each
+    fc = f_in[:, None, :] + 1j * H * np.eye(q)[None, :, :]
+    Cc = collision.collide(lat, fc, np.repeat(Fs[:, None, :], q, axis=1).astype(complex), np.array(om, dtype=complex))
+    want = np.einsum("na,nba->nb", post, Cc.imag / H)
+    Fc = Fs[:, None, :] + 1j * H * np.eye(3)[None, :, :]
+    CF = collision.collide(lat, np.repeat(f_in[:, None, :], 3, axis=1).astype(complex), Fc, np.array(om, dtype=complex))
+    want_F = np.einsum("na,nca->nc", post, CF.imag / H)
+    err = np.abs(got - want).max() / np.abs(want).max()
+    err_F = np.abs(got_F - want_F).max() / np.abs(want_F).max()
+    print(f"adjoint full512 q{q}: lam rel err {err:.2e}, dL/dF rel err {err_F:.2e}", flush=True)
+    assert err < 1e-5 and err_F < 1e-5
