@@ -402,7 +402,7 @@ def benchmark_adjoint_ratio(sim, nsteps, forward_ms_per_step, budget_gib=None):
     fwd_ms, bwd_ms = times[1]
     dLdw_shear = float(st["dLdomega_fp64"][:5].sum())
     recomputed, adj_steps = st["recomputed"], st["adjoint_steps"]
-    loss_value = float(loss)
+    loss_value = float(loss.detach())
     del out, loss, st
     _last_stats.clear()
     # average duration of the adjoint step kernel alone (events on the launch stream)

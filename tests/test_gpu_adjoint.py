@@ -164,7 +164,7 @@ def test_whole_run_gradient_fp64(schedule, masked, per_mass, q):
     loss = ag.kinetic_energy(sim, out, Ft, n_fluid=int(fluid.sum()))
     loss.backward()
     ref_loss = _oracle_loss(rho0, u0, F, om, nsteps, solid, per_mass, q)
-    assert abs(float(loss) - ref_loss) <= 1e-12 * abs(ref_loss)
+    assert abs(float(loss.detach()) - ref_loss) <= 1e-12 * abs(ref_loss)
     gF = Ft.grad.cpu().numpy()
     gw = wt.grad.numpy()
     for k in range(3):
@@ -188,10 +188,10 @@ def _config4(prec, F=None, om_shear=1.6, nsteps=200, every=20, n=64, want_grad=T
     out = ag.run(sim, rho0, u0, Ft, wt, nsteps, every=every)
     loss = ag.kinetic_energy(sim, out, Ft)
     if not want_grad:
-        return float(loss)
+        return float(loss.detach())
     loss.backward()
     # F.grad holds the run's adjoint plus the direct dKE/dF = u/(2N) term
-    return float(loss), Ft.grad.cpu().numpy(), wt.grad.numpy()
+    return float(loss.detach()), Ft.grad.cpu().numpy(), wt.grad.numpy()
 
 
 def test_config_64cubed_200_steps():
