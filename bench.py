@@ -52,10 +52,14 @@ def hbm_ceiling(n):
     shape does not cover n or it is not built."""
     if n % 256 != 0 or n > 1024 or not os.path.exists(PROBE):
         return None
-    res = subprocess.run([PROBE, str(n)], capture_output=True, text=True, timeout=300)
-    if res.returncode != 0:
-        raise RuntimeError("hbm_probe failed: " + res.stderr[-500:])
-    return json.loads(res.stdout.strip().splitlines()[-1])
+    try:
+        res = subprocess.run([PROBE, str(n)], capture_output=True, text=True, timeout=300)
+        if res.returncode == 0:
+            return json.loads(res.stdout.strip().splitlines()[-1])
+        print("hbm_probe failed (no ceiling reported): " + res.stderr[-500:], file=sys.stderr)
+    except (OSError, ValueError, IndexError, subprocess.TimeoutExpired) as e:
+        print(f"hbm_probe failed (no ceiling reported): {e}", file=sys.stderr)
+    return None
 
 
 def measured_traffic(n_nodes):
