@@ -54,3 +54,14 @@ def test_null_handle_and_out():
     assert lib.cmlbm_step(None, None, None, None) == -1
     assert lib.cmlbm_set_rates(None, None, 23) == -1
     lib.cmlbm_destroy(None)
+
+
+def test_rate_probe_refuses_sizes_before_the_device():
+    # The HBM rate probe checks its lattice size before any HIP call.
+    import subprocess
+    exe = os.path.join(ROOT, "paper_1202_6081_amd", "hbm_probe")
+    if not os.path.exists(exe):
+        pytest.skip("hbm_probe is built by __graft_entry__.build()")
+    for bad in ("100", "128", "1280", "0"):
+        res = subprocess.run([exe, bad], capture_output=True, text=True, timeout=60)
+        assert res.returncode == 2 and "multiple of 256" in res.stderr, (bad, res.returncode, res.stderr)
