@@ -5,7 +5,8 @@
  *     (Eqs. densitycalculation, velocitycalculation: the collision conserves
  *     mass and momentum, the source adds F at every node);
  *   - the in-place run ends in the same FP64 totals as the two-buffer run;
- *   - argument errors come back as CMLBM_EINVAL with a message.
+ *   - argument errors (aliasing, counts, rates, misaligned pointers) come back
+ *     as CMLBM_EINVAL with a message, before any launch.
  * Prints "abi_from_c ok" and exits 0 on success. */
 #include <hip/hip_runtime_api.h>
 #include <math.h>
@@ -81,6 +82,9 @@ int main(void) {
   CHECK(cmlbm_step(s, fa, fa, NULL) == CMLBM_EINVAL, "aliased step accepted");
   CHECK(cmlbm_last_error(s)[0] != '\0', "no message for the aliased step");
   CHECK(cmlbm_run_inplace(s, fin, 3, NULL) == CMLBM_EINVAL, "odd in-place run accepted");
+  /* an FP64 buffer at a 4-byte offset: refused before any launch */
+  CHECK(cmlbm_step(s, fa, (char *)fb + 4, NULL) == CMLBM_EINVAL, "misaligned buffer accepted");
+  CHECK(cmlbm_macroscopic(s, fa, (char *)rho + 4, u, NULL) == CMLBM_EINVAL, "misaligned field accepted");
   CHECK(cmlbm_set_rates(s, omega, 22) == CMLBM_EINVAL, "wrong rate count accepted");
   omega[0] = 2.0;
   CHECK(cmlbm_set_rates(s, omega, 23) == CMLBM_EINVAL, "rate 2 accepted");
