@@ -7,12 +7,17 @@
 // force gradient), with no arithmetic of the method.  A standalone program;
 // prints one JSON line.
 //
-//   hbm_probe [n]     n^3 nodes for the stencil probes (n a multiple of 256; default 512)
+//   hbm_probe [n]        n^3 nodes for the stencil probes (n a multiple of 256; default 512)
+//   hbm_probe placement  the step's traffic at 512^3 on buffers placed three ways (one
+//                        JSON line each): the process's first allocations, buffers carved
+//                        from one 150 GiB allocation, and new allocations made after all of
+//                        that memory was released
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 
 namespace {
 
@@ -146,9 +151,59 @@ double time_ms(hipEvent_t e0, hipEvent_t e1, int reps, Launch launch) {
   return double(ms) / reps;
 }
 
+// The step's traffic at 512^3 (both directions between the two buffers) on
+// buffers placed three ways.  The same kernel, the same bytes: only where the
+// pages lie differs.
+int placement_study() {
+  const uint32_t n = 512;
+  const uint64_t N = uint64_t(n) * n * n;
+  const size_t pop = size_t(kQ) * N * sizeof(float), fb = size_t(3) * N * sizeof(float);
+  hipEvent_t e0, e1;
+  PROBE_CHECK(hipEventCreate(&e0));
+  PROBE_CHECK(hipEventCreate(&e1));
+  const dim3 grid(unsigned(N / kBlock)), block(kBlock);
+  auto run = [&](const char* name, float* fa, float* fb_, float* force) {
+    PROBE_CHECK(hipMemset(fa, 0, pop));
+    PROBE_CHECK(hipMemset(fb_, 0, pop));
+    PROBE_CHECK(hipMemset(force, 0, fb));
+    const double ab = time_ms(e0, e1, 20, [&] {
+      hipLaunchKernelGGL(k_stencil<true>, grid, block, 0, 0, fa, force, fb_, n, n, n);
+    });
+    const double ba = time_ms(e0, e1, 20, [&] {
+      hipLaunchKernelGGL(k_stencil<true>, grid, block, 0, 0, fb_, force, fa, n, n, n);
+    });
+    std::printf("{\"placement\": \"%s\", \"ms_a_to_b\": %.4f, \"ms_b_to_a\": %.4f, \"GBs\": %.1f}\n", name, ab,
+                ba, 228.0 * double(N) / (0.5 * (ab + ba) * 1e-3) / 1e9);
+    std::fflush(stdout);
+  };
+  float *a = nullptr, *b = nullptr, *f = nullptr;
+  PROBE_CHECK(hipMalloc(&a, pop));
+  PROBE_CHECK(hipMalloc(&b, pop));
+  PROBE_CHECK(hipMalloc(&f, fb));
+  run("first allocations", a, b, f);
+  const size_t big = size_t(150) << 30;   // room for the three buffers many times over
+  char* pool = nullptr;
+  PROBE_CHECK(hipMalloc(&pool, big));
+  run("carved from one 150 GiB allocation", reinterpret_cast<float*>(pool), reinterpret_cast<float*>(pool + pop),
+      reinterpret_cast<float*>(pool + 2 * pop));
+  PROBE_CHECK(hipFree(a));
+  PROBE_CHECK(hipFree(b));
+  PROBE_CHECK(hipFree(f));
+  PROBE_CHECK(hipFree(pool));
+  PROBE_CHECK(hipMalloc(&a, pop));
+  PROBE_CHECK(hipMalloc(&b, pop));
+  PROBE_CHECK(hipMalloc(&f, fb));
+  run("allocated after releasing the above", a, b, f);
+  PROBE_CHECK(hipFree(a));
+  PROBE_CHECK(hipFree(b));
+  PROBE_CHECK(hipFree(f));
+  return 0;
+}
+
 }  // namespace
 
 int main(int argc, char** argv) {
+  if (argc > 1 && std::strcmp(argv[1], "placement") == 0) return placement_study();
   const long n = argc > 1 ? std::atol(argv[1]) : 512;
   if (n < kBlock || n % kBlock != 0 || n > 1024) {
     std::fprintf(stderr, "hbm_probe: n must be a multiple of %d in [%d, 1024]\n", kBlock, kBlock);
