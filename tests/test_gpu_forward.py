@@ -274,15 +274,16 @@ def test_misaligned_buffers_rejected():
     assert int(torch.count_nonzero(short)) == 0
 
 
-@pytest.mark.parametrize("q", [27, 15])
-def test_full_size_sampled_nodes(q):
+@pytest.mark.parametrize("q,prec", [(27, F32), (15, F32), (27, F16), (15, BF16)])
+def test_full_size_sampled_nodes(q, prec):
     # The benchmark configuration: 512^3 FP32 D3Q27 (and D3Q15) with the
-    # Kolmogorov force field F_x = 1e-6 sin(2 pi 4 y / 512), shear rate 1.9.
-    # One step from a perturbed state; the oracle collides 4096 sampled nodes
-    # from the pre-collision populations the GPU pulled.
-    print(f"case full512 q{q}", flush=True)
+    # Kolmogorov force field F_x = 1e-6 sin(2 pi 4 y / 512), shear rate 1.9,
+    # and the same lattice with 16-bit deviation storage.  One step from a
+    # perturbed state; the oracle collides 4096 sampled nodes from the
+    # pre-collision populations the GPU pulled (decoded, for 16-bit storage).
+    print(f"case full512 q{q} p{prec}", flush=True)
     n = 512
-    sim = gpu_setup(q, (n, n, n), F32, shear_rates(q, 1.9))
+    sim = gpu_setup(q, (n, n, n), prec, shear_rates(q, 1.9))
     F = torch.from_numpy(inp.kolmogorov_force(n)).to("cuda", torch.float32)
     sim.set_force(F)
     rho0 = torch.ones((n, n, n), device="cuda", dtype=torch.float32)
@@ -302,7 +303,12 @@ def test_full_size_sampled_nodes(q):
     f_gpu = post.reshape(q, -1)[:, idx_t].double().cpu().numpy().T
     Fs = F.reshape(3, -1)[:, idx_t].double().cpu().numpy().T
     want = collision.collide(LATTICES[q], f_in, Fs, shear_rates(q, 1.9))
-    assert np.abs(f_gpu - want).max() < 2e-6
+    if prec == F32:
+        assert np.abs(f_gpu - want).max() < 2e-6
+    else:   # the stored deviation f - w_a rounded to 16 bits: half an ulp of it, plus FP32 arithmetic
+        w = collision.equilibrium(LATTICES[q], np.array(1.0), np.zeros(3))
+        bound = 0.5 * _ulp16(want - w[None, :], prec) + 2e-6
+        assert (np.abs(f_gpu - want) <= bound).all(), np.abs(f_gpu - want).max()
 
 
 def test_duct_128_transient_closed_form():
