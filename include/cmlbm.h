@@ -94,8 +94,10 @@ typedef struct cmlbm_sim cmlbm_sim; /* opaque; host memory owned by the library 
 /* Create a handle for a nx * ny * nz lattice, periodic in all directions until
  * a mask is set.  q: 15 or 27 (Eq. velocityd3qq27, Appendix G).  All rates
  * start at 1, the force at zero, the force scale at 1.  Limits: 1 <= nx,
- * ny, nz <= 65535, nx * ny * nz < 2^31.  Errors: EINVAL (sizes, q, precision,
- * out == NULL), EDEVICE (no HIP device), ENOMEM. */
+ * ny, nz <= 65535, nx * ny * nz < 2^31, and ny * nz rows of nx rounded up to
+ * 64 (to 256 above 256) below 2^32 lanes, which only a lattice short in x with
+ * more than 2^26 rows reaches (make x the longest axis).  Errors: EINVAL
+ * (sizes, q, precision, out == NULL), EDEVICE (no HIP device), ENOMEM. */
 cmlbm_status cmlbm_create(int q, int nx, int ny, int nz, int precision, cmlbm_sim **out);
 
 /* Release the handle and its device scratch.  NULL is allowed. */

@@ -172,6 +172,19 @@ cmlbm_status cmlbm_create(int q, int nx, int ny, int nz, int precision, cmlbm_si
     g_create_error = "nx*ny*nz must be below 2^31";
     return CMLBM_EINVAL;
   }
+  {
+    cmlbm::Geom g{};
+    g.nx = nx;
+    g.ny = ny;
+    g.nz = nz;
+    g.nxy = uint32_t(nx) * uint32_t(ny);
+    g.N = N;
+    if (cmlbm::max_work_items(g) > UINT32_MAX) {
+      g_create_error = "too many rows for one launch: the launches give every row a multiple of 64 lanes, "
+                       "so a lattice this short in x exceeds 2^32 work-items; make x the longest axis";
+      return CMLBM_EINVAL;
+    }
+  }
   if (precision < CMLBM_F64 || precision > CMLBM_F32_BF16DEV) {
     g_create_error = "unknown precision";
     return CMLBM_EINVAL;

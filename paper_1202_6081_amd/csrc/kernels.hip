@@ -1545,5 +1545,10 @@ hipError_t launch_init_adjoint(int q, int prec, const Geom& g, const void* u0, c
                  : init_adj_impl<15, float>(g, u0, lam0, mask, f32, dLdF, partials, nblk, st);
 }
 
+uint64_t max_work_items(const Geom& g) {
+  const uint64_t step = uint64_t(step_grid(g, step_block(g)).x) * uint64_t(step_block(g));
+  const uint64_t adj = uint64_t(adjoint_blocks(g)) * uint64_t(adjoint_block(g));
+  return step > adj ? step : adj;
+}
 
 }  // namespace cmlbm

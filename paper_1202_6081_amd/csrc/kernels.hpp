@@ -113,4 +113,9 @@ constexpr int kReduceChunks = 256;
 // Blocks of one step launch (one block per CMLBM_STEP_BLOCK-wide row segment).
 uint64_t step_blocks(const Geom& g);
 
+// Work-items of the largest grid the lattice's launches use (the step and the
+// adjoint cover whole row segments rounded up to 64 lanes); a dispatch counts
+// its work-items in 32 bits.
+uint64_t max_work_items(const Geom& g);
+
 }  // namespace cmlbm

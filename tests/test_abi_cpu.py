@@ -37,7 +37,8 @@ def test_status_strings_and_version():
 
 
 @pytest.mark.parametrize("args", [(26, 8, 8, 8, 1), (27, 0, 8, 8, 1), (27, 8, 8, 8, 7), (15, 70000, 2, 2, 1),
-                                  (27, 2048, 2048, 1024, 1)])
+                                  (27, 2048, 2048, 1024, 1),
+                                  (27, 1, 8192, 8192, 1)])   # 2^26 rows of 64 lanes: 2^32 work-items
 def test_create_rejects_bad_arguments_before_the_device(args):
     from paper_1202_6081_amd import cmlbm
     lib = cmlbm.load_library()
@@ -65,3 +66,18 @@ def test_rate_probe_refuses_sizes_before_the_device():
     for bad in ("100", "128", "1280", "0"):
         res = subprocess.run([exe, bad], capture_output=True, text=True, timeout=60)
         assert res.returncode == 2 and "multiple of 256" in res.stderr, (bad, res.returncode, res.stderr)
+
+
+def test_create_row_lane_limit_boundary():
+    # 2^25 rows of one node (64 lanes each) stay within one launch; with no
+    # device here the call gets past the argument checks and fails on the device.
+    from paper_1202_6081_amd import cmlbm
+    lib = cmlbm.load_library()
+    h = ctypes.c_void_p()
+    code = lib.cmlbm_create(27, 1, 4096, 8192, 1, ctypes.byref(h))
+    if code == 0:
+        lib.cmlbm_destroy(h)
+    else:
+        assert code != -1, lib.cmlbm_last_error(None)
+    assert lib.cmlbm_create(27, 1, 8192, 8192, 1, ctypes.byref(h)) == -1
+    assert b"longest axis" in lib.cmlbm_last_error(None)
