@@ -17,8 +17,16 @@ collision  the per-node collision as its plain definition (central moments of
 lbm        whole-lattice step (push streaming, periodic, half-way bounce-back),
            initial condition, macroscopic fields, totals, kinetic energy
 
-Parity status: every function here is pinned by the ``-m "not gpu"`` tests
-(printed tables of the paper, the printed collision cascade in exact rational
-arithmetic, conservation, Galilean invariance, the equilibrium fixed point and
-closed-form channel/duct flows).  No function is "parity unpinned".
+Parity status (the ``-m "not gpu"`` tests):
+* the printed tables of the paper (basis matrices, kernel moments, source rows);
+* the printed collision cascade, equal to ``collision.collide`` exactly in
+  rational arithmetic once its misprints are corrected;
+* the D3Q15 source projections m^s of Appendix G, every row, against the K_b
+  projections of the continuous raw source moments (binomial theorem on the
+  central source moments of Eq. forcingaliased);
+* conservation, Galilean invariance, the equilibrium fixed point, and
+  closed-form channel and duct flows.
+Two choices that no printed value arbitrates are pinned by their own exact
+properties only: the density normalisation of the factorized attractors
+(``per_mass``), and the D3Q15 source beyond its printed projections.
 """
