@@ -136,6 +136,8 @@ class _Sweep:
 
     def binomial(self, l, r, xl, s):
         n = r - l
+        if n <= 0:
+            return
         if n == 1:
             self.adjoint(xl)
             return
@@ -156,6 +158,8 @@ class _Sweep:
 
     def segment(self, l, r, xl):
         """Replay [l, r) once, keeping every state, then reverse it."""
+        if r <= l:
+            return
         states = [xl]
         cur = xl
         for _ in range(l, r - 1):
@@ -191,7 +195,11 @@ def forward_sweep(sim, pool, x0, nsteps, keep, keep_x0=True):
 def backward_sweep(sw, stored, nsteps, every, snapshots, rebuild_x0=None):
     """Run the adjoint steps N-1 .. 0 with recomputation from `stored`.
     When x(0) is not stored, rebuild_x0() returns a pool buffer holding it,
-    called once, when the first interval is reached."""
+    called once, when the first interval is reached.  nsteps == 0 leaves
+    nothing to reverse."""
+    if nsteps <= 0:
+        return
+
     def start(l):
         if l in stored:
             return stored[l], False
@@ -302,7 +310,10 @@ def run(sim, rho0, u0, F, omega, nsteps, every=None, snapshots=None):
     (3, nz, ny, nx) or uniform force F (3,), and the rates omega (Q - 4,).
     Exactly one of `every` (uniform checkpoint interval) or `snapshots`
     (binomial schedule with that many stored states besides x(0)) must be
-    given."""
+    given.  nsteps = 0 returns fbar(0), whose gradient is that of the initial
+    state alone."""
+    if int(nsteps) != nsteps or nsteps < 0:
+        raise ValueError("nsteps must be an integer >= 0")
     if len(omega) != sim.q - 4:
         raise ValueError(f"expected {sim.q - 4} rates")
     if (every is None) == (snapshots is None):

@@ -136,3 +136,38 @@ def test_binomial_schedule_long_run_is_cheap():
     # n steps below the bound for a reversal that starts from x(0) alone
     bound = ag._min_recompute(20000, 12)
     assert bound - 20000 <= total <= bound
+
+
+@pytest.mark.parametrize("keep_x0", [True, False])
+@pytest.mark.parametrize("schedule", [{"every": 1}, {"every": 4}, {"snapshots": 0}, {"snapshots": 3}])
+@pytest.mark.parametrize("nsteps", [0, 1, 2])
+def test_short_runs_take_one_adjoint_step_per_step(nsteps, schedule, keep_x0):
+    # nsteps forward steps are reversed by exactly nsteps adjoint steps, in
+    # reverse order, each on its own forward state: none for an empty run (its
+    # gradient is the initial state's alone), and no buffer handed back twice.
+    sim, sw, pool, stored = _run(nsteps, keep_x0=keep_x0 or nsteps == 0, **schedule)
+    assert sw.adjoint_steps == nsteps
+    assert sim.seen == list(range(nsteps - 1, -1, -1))
+    assert len(pool.free) == len({id(b) for b in pool.free})
+
+
+def test_empty_ranges_are_no_ops():
+    sim = FakeSim()
+    pool = ag._Pool(sim)
+    x = pool.get()
+    x.t = 0
+    sw = ag._Sweep(sim, pool, None, None, None, None)
+    for s in (0, 1, 5):
+        sw.binomial(3, 3, x, s)
+    sw.segment(2, 2, x)
+    assert sw.adjoint_steps == 0 and sim.steps == 0 and pool.free == []
+
+
+def test_run_rejects_negative_step_counts():
+    class _Q:
+        q = 27
+
+    with pytest.raises(ValueError):
+        ag.run(_Q(), None, None, None, [1.0] * 23, -1, every=1)
+    with pytest.raises(ValueError):
+        ag.run(_Q(), None, None, None, [1.0] * 23, 2.5, every=1)
