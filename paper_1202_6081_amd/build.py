@@ -89,7 +89,55 @@ def build_probe(verbose=False):
     return PROBE_BIN
 
 
+HOST_DIR = os.path.join(ROOT, "tests", "host")
+HOST_SRC = os.path.join(HOST_DIR, "host_collide.cpp")
+HOST_LIB = os.path.join(HOST_DIR, "libhostmath.so")
+HOST_SAN_SRC = os.path.join(HOST_DIR, "sanitize_main.cpp")
+HOST_SAN_BIN = os.path.join(HOST_DIR, "host_sanitize")
+HOST_FLAGS = ["-std=c++17", "-Wall", "-Wextra", "-Wno-unknown-pragmas", "-Wno-unused-parameter", "-I", CSRC]
+
+
+def _cxx():
+    cxx = shutil.which("g++") or shutil.which("c++")
+    if cxx is None:
+        raise RuntimeError("no C++ compiler found for the host build of the device math")
+    return cxx
+
+
+def build_host_math(verbose=False):
+    """The library's per-node device math (collision, adjoint, initial state)
+    compiled for the CPU as a shared library for the CPU tests
+    (tests/host/host_collide.cpp includes the same headers the kernels use)."""
+    tmp = HOST_LIB + ".tmp"
+    cmd = [_cxx(), *HOST_FLAGS, "-O2", "-fPIC", "-shared", HOST_SRC, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("building the host device math failed")
+    os.replace(tmp, HOST_LIB)
+    return HOST_LIB
+
+
+def build_host_sanitized(verbose=False):
+    """The same host code as an executable with AddressSanitizer and
+    UndefinedBehaviorSanitizer, driven by tests/host/sanitize_main.cpp (CPU only)."""
+    tmp = HOST_SAN_BIN + ".tmp"
+    cmd = [_cxx(), *HOST_FLAGS, "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+           HOST_SRC, HOST_SAN_SRC, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("building the sanitized host device math failed")
+    os.replace(tmp, HOST_SAN_BIN)
+    return HOST_SAN_BIN
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build_host_math(verbose=True))
     print(build_c_test(verbose=True))
     print(build_probe(verbose=True))

@@ -436,4 +436,50 @@ CMLBM_HD void collide27_adj(R (&f)[27], R Fx, R Fy, R Fz, const Rates<R>& p, R (
         g[K3(a, b, c)] += grho + R(a - 1) * gjx + R(b - 1) * gjy + R(c - 1) * gjz;
 }
 
+
+// Initial transformed populations fbar = f^eq(rho, u) - S/2 (paper order): the
+// central moments about u are the Maxwellian's (Sec. 3: rho c_s^(2k) on the
+// even monomials, zero on the odd ones) with -F/2 on the first-order ones (the
+// source changes only those, Eq. discretecentralsources); the inverse passes
+// return them to populations.
+template <typename R>
+CMLBM_HD void initial27(R rho, R ux, R uy, R uz, R Fx, R Fy, R Fz, R (&f)[27]) {
+  R m[27];
+#pragma unroll
+  for (int i = 0; i < 27; ++i) m[i] = R(0);
+  const R c2 = rho * R(1.0 / 3.0);
+  m[K3(0, 0, 0)] = rho;
+  m[K3(1, 0, 0)] = R(-0.5) * Fx;
+  m[K3(0, 1, 0)] = R(-0.5) * Fy;
+  m[K3(0, 0, 1)] = R(-0.5) * Fz;
+  m[K3(2, 0, 0)] = m[K3(0, 2, 0)] = m[K3(0, 0, 2)] = c2;
+  m[K3(2, 2, 0)] = m[K3(2, 0, 2)] = m[K3(0, 2, 2)] = c2 * R(1.0 / 3.0);
+  m[K3(2, 2, 2)] = c2 * R(1.0 / 9.0);
+  inv_pass<0>(m, ux);
+  inv_pass<1>(m, uy);
+  inv_pass<2>(m, uz);
+#pragma unroll
+  for (int a = 0; a < 27; ++a) f[a] = m[cube27(a)];
+}
+
+// Adjoint of initial27 with respect to the force (u fixed): the populations
+// are the inverse-pass image of the moments above, linear in F through the
+// first-order entries -F/2.  lam: adjoint of f (paper order); adds to gF*.
+template <typename R>
+CMLBM_HD void initial27_adj_force(R ux, R uy, R uz, const R (&lam)[27], R& gFx, R& gFy, R& gFz) {
+  R gm[27], zero[27];
+#pragma unroll
+  for (int a = 0; a < 27; ++a) {
+    gm[cube27(a)] = lam[a];
+    zero[a] = R(0);
+  }
+  R gu = R(0);   // the inputs of the passes only enter the velocity adjoint, unused here
+  inv_pass_adj<2>(zero, uz, gm, gu);
+  inv_pass_adj<1>(zero, uy, gm, gu);
+  inv_pass_adj<0>(zero, ux, gm, gu);
+  gFx += R(-0.5) * gm[K3(1, 0, 0)];
+  gFy += R(-0.5) * gm[K3(0, 1, 0)];
+  gFz += R(-0.5) * gm[K3(0, 0, 1)];
+}
+
 }  // namespace cmlbm

@@ -852,24 +852,7 @@ __global__ __launch_bounds__(256) void k_initial_pre(Geom g, const typename ST::
       R Fx, Fy, Fz;
       force_at(force, g.N, n, Fx, Fy, Fz);
       if constexpr (Q == 27) {
-        // central moments of f^eq - S/2 about u: Maxwellian values rho c_s^(2k)
-        // on even monomials and -F/2 on the first-order ones; then the inverse passes.
-        R m[27];
-#pragma unroll
-        for (int i = 0; i < 27; ++i) m[i] = R(0);
-        const R c2 = rho * R(1.0 / 3.0);
-        m[K3(0, 0, 0)] = rho;
-        m[K3(1, 0, 0)] = R(-0.5) * Fx;
-        m[K3(0, 1, 0)] = R(-0.5) * Fy;
-        m[K3(0, 0, 1)] = R(-0.5) * Fz;
-        m[K3(2, 0, 0)] = m[K3(0, 2, 0)] = m[K3(0, 0, 2)] = c2;
-        m[K3(2, 2, 0)] = m[K3(2, 0, 2)] = m[K3(0, 2, 2)] = c2 * R(1.0 / 3.0);
-        m[K3(2, 2, 2)] = c2 * R(1.0 / 9.0);
-        inv_pass<0>(m, ux);
-        inv_pass<1>(m, uy);
-        inv_pass<2>(m, uz);
-#pragma unroll
-        for (int a = 0; a < 27; ++a) f[a] = m[cube27(a)];
+        initial27(rho, ux, uy, uz, Fx, Fy, Fz, f);
       } else {
         initial15(rho, ux, uy, uz, Fx, Fy, Fz, f);
       }
@@ -1162,31 +1145,14 @@ __global__ __launch_bounds__(256) void k_init_adjoint(Geom g, const R* u0, const
   for (uint32_t n = blockIdx.x * blockDim.x + threadIdx.x; n < g.N; n += gridDim.x * blockDim.x) {
     if (mask && mask[n]) continue;
     const R ux = u0[n], uy = u0[g.N + n], uz = u0[2 * g.N + n];
-    R gx_, gy_, gz_;
-    if constexpr (Q == 27) {
-      // fbar(0) = inverse passes of (Maxwellian moments, -F/2 on the first
-      // central moments): the F adjoint is -1/2 times the first-order entries
-      // of the inverse passes' adjoint.
-      R gm[27], zero[27];
+    R lam[Q];
 #pragma unroll
-      for (int a = 0; a < 27; ++a) {
-        gm[cube27(a)] = lam0[uint64_t(a) * g.N + n];
-        zero[a] = R(0);
-      }
-      R gu = R(0);
-      inv_pass_adj<2>(zero, uz, gm, gu);
-      inv_pass_adj<1>(zero, uy, gm, gu);
-      inv_pass_adj<0>(zero, ux, gm, gu);
-      gx_ = R(-0.5) * gm[K3(1, 0, 0)];
-      gy_ = R(-0.5) * gm[K3(0, 1, 0)];
-      gz_ = R(-0.5) * gm[K3(0, 0, 1)];
-    } else {
-      R lam[15];
-#pragma unroll
-      for (int a = 0; a < 15; ++a) lam[a] = lam0[uint64_t(a) * g.N + n];
-      gx_ = gy_ = gz_ = R(0);
+    for (int a = 0; a < Q; ++a) lam[a] = lam0[uint64_t(a) * g.N + n];
+    R gx_ = R(0), gy_ = R(0), gz_ = R(0);
+    if constexpr (Q == 27)
+      initial27_adj_force(ux, uy, uz, lam, gx_, gy_, gz_);
+    else
       initial15_adj_force(ux, uy, uz, lam, gx_, gy_, gz_);
-    }
     const double c = double(force.scale);
     const double gx = c * double(gx_), gy = c * double(gy_), gz = c * double(gz_);
     if (force.field) {

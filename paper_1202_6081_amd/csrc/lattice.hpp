@@ -8,7 +8,8 @@
 
 #include <cstdint>
 
-// Device code below is also compiled for the host by the build's self-checks.
+// The per-node math in these headers is also compiled for the CPU
+// (tests/host/host_collide.cpp), where the CPU tests compare it with the oracle.
 #ifndef CMLBM_HD
 #define CMLBM_HD __host__ __device__ __forceinline__
 #define CMLBM_HDC __host__ __device__ constexpr
