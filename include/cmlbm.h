@@ -20,7 +20,8 @@
  *             (nx*ny*nz/8 bytes for the fused step totals, about
  *             26*ceil(nx/256)*ny*nz bytes for the adjoint's partial sums, and
  *             about 120 KiB), all allocated by cmlbm_create: no other call
- *             allocates.
+ *             allocates.  cmlbm_step_totals_noalloc uses a static device array
+ *             of the library instead (see there).
  *             Device pointers must be aligned to their element size
  *             (hipMalloc and torch allocations are); a call given a
  *             misaligned one returns EINVAL before launching anything.
@@ -166,6 +167,21 @@ cmlbm_status cmlbm_step(cmlbm_sim *sim, const void *f_in, void *f_out, void *str
  * overwritten, written asynchronously on `stream` (no host synchronization).
  * Errors: as cmlbm_step; EINVAL if totals_dev is NULL. */
 cmlbm_status cmlbm_step_totals(cmlbm_sim *sim, const void *f_in, void *f_out, double *totals_dev, void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same step
+ * and totals as cmlbm_step_totals, bit for bit, with the per-block partial sums
+ * kept in a static device array of the library (16 MiB + 8 KiB per device,
+ * held until the process ends) instead of the handle's scratch.  This call
+ * allocates nothing and clears nothing: every partial it reads was written by
+ * the same call.  All handles on one device share that array, so calls that
+ * overlap in time on one device race (order them on one stream).  Limit: the
+ * lattice may have at most 2^19 step blocks, ceil(nx/256)*ny*nz <= 524288
+ * (512^3, for instance).  Errors: as cmlbm_step_totals; EINVAL for a larger
+ * lattice (checked before any launch); EDEVICE if the array's device address
+ * could not be looked up when the handle was created. */
+cmlbm_status cmlbm_step_totals_noalloc(cmlbm_sim *sim, const void *f_in, void *f_out, double *totals_dev,
+                                       void *stream);
 
 /* nsteps >= 0 steps ping-ponging between f_a and f_b, starting from f_a.
  * *result_in_b (may be NULL) is set to 1 when the last state is in f_b. */

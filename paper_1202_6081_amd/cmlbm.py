@@ -48,6 +48,7 @@ def load_library():
         "cmlbm_init_equilibrium": (i, [vp, vp, vp, vp, vp, vp]),
         "cmlbm_step": (i, [vp, vp, vp, vp]),
         "cmlbm_step_totals": (i, [vp, vp, vp, vp, vp]),
+        "cmlbm_step_totals_noalloc": (i, [vp, vp, vp, vp, vp]),
         "cmlbm_run": (i, [vp, vp, vp, i, vp, ctypes.POINTER(i)]),
         "cmlbm_gather_precollision": (i, [vp, vp, vp, vp]),
         "cmlbm_export_populations": (i, [vp, vp, vp, vp]),
@@ -79,7 +80,8 @@ def load_library():
 def exported_symbols():
     return ["cmlbm_create", "cmlbm_destroy", "cmlbm_set_rates", "cmlbm_set_force_uniform",
             "cmlbm_set_force_field", "cmlbm_set_force_scale", "cmlbm_set_attractor_per_mass", "cmlbm_set_mask",
-            "cmlbm_init_equilibrium", "cmlbm_step", "cmlbm_step_totals", "cmlbm_run", "cmlbm_gather_precollision",
+            "cmlbm_init_equilibrium", "cmlbm_step", "cmlbm_step_totals", "cmlbm_step_totals_noalloc", "cmlbm_run",
+            "cmlbm_gather_precollision",
             "cmlbm_export_populations", "cmlbm_import_populations", "cmlbm_macroscopic", "cmlbm_totals",
             "cmlbm_init_equilibrium_inplace", "cmlbm_step_inplace", "cmlbm_step_inplace_totals",
             "cmlbm_run_inplace", "cmlbm_macroscopic_pre", "cmlbm_totals_pre",
@@ -182,6 +184,12 @@ def cmlbm_step_totals(h, f_in, f_out, totals, stream=None):
     if totals.dtype != torch.float64 or totals.numel() < 4:
         raise CmlbmError(-1, "totals must be a device tensor of at least 4 float64")
     _check(load_library().cmlbm_step_totals(h, _ptr(f_in), _ptr(f_out), _ptr(totals), _stream(stream)), h)
+
+
+def cmlbm_step_totals_noalloc(h, f_in, f_out, totals, stream=None):
+    if totals.dtype != torch.float64 or totals.numel() < 4:
+        raise CmlbmError(-1, "totals must be a device tensor of at least 4 float64")
+    _check(load_library().cmlbm_step_totals_noalloc(h, _ptr(f_in), _ptr(f_out), _ptr(totals), _stream(stream)), h)
 
 
 def cmlbm_run(h, f_a, f_b, nsteps, stream=None):

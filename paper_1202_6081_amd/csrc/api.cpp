@@ -29,6 +29,8 @@ struct cmlbm_sim {
   double* adj_partials = nullptr;      // [adj_nblk][26] + [kReduceChunks][26]: adjoint dL/domega, uniform dL/dF
   int adj_nblk = 0;
   double* step_partials = nullptr;     // [step_blocks][4] + [kReduceChunks][4], fused step totals
+  double* static_partials = nullptr;   // this device's static scratch (cmlbm_step_totals_noalloc), not owned
+  std::string static_err;              // why static_partials is null
   std::string err;
 };
 
@@ -214,6 +216,10 @@ cmlbm_status cmlbm_create(int q, int nx, int ny, int nz, int precision, cmlbm_si
     cmlbm_destroy(s);
     return CMLBM_ENOMEM;
   }
+  // the allocation-free step's scratch: looked up once per device, here, with
+  // the handle's device current
+  const hipError_t se = cmlbm::static_scratch(&s->static_partials);
+  if (se != hipSuccess) s->static_err = std::string("static scratch lookup failed: ") + hipGetErrorString(se);
   *out = s;
   return CMLBM_OK;
 }
@@ -304,15 +310,18 @@ cmlbm_status cmlbm_init_equilibrium_inplace(cmlbm_sim* s, const void* rho_dev, c
 
 namespace {
 
-cmlbm_status step_common(cmlbm_sim* s, const void* f_in, void* f_out, double* totals_dev, void* stream) {
+// scratch: [step_blocks][4] partials followed by [kReduceChunks][4] stage sums
+// (used only with totals_dev).
+cmlbm_status step_common(cmlbm_sim* s, const void* f_in, void* f_out, double* totals_dev, double* scratch,
+                         void* stream) {
   if (!f_in || !f_out) return fail(s, CMLBM_EINVAL, "NULL population buffer");
   if (f_in == f_out) return fail(s, CMLBM_EINVAL, "f_in and f_out must differ (pull streaming)");
   CMLBM_CHECK_ALIGNED(s, {f_in, pop_bytes(s)}, {f_out, pop_bytes(s)}, {totals_dev, sizeof(double)});
   double* partials = nullptr;
   double* stage = nullptr;
   if (totals_dev) {
-    partials = s->step_partials;
-    stage = s->step_partials + 4 * cmlbm::step_blocks(s->g);
+    partials = scratch;
+    stage = scratch + 4 * cmlbm::step_blocks(s->g);
   }
   cmlbm::StepArgs<double> a64{};
   cmlbm::StepArgs<float> a32{};
@@ -344,13 +353,25 @@ cmlbm_status step_common(cmlbm_sim* s, const void* f_in, void* f_out, double* to
 
 cmlbm_status cmlbm_step(cmlbm_sim* s, const void* f_in, void* f_out, void* stream) {
   CMLBM_WORK_ENTRY(s);
-  return step_common(s, f_in, f_out, nullptr, stream);
+  return step_common(s, f_in, f_out, nullptr, nullptr, stream);
 }
 
 cmlbm_status cmlbm_step_totals(cmlbm_sim* s, const void* f_in, void* f_out, double* totals_dev, void* stream) {
   CMLBM_WORK_ENTRY(s);
   if (!totals_dev) return fail(s, CMLBM_EINVAL, "totals_dev is NULL");
-  return step_common(s, f_in, f_out, totals_dev, stream);
+  return step_common(s, f_in, f_out, totals_dev, s->step_partials, stream);
+}
+
+cmlbm_status cmlbm_step_totals_noalloc(cmlbm_sim* s, const void* f_in, void* f_out, double* totals_dev,
+                                       void* stream) {
+  CMLBM_WORK_ENTRY(s);
+  if (cmlbm::step_blocks(s->g) > cmlbm::kStaticStepBlocks)
+    return fail(s, CMLBM_EINVAL,
+                "lattice too large for the static scratch: " + std::to_string(cmlbm::step_blocks(s->g)) +
+                    " step blocks (ceil(nx/256)*ny*nz), at most " + std::to_string(cmlbm::kStaticStepBlocks));
+  if (!totals_dev) return fail(s, CMLBM_EINVAL, "totals_dev is NULL");
+  if (!s->static_partials) return fail(s, CMLBM_EDEVICE, s->static_err);
+  return step_common(s, f_in, f_out, totals_dev, s->static_partials, stream);
 }
 
 cmlbm_status cmlbm_run(cmlbm_sim* s, void* f_a, void* f_b, int nsteps, void* stream, int* result_in_b) {

@@ -113,6 +113,17 @@ constexpr int kReduceChunks = 256;
 // Blocks of one step launch (one block per CMLBM_STEP_BLOCK-wide row segment).
 uint64_t step_blocks(const Geom& g);
 
+// Static device scratch of the allocation-free fused-totals step: room for the
+// per-block partials of at most kStaticStepBlocks step blocks and the
+// second-stage sums, kStaticScratchDoubles doubles (16 MiB + 8 KiB) per device,
+// held until the process ends.
+constexpr uint64_t kStaticStepBlocks = uint64_t(1) << 19;
+constexpr uint64_t kStaticScratchDoubles = 4 * (kStaticStepBlocks + kReduceChunks);
+
+// Device address of that scratch on the current device, looked up once per
+// device (hipGetSymbolAddress) and cached; *out is null on failure.
+hipError_t static_scratch(double** out);
+
 // Work-items of the largest grid the lattice's launches use (the step and the
 // adjoint cover whole row segments rounded up to 64 lanes); a dispatch counts
 // its work-items in 32 bits.
