@@ -8,7 +8,9 @@ the step is analytic).
   dL/domega of the mean kinetic energy after N steps;
 * the 64^3, 200-step, checkpoint-every-20 configuration: FP32 gradient against
   the FP64 GPU gradient, and the FP64 GPU gradient against central finite
-  differences of the FP64 GPU forward run.
+  differences of the FP64 GPU forward run;
+* the same configuration on a reduced 32^3 lattice against the FP64 oracle's
+  complex-step derivatives (tests/golden/adjoint32_d3q27.json), FP64 and FP32.
 """
 import numpy as np
 import pytest
@@ -320,3 +322,50 @@ def test_full_size_adjoint_sampled_nodes(q):
     err_F = np.abs(got_F - want_F).max() / np.abs(want_F).max()
     print(f"adjoint full512 q{q}: lam rel err {err:.2e}, dL/dF rel err {err_F:.2e}", flush=True)
     assert err < 1e-5 and err_F < 1e-5
+
+
+def _golden(name):
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)) as fh:
+        return json.load(fh)
+
+
+# FP64: the GPU adjoint and the oracle's complex step differ by rounding only
+# (measured: loss 2.6e-13, dL/dF.v 2.7e-12, dL/domega_shear 1.9e-13, entries
+# 6.6e-13).  FP32: populations rounded to 2^-24 carry a velocity of 0.02 as
+# differences of O(0.1) values, about 1e-6 relative per step over 200 steps,
+# and a projection of the gradient on a random direction cancels further
+# (measured: loss 1.0e-5, dL/dF.v 1.2e-4, shear 7.3e-6, entries 8.5e-6); the
+# bounds are about three times those.
+GOLDEN4_TOL = {F64: 1e-9, F32: 4e-4}
+GOLDEN4_LOSS_TOL = {F64: 1e-12, F32: 3e-5}
+
+
+@pytest.mark.parametrize("prec", [F64, F32])
+def test_config4_reduced_lattice_vs_oracle_golden(prec):
+    # The adjoint configuration on a reduced 32^3 lattice (Taylor-Green start,
+    # k0 = 2 pi/32, u0 = 0.02; F ~ N(0, (1e-6)^2) per node and component, seed
+    # 2024; shear 1.6, others 1; 200 steps, checkpoints every 20; loss = mean
+    # kinetic energy of fbar(200)) against complex-step derivatives of the FP64
+    # oracle's run (tests/golden/adjoint32_d3q27.json, written by
+    # tests/golden/make_config_goldens.py): the loss, dL/dF along a seeded unit
+    # direction, four single entries of dL/dF, and dL/domega_shear.
+    print(f"case config4 golden 32^3 p{prec}", flush=True)
+    g = _golden("adjoint32_d3q27.json")
+    n, steps = g["recipe"]["n"], g["recipe"]["steps"]
+    F = inp.gaussian_force((n, n, n), 1e-6, 2024)
+    v = inp.gaussian_force((n, n, n), 1.0, 99)
+    v /= np.sqrt((v * v).sum())
+    L, gF, gw = _config4(prec, F, om_shear=g["recipe"]["shear"], nsteps=steps, every=20, n=n)
+    d_v = float((gF * v).sum())
+    d_shear = float(gw[:5].sum())
+    d_entries = [float(gF[c, z, y, x]) for c, z, y, x in g["entries"]]
+    scale = max(abs(e) for e in g["dL_dF_entries"])
+    errs = {"loss": abs(L / g["loss"] - 1), "dF.v": abs(d_v / g["dL_dF_dot_v"] - 1),
+            "dw_shear": abs(d_shear / g["dL_domega_shear"] - 1),
+            "entries": max(abs(a - b) for a, b in zip(d_entries, g["dL_dF_entries"])) / scale}
+    print(f"config4 golden p{prec}: " + ", ".join(f"{k} {e:.3e}" for k, e in errs.items()), flush=True)
+    tol = GOLDEN4_TOL[prec]
+    assert errs["dF.v"] <= tol and errs["dw_shear"] <= tol and errs["entries"] <= tol
+    assert errs["loss"] <= GOLDEN4_LOSS_TOL[prec]
