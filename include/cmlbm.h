@@ -276,6 +276,25 @@ cmlbm_status cmlbm_totals_pre(cmlbm_sim *sim, const void *f_pre_buf, double out4
 cmlbm_status cmlbm_adjoint_step(cmlbm_sim *sim, const void *f_post_prev, const void *lam_next, void *lam,
                                 double *dLdF_dev, double *dLdomega_dev, void *stream);
 
+/* Wall-layout sensitivity of one step.  The paper's walls are whole nodes
+ * with half-way bounce-back (Sec. 9); to differentiate a loss with respect to
+ * where they lie, give every node a wall fraction phi in [0, 1] and stream by
+ *   fbar_a(x) = (1 - phi(x)) fbar~_a(x - e_a) + phi(x - e_a) fbar~_abar(x),
+ * which is plain streaming at phi = 0 and the half-way bounce-back at phi = 1
+ * (the population from s to t = s + e_a arrives with weight 1 - phi(t) and
+ * returns reversed with weight phi(t), so mass is conserved).  At phi = the
+ * mask, this call adds the step's contribution
+ *   dL/dphi(t) += sum_a fbar~_a(t - e_a) (lam_abar(t - e_a) - lam_a(t))
+ * over fluid neighbours t - e_a, to dLdphi_dev (FP64 [nz][ny][nx]) at every
+ * fluid node t; solid nodes are left unchanged (the collision switches off at
+ * phi = 1, so the derivative does not exist there).  f_post_prev and lam_next
+ * are those of cmlbm_adjoint_step for the same step (lam_next = dL/dfbar^(n+1),
+ * "real" SoA populations); call it before the adjoint step that replaces
+ * lam_next.  The additions are FP64 atomics, in no fixed order.  Uses the
+ * current force, rates and mask.  Errors: EINVAL (NULL, aliasing). */
+cmlbm_status cmlbm_wall_sensitivity(cmlbm_sim *sim, const void *f_post_prev, const void *lam_next,
+                                    double *dLdphi_dev, void *stream);
+
 /* Kinetic-energy loss of a pre-collision state: *out = sum over fluid nodes of
  * |rho u|^2 / (2 rho), rho u = sum fbar e + F/2 (Eqs. densitycalculation,
  * velocitycalculation), accumulated in FP64.  f_pre: "real" [q][nz][ny][nx]

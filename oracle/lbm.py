@@ -65,6 +65,36 @@ def stream(lat, post, solid=None):
     return out
 
 
+def stream_wall_fraction(lat, post, phi):
+    """Streaming with a wall fraction phi(x) in [0, 1] per node, a linear blend
+    of plain streaming and the half-way bounce-back named in Sec. 9 (the paper
+    has only whole walls; this continuous form exists to differentiate the loss
+    with respect to the wall layout):
+
+        fbar_a(x) = (1 - phi(x)) fbar~_a(x - e_a) + phi(x - e_a) fbar~_abar(x).
+
+    A population leaving s towards t = s + e_a arrives at t with weight
+    1 - phi(t) and returns to s, reversed, with weight phi(t), so mass is
+    conserved.  Nodes with phi = 1 are solid: never collided, zero populations.
+    With phi in {0, 1} this is ``stream(lat, post, solid=(phi == 1))`` exactly."""
+    phi = np.asarray(phi)
+    out = np.zeros(post.shape, dtype=np.result_type(post, phi))
+    for a, (ex, ey, ez) in enumerate(lat.E):
+        shift = (int(ez), int(ey), int(ex))
+        pulled = np.roll(post[a], shift=shift, axis=(0, 1, 2))        # fbar~_a(x - e_a)
+        phi_src = np.roll(phi, shift=shift, axis=(0, 1, 2))           # phi(x - e_a)
+        out[a] = (1 - phi) * pulled + phi_src * post[lat.opp[a]]
+    out[:, phi == 1] = 0
+    return out
+
+
+def step_wall_fraction(lat, f, F, omega, phi, per_mass=False):
+    """One step with the wall-fraction streaming above; nodes with phi < 1
+    collide."""
+    solid = np.asarray(phi) == 1
+    return stream_wall_fraction(lat, collide_field(lat, f, F, omega, solid, per_mass), phi)
+
+
 def step(lat, f, F, omega, solid=None, per_mass=False):
     """One collide-and-stream step of the pre-collision state (per_mass: the
     attractor form, see collision.attractors)."""

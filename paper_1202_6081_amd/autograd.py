@@ -122,14 +122,19 @@ def _advance(sim, pool, x, k):
 class _Sweep:
     """Reverse sweep over steps [l, r) given stored x(l)."""
 
-    def __init__(self, sim, pool, lam, lam_tmp, dLdF, dLdw):
+    def __init__(self, sim, pool, lam, lam_tmp, dLdF, dLdw, dLdphi=None):
         self.sim, self.pool = sim, pool
         self.lam, self.lam_tmp = lam, lam_tmp
         self.dLdF, self.dLdw = dLdF, dLdw
+        self.dLdphi = dLdphi
         self.recomputed = 0
         self.adjoint_steps = 0
 
     def adjoint(self, x):
+        # the wall-layout term of this step's streaming needs lam(n+1), which
+        # the adjoint step is about to replace
+        if self.dLdphi is not None:
+            self.sim.wall_sensitivity(x, self.lam, self.dLdphi)
         self.sim.adjoint_step(x, self.lam, self.lam_tmp, self.dLdF, self.dLdw)
         self.lam, self.lam_tmp = self.lam_tmp, self.lam
         self.adjoint_steps += 1
@@ -237,9 +242,11 @@ def keep_positions(nsteps, every, snapshots):
 
 class _Run(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, F, omega, sim, rho0, u0, nsteps, every, snapshots):
+    def forward(ctx, F, omega, sim, rho0, u0, nsteps, every, snapshots, wall=None):
         rates = [float(w) for w in omega.detach().cpu()]
         sim.set_rates(rates)
+        if wall is not None:
+            sim.set_mask(wall.detach() == 1)
         Fr = F.detach().to(device=sim.device, dtype=sim.real).contiguous()
         sim.set_force(Fr)
         pool = _Pool(sim)
@@ -261,6 +268,8 @@ class _Run(torch.autograd.Function):
         ctx.F_dtype, ctx.w_dtype, ctx.F_shape = F.dtype, omega.dtype, F.shape
         ctx.F_device, ctx.w_device = F.device, omega.device
         ctx.Fr, ctx.rates = Fr, rates
+        ctx.wall = None if wall is None else wall.detach()
+        ctx.wall_dtype = None if wall is None else wall.dtype
         ctx.consumed = False
         return pre
 
@@ -274,11 +283,15 @@ class _Run(torch.autograd.Function):
         # the handle may have run something else since the forward pass
         sim.set_rates(ctx.rates)
         sim.set_force(ctx.Fr)
+        dLdphi = None
+        if ctx.wall is not None:
+            sim.set_mask(ctx.wall == 1)
+            dLdphi = torch.zeros((sim.nz, sim.ny, sim.nx), dtype=torch.float64, device=sim.device)
         lam = g.detach().to(dtype=sim.real).contiguous().clone()
         lam_tmp = sim.real_populations()
         dLdF = torch.zeros(ctx.F_shape, dtype=torch.float64, device=sim.device)
         dLdw = torch.zeros(sim.q - 4, dtype=torch.float64, device=sim.device)
-        sw = _Sweep(sim, pool, lam, lam_tmp, dLdF, dLdw)
+        sw = _Sweep(sim, pool, lam, lam_tmp, dLdF, dLdw, dLdphi)
 
         def rebuild_x0():
             # lam_tmp is free between adjoint steps: scratch for the pre-collision state
@@ -292,8 +305,10 @@ class _Run(torch.autograd.Function):
         _last_stats.update(ctx.stats)
         _last_stats["dLdF_fp64"] = dLdF
         _last_stats["dLdomega_fp64"] = dLdw
+        _last_stats["dLdphi_fp64"] = dLdphi
+        gwall = None if dLdphi is None else dLdphi.to(device=ctx.wall.device, dtype=ctx.wall_dtype)
         return (dLdF.to(device=ctx.F_device, dtype=ctx.F_dtype), dLdw.to(device=ctx.w_device, dtype=ctx.w_dtype),
-                None, None, None, None, None, None)
+                None, None, None, None, None, None, gwall)
 
 
 _last_stats = {}
@@ -304,21 +319,32 @@ def last_backward_stats():
     return dict(_last_stats)
 
 
-def run(sim, rho0, u0, F, omega, nsteps, every=None, snapshots=None):
+def run(sim, rho0, u0, F, omega, nsteps, every=None, snapshots=None, wall=None):
     """Differentiable run: returns the pre-collision populations fbar(N)
     (Q, nz, ny, nx), differentiable with respect to the force field F
     (3, nz, ny, nx) or uniform force F (3,), and the rates omega (Q - 4,).
     Exactly one of `every` (uniform checkpoint interval) or `snapshots`
     (binomial schedule with that many stored states besides x(0)) must be
     given.  nsteps = 0 returns fbar(0), whose gradient is that of the initial
-    state alone."""
+    state alone.
+
+    wall: optional wall fraction phi (nz, ny, nx) with values 0 (fluid) or 1
+    (solid); it sets the sim's mask for the run, and its gradient is dL/dphi of
+    the streaming fbar_a(x) = (1 - phi(x)) fbar~_a(x - e_a) + phi(x - e_a)
+    fbar~_abar(x), which is the half-way bounce-back at phi in {0, 1}: the
+    sensitivity of the loss to making each fluid node partly solid (zero at
+    solid nodes, where the collision switches off and no derivative exists)."""
     if int(nsteps) != nsteps or nsteps < 0:
         raise ValueError("nsteps must be an integer >= 0")
     if len(omega) != sim.q - 4:
         raise ValueError(f"expected {sim.q - 4} rates")
     if (every is None) == (snapshots is None):
         raise ValueError("give exactly one of every= or snapshots=")
-    return _Run.apply(F, omega, sim, rho0, u0, int(nsteps), int(every or 0), int(snapshots or 0))
+    if wall is not None:
+        w = wall.detach()
+        if tuple(w.shape) != (sim.nz, sim.ny, sim.nx) or not bool(((w == 0) | (w == 1)).all()):
+            raise ValueError("wall must be a (nz, ny, nx) tensor of zeros (fluid) and ones (solid)")
+    return _Run.apply(F, omega, sim, rho0, u0, int(nsteps), int(every or 0), int(snapshots or 0), wall)
 
 
 class _KineticEnergy(torch.autograd.Function):

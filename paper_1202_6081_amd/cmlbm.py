@@ -62,6 +62,7 @@ def load_library():
         "cmlbm_macroscopic_pre": (i, [vp, vp, vp, vp, vp]),
         "cmlbm_totals_pre": (i, [vp, vp, ctypes.POINTER(d), vp]),
         "cmlbm_adjoint_step": (i, [vp, vp, vp, vp, vp, vp, vp]),
+        "cmlbm_wall_sensitivity": (i, [vp, vp, vp, vp, vp]),
         "cmlbm_kinetic_energy_sum": (i, [vp, vp, ctypes.POINTER(d), vp]),
         "cmlbm_kinetic_energy_seed": (i, [vp, vp, d, vp, vp, vp]),
         "cmlbm_init_adjoint": (i, [vp, vp, vp, vp, vp]),
@@ -85,7 +86,8 @@ def exported_symbols():
             "cmlbm_export_populations", "cmlbm_import_populations", "cmlbm_macroscopic", "cmlbm_totals",
             "cmlbm_init_equilibrium_inplace", "cmlbm_step_inplace", "cmlbm_step_inplace_totals",
             "cmlbm_run_inplace", "cmlbm_macroscopic_pre", "cmlbm_totals_pre",
-            "cmlbm_adjoint_step", "cmlbm_kinetic_energy_sum", "cmlbm_kinetic_energy_seed", "cmlbm_init_adjoint",
+            "cmlbm_adjoint_step", "cmlbm_wall_sensitivity", "cmlbm_kinetic_energy_sum", "cmlbm_kinetic_energy_seed",
+            "cmlbm_init_adjoint",
             "cmlbm_status_string", "cmlbm_last_error", "cmlbm_version"]
 
 
@@ -251,6 +253,11 @@ def cmlbm_totals_pre(h, f_pre_buf, stream=None):
 def cmlbm_adjoint_step(h, f_post_prev, lam_next, lam, dLdF, dLdomega, stream=None):
     _check(load_library().cmlbm_adjoint_step(h, _ptr(f_post_prev), _ptr(lam_next), _ptr(lam), _ptr(dLdF),
                                               _ptr(dLdomega), _stream(stream)), h)
+
+
+def cmlbm_wall_sensitivity(h, f_post_prev, lam_next, dLdphi, stream=None):
+    _check(load_library().cmlbm_wall_sensitivity(h, _ptr(f_post_prev), _ptr(lam_next), _ptr(dLdphi),
+                                                  _stream(stream)), h)
 
 
 def cmlbm_kinetic_energy_sum(h, f_pre, stream=None):
@@ -458,6 +465,12 @@ class Sim:
         self._dLdF(dLdF)
         self._need(dLdomega, torch.float64, self.q - 4, "dLdomega")
         cmlbm_adjoint_step(self.h, f_post_prev, lam_next, lam, dLdF, dLdomega, stream)
+
+    def wall_sensitivity(self, f_post_prev, lam_next, dLdphi, stream=None):
+        self._pop(f_post_prev, "f_post_prev")
+        self._realpop(lam_next, "lam_next")
+        self._need(dLdphi, torch.float64, self.nodes, "dLdphi")
+        cmlbm_wall_sensitivity(self.h, f_post_prev, lam_next, dLdphi, stream)
 
     def kinetic_energy_sum(self, f_pre, stream=None):
         return cmlbm_kinetic_energy_sum(self.h, self._realpop(f_pre, "f_pre"), stream)

@@ -560,6 +560,35 @@ cmlbm_status cmlbm_adjoint_step(cmlbm_sim* s, const void* f_post_prev, const voi
   return check_hip(s, e, "adjoint_step");
 }
 
+cmlbm_status cmlbm_wall_sensitivity(cmlbm_sim* s, const void* f_post_prev, const void* lam_next, double* dLdphi_dev,
+                                    void* stream) {
+  CMLBM_WORK_ENTRY(s);
+  if (!f_post_prev || !lam_next || !dLdphi_dev) return fail(s, CMLBM_EINVAL, "NULL buffer");
+  if (f_post_prev == lam_next || static_cast<const void*>(dLdphi_dev) == lam_next ||
+      static_cast<const void*>(dLdphi_dev) == f_post_prev)
+    return fail(s, CMLBM_EINVAL, "f_post_prev, lam_next and dLdphi must differ");
+  CMLBM_CHECK_ALIGNED(s, {f_post_prev, pop_bytes(s)}, {lam_next, real_bytes(s)}, {dLdphi_dev, sizeof(double)});
+  cmlbm::AdjArgs<double> a64{};
+  cmlbm::AdjArgs<float> a32{};
+  if (s->prec == CMLBM_F64) {
+    a64.g = s->g;
+    a64.fpost = f_post_prev;
+    a64.lam_next = static_cast<const double*>(lam_next);
+    a64.mask = s->mask;
+    a64.force = make_force<double>(s);
+    a64.rates = make_rates<double>(s);
+  } else {
+    a32.g = s->g;
+    a32.fpost = f_post_prev;
+    a32.lam_next = static_cast<const float*>(lam_next);
+    a32.mask = s->mask;
+    a32.force = make_force<float>(s);
+    a32.rates = make_rates<float>(s);
+  }
+  hipError_t e = cmlbm::launch_wall_sensitivity(s->q, s->prec, a64, a32, dLdphi_dev, static_cast<hipStream_t>(stream));
+  return check_hip(s, e, "wall_sensitivity");
+}
+
 cmlbm_status cmlbm_kinetic_energy_sum(cmlbm_sim* s, const void* f_pre, double* out, void* stream) {
   CMLBM_WORK_ENTRY(s);
   if (!f_pre || !out) return fail(s, CMLBM_EINVAL, "NULL buffer");

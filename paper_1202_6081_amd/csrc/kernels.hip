@@ -1055,6 +1055,46 @@ __global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(adjoi
 }
 
 // ---------------------------------------------------------------------------
+// Wall-layout sensitivity.  Give each node a wall fraction phi(x) in [0, 1] and
+// stream by fbar_a(x) = (1 - phi(x)) fbar~_a(x - e_a) + phi(x - e_a) fbar~_abar(x):
+// a population leaving s for t = s + e_c arrives with weight 1 - phi(t) and
+// returns to s reversed with weight phi(t).  At phi in {0, 1} this is the pull
+// with half-way bounce-back (Sec. 9) that the step kernels run.  Its derivative
+// at the mask, with lam_next = dL/dfbar^{n+1}:
+//   dL/dphi(t) += sum_c fbar~_c(s) [lam_cbar(s) - lam_c(t)],  s = t - e_c fluid
+// (solid nodes hold no populations).  Each fluid node s recomputes fbar~(s)
+// from the pull of f_post_prev and adds its terms to its fluid targets with
+// FP64 atomics; solid targets get nothing (the collision switches off there).
+// ---------------------------------------------------------------------------
+template <int Q, class ST, bool MASK>
+__global__ __launch_bounds__(256) void k_wall_sens(AdjArgs<typename ST::R> args, double* dLdphi) {
+  using R = typename ST::R;
+  const Geom g = args.g;
+  const uint32_t nx = uint32_t(g.nx);
+  for (uint32_t n = blockIdx.x * blockDim.x + threadIdx.x; n < g.N; n += gridDim.x * blockDim.x) {
+    if (MASK && args.mask[n]) continue;
+    const Coord c = coord_of(g, n);
+    R f[Q];
+    {
+      const Stencil up(g, c, +1);
+      pull<Q, ST, MASK>(static_cast<const typename ST::T*>(args.fpost), g, args.mask, up, n / nx, uint32_t(c.x), f);
+    }
+    R Fx, Fy, Fz;
+    force_at(args.force, g.N, n, Fx, Fy, Fz);
+    collide<Q>(f, Fx, Fy, Fz, args.rates);
+    const Stencil dn(g, c, -1);
+#pragma unroll
+    for (int a = 1; a < Q; ++a) {
+      const uint32_t t = dn.node(Lattice<Q>::e(a), nx);
+      if (MASK && args.mask[t]) continue;
+      const double own = double(args.lam_next[uint64_t(opposite<Q>(a)) * g.N + n]);
+      const double arrived = double(args.lam_next[uint64_t(a) * g.N + t]);
+      atomicAdd(dLdphi + t, double(f[a]) * (own - arrived));
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Kinetic-energy loss and its seed: E = sum over fluid x of |j|^2 / (2 rho),
 // j = sum fbar e + F/2, on pre-collision populations (compute type).
 // dE/dfbar_a = u.e_a - |u|^2/2, dE/dF = u/2 (times the force scale).
@@ -1377,6 +1417,15 @@ hipError_t adjoint_impl(const AdjArgs<typename ST::R>& a, double* partials, int 
   return hipGetLastError();
 }
 
+template <int Q, class ST>
+hipError_t wall_sens_impl(const AdjArgs<typename ST::R>& a, double* dLdphi, hipStream_t st) {
+  if (a.mask)
+    hipLaunchKernelGGL((k_wall_sens<Q, ST, true>), dim3(aux_grid(a.g)), dim3(kBlock), 0, st, a, dLdphi);
+  else
+    hipLaunchKernelGGL((k_wall_sens<Q, ST, false>), dim3(aux_grid(a.g)), dim3(kBlock), 0, st, a, dLdphi);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 // Dispatch on (Q, precision).
@@ -1479,6 +1528,16 @@ hipError_t launch_adjoint(int q, int prec, const AdjArgs<double>& a64, const Adj
                  (adjoint_impl<15, StF32>(a32, partials, nblk, dLdomega, dLdF_uniform, st)),
                  (adjoint_impl<15, StF16>(a32, partials, nblk, dLdomega, dLdF_uniform, st)),
                  (adjoint_impl<15, StBF16>(a32, partials, nblk, dLdomega, dLdF_uniform, st)))
+}
+
+hipError_t launch_wall_sensitivity(int q, int prec, const AdjArgs<double>& a64, const AdjArgs<float>& a32,
+                                   double* dLdphi, hipStream_t st) {
+  if (q == 27) {
+    CMLBM_DISPATCH(prec, (wall_sens_impl<27, StF64>(a64, dLdphi, st)), (wall_sens_impl<27, StF32>(a32, dLdphi, st)),
+                   (wall_sens_impl<27, StF16>(a32, dLdphi, st)), (wall_sens_impl<27, StBF16>(a32, dLdphi, st)))
+  }
+  CMLBM_DISPATCH(prec, (wall_sens_impl<15, StF64>(a64, dLdphi, st)), (wall_sens_impl<15, StF32>(a32, dLdphi, st)),
+                 (wall_sens_impl<15, StF16>(a32, dLdphi, st)), (wall_sens_impl<15, StBF16>(a32, dLdphi, st)))
 }
 
 #undef CMLBM_DISPATCH

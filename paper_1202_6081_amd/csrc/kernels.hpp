@@ -84,6 +84,11 @@ hipError_t launch_init(int q, int prec, const Geom& g, const void* rho0, const v
 hipError_t launch_adjoint(int q, int prec, const AdjArgs<double>& a64, const AdjArgs<float>& a32, double* partials,
                           int nblk, double* dLdomega, double* dLdF_uniform, hipStream_t st);
 
+// Wall-layout sensitivity of one step (fpost, lam_next, mask, force, rates of
+// the AdjArgs; lam and dLdF unused): accumulates into dLdphi[N] (FP64).
+hipError_t launch_wall_sensitivity(int q, int prec, const AdjArgs<double>& a64, const AdjArgs<float>& a32,
+                                   double* dLdphi, hipStream_t st);
+
 hipError_t launch_ke_sum(int q, int prec, const Geom& g, const void* fpre, const uint8_t* mask,
                          const ForceArgs<double>& f64, const ForceArgs<float>& f32, double* partials, int nblk,
                          double* out, hipStream_t st);

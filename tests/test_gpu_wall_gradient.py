@@ -1,0 +1,125 @@
+"""GPU parity of the wall-layout gradient (through the C ABI) against complex-step
+derivatives of the FP64 oracle's wall-fraction step.
+
+The wall fraction phi(x) in [0, 1] blends plain streaming and half-way
+bounce-back, fbar_a(x) = (1 - phi(x)) fbar~_a(x - e_a) + phi(x - e_a)
+fbar~_abar(x) (oracle/lbm.py, stream_wall_fraction); with phi in {0, 1} it is the
+masked step.  cmlbm_wall_sensitivity accumulates dL/dphi at every fluid node,
+evaluated at the mask: one step's contribution against the oracle, and whole
+checkpointed runs (torch.autograd through ``autograd.run(..., wall=phi)``).
+"""
+import numpy as np
+import pytest
+import torch
+
+import lbm_inputs as inp
+from gpu_helpers import gpu_setup
+from oracle import lbm
+from oracle.lattice import LATTICES
+
+pytestmark = pytest.mark.gpu
+
+F64, F32 = 0, 1
+H = 1e-30
+
+
+def _walls(shape):
+    solid = np.zeros(shape, dtype=bool)
+    solid[0] = True
+    solid[shape[0] // 2, shape[1] // 2, shape[2] // 3] = True
+    solid[shape[0] // 2 + 1, 1:3, 5:9] = True
+    return solid
+
+
+def _fluid_direction(rng, solid):
+    v = rng.standard_normal(solid.shape)
+    v[solid] = 0.0
+    return v / np.linalg.norm(v)
+
+
+@pytest.mark.parametrize("q,per_mass", [(27, False), (27, True), (15, False)])
+def test_wall_sensitivity_one_step(q, per_mass):
+    # d/de <mu, step(fbar; phi + e v)> at phi = mask, for random mu and v on
+    # the fluid nodes, and at single fluid nodes next to a wall.
+    print(f"case wall-sens step q{q} per_mass={per_mass}", flush=True)
+    from paper_1202_6081_amd import cmlbm
+    lat = LATTICES[q]
+    shape = (6, 7, 67)
+    rng = np.random.default_rng(41)
+    om = list(rng.uniform(0.7, 1.9, q - 4))
+    F = inp.gaussian_force(shape, 1e-4, 5)
+    solid = _walls(shape)
+    phi = solid.astype(float)
+    sim = gpu_setup(q, shape, F64, om, F, solid, per_mass)
+    rho0 = 1 + 0.01 * rng.standard_normal(shape)
+    u0 = 0.05 * rng.uniform(-1, 1, (3,) + shape)
+    x, _ = sim.init_equilibrium(torch.from_numpy(rho0).cuda(), torch.from_numpy(u0).cuda())
+    x = sim.run(x, sim.populations(), 2)
+    f_pre = sim.gather(x).cpu().numpy()
+    mu = rng.standard_normal((q,) + shape)
+    mu[:, solid] = 0.0
+    g = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    cmlbm.cmlbm_wall_sensitivity(sim.h, x, torch.from_numpy(mu).cuda(), g)
+    g = g.cpu().numpy()
+    assert np.all(g[solid] == 0.0)
+
+    def L(p):
+        return np.sum(mu * lbm.step_wall_fraction(lat, f_pre.astype(complex), F.astype(complex), om, p, per_mass))
+
+    for k in range(2):
+        v = _fluid_direction(rng, solid)
+        ref = L(phi + 1j * H * v).imag / H
+        got = float(np.sum(g * v))
+        assert abs(got - ref) <= 1e-10 * abs(ref), (k, got, ref)
+    # single fluid nodes: beside the bottom wall, beside the obstacle, in the bulk
+    for z, y, xx in [(1, 3, 10), (shape[0] // 2, shape[1] // 2, shape[2] // 3 + 1), (4, 5, 50)]:
+        assert not solid[z, y, xx]
+        e = np.zeros(shape)
+        e[z, y, xx] = 1.0
+        ref = L(phi + 1j * H * e).imag / H
+        assert abs(g[z, y, xx] - ref) <= 1e-10 * abs(ref) + 1e-16, ((z, y, xx), g[z, y, xx], ref)
+
+
+def _oracle_loss(q, rho0, u0, F, om, nsteps, phi):
+    lat = LATTICES[q]
+    solid = np.asarray(phi) == 1
+    f = lbm.initial_state(lat, rho0, u0, F, solid)
+    for _ in range(nsteps):
+        f = lbm.step_wall_fraction(lat, f, F, om, phi)
+    return lbm.kinetic_energy(lat, f, F, solid)
+
+
+@pytest.mark.parametrize("q,prec,schedule", [(27, F64, {"every": 2}), (27, F64, {"snapshots": 1}),
+                                             (15, F64, {"every": 3}), (27, F32, {"every": 2})])
+def test_wall_gradient_of_a_run(q, prec, schedule):
+    # L = mean kinetic energy after N steps; dL/dphi of a whole checkpointed
+    # run against the oracle's complex step along a random fluid direction.
+    print(f"case wall-grad run q{q} p{prec} {schedule}", flush=True)
+    from paper_1202_6081_amd import autograd as ag
+    shape = (5, 6, 66)
+    nsteps = 5
+    rng = np.random.default_rng(43)
+    om = np.array(rng.uniform(0.8, 1.9, q - 4))
+    F = inp.gaussian_force(shape, 1e-4, 8)
+    solid = _walls(shape)
+    phi = solid.astype(float)
+    rho0 = 1 + 0.01 * rng.standard_normal(shape)
+    u0 = 0.05 * rng.uniform(-1, 1, (3,) + shape)
+    u0[:, solid] = 0.0
+    sim = gpu_setup(q, shape, prec, list(om))
+    real = torch.float64 if prec == F64 else torch.float32
+    Ft = torch.from_numpy(F).cuda().requires_grad_(True)
+    wt = torch.from_numpy(om.copy()).requires_grad_(True)
+    pt = torch.from_numpy(phi).cuda().requires_grad_(True)
+    out = ag.run(sim, torch.from_numpy(rho0).cuda().to(real), torch.from_numpy(u0).cuda().to(real), Ft, wt,
+                 nsteps, wall=pt, **schedule)
+    ag.kinetic_energy(sim, out, Ft).backward()
+    g = pt.grad.double().cpu().numpy()
+    assert np.all(g[solid] == 0.0)
+    for k in range(2):
+        v = _fluid_direction(rng, solid)
+        ref = _oracle_loss(q, rho0, u0, F, list(om), nsteps, phi + 1j * H * v).imag / H
+        got = float(np.sum(g * v))
+        tol = 1e-9 if prec == F64 else 1e-3   # FP32: the populations round to 2^-24 every step (measured 2.4e-4)
+        print(f"wall-grad q{q} p{prec}: dir {k}: {got:.10e} vs oracle {ref:.10e}", flush=True)
+        assert abs(got - ref) <= tol * abs(ref), (k, got, ref)
