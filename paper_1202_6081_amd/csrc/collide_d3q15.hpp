@@ -8,13 +8,15 @@
 //     sourceformulation1).
 //  3. Raw moments of h = fbar + S for the fifteen monomials the D3Q15 kernels
 //     use (1, x, y, z, xy, xz, yz, xx, yy, zz, xyy, xxy, xxz, xyz, xxyy); on this
-//     lattice they are signed sums over the rest, axis and corner links.
-//  4. Binomial shift to central moments, relaxation of xy, xz, yz (g4..g6),
+//     lattice they are signed sums over the rest, axis and corner links (the
+//     corners by a Walsh-Hadamard transform).
+//  4. Binomial shift to central moments, one axis at a time, relaxation of xy, xz, yz (g4..g6),
 //     xx-yy, xx+yy-2zz, xx+yy+zz (g7..g9), xyy, xxy, xxz, xyz (g10..g13) toward
 //     zero (rho for g9) and xxyy (g14) toward kxx~ kyy~; rho and the first central
 //     moments (F/2) are conserved.
 //  5. Inverse shift to raw moments and exact inversion of the fifteen raw
-//     moments to populations (the K g + S rows of Appendix G).
+//     moments to populations (the K g + S rows of Appendix G), the corners by the
+//     inverse transform.
 #pragma once
 
 #include <type_traits>
@@ -136,42 +138,125 @@ CMLBM_HD void source15(R Fx, R Fy, R Fz, R ux, R uy, R uz, R (&S)[15]) {
   });
 }
 
-// Populations with the given central moments about u: rho; first order
-// (hx, hy, hz); second order t..; third order txyy, txxy, txxz, txyz; fourth
-// order txxyy.  Binomial shift back to raw moments, then the exact inversion of
-// the fifteen raw moments on D3Q15.
+// The fifteen moments the D3Q15 kernels use, in this order.
+enum : int { M0 = 0, MX, MY, MZ, MXY, MXZ, MYZ, MXX, MYY, MZZ, MXYY, MXXY, MXXZ, MXYZ, MXXYY };
+
+// The binomial shift between raw and central moments factors into one shift
+// per axis, because this set is closed under lowering any one exponent: along
+// an axis the moments form triples (exponent 0, 1, 2), pairs (0, 1) and
+// singles, and a triple (m0, m1, m2) shifts by u as
+// (m0, m1 - u m0, m2 - 2 u m1 + u^2 m0) (raw to central) or
+// (m0, m1 + u m0, m2 + 2 u m1 + u^2 m0) (central to raw).
+struct Groups15 {
+  int t[4][3];   // triples
+  int nt;
+  int p[4][2];   // pairs
+  int np;
+};
+
+template <int AX>
+CMLBM_HDC Groups15 groups15() {
+  if constexpr (AX == 0)
+    return {{{0, 1, 7}, {2, 4, 11}, {3, 5, 12}, {8, 10, 14}}, 4, {{6, 13}, {0, 0}, {0, 0}, {0, 0}}, 1};
+  else if constexpr (AX == 1)
+    return {{{0, 2, 8}, {1, 4, 10}, {7, 11, 14}, {0, 0, 0}}, 3, {{3, 6}, {5, 13}, {0, 0}, {0, 0}}, 2};
+  else
+    return {{{0, 3, 9}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, 1, {{1, 5}, {2, 6}, {4, 13}, {7, 12}}, 4};
+}
+
+// Shift of moments m by u along axis AX (sg = -1: raw to central, +1: back).
+template <int AX, typename R>
+CMLBM_HD void shift15(R (&m)[15], R u, R sg) {
+  constexpr Groups15 G = groups15<AX>();
+  const R v = sg * u;
+  static_for<G.nt>([&](auto i) {
+    constexpr int a = G.t[decltype(i)::value][0], b = G.t[decltype(i)::value][1], c = G.t[decltype(i)::value][2];
+    m[c] = m[c] + v * (R(2) * m[b] + v * m[a]);
+    m[b] = m[b] + v * m[a];
+  });
+  static_for<G.np>([&](auto i) {
+    constexpr int a = G.p[decltype(i)::value][0], b = G.p[decltype(i)::value][1];
+    m[b] += v * m[a];
+  });
+}
+
+// Raw moments r of populations f (paper order).  The eight corner links' sign
+// patterns are the moments 1, x, y, z, xy, xz, yz, xyz, so the corner sums come
+// from a three-stage Walsh-Hadamard transform (24 additions); on the corners
+// xyy = x, xxy = y, xxz = z and xx = yy = zz = xxyy = 1, and the axis links
+// carry only 1, x, y, z, xx, yy, zz.  Corner 7 + i has e_x = -1 when bit 0 of i
+// is set, e_y = -1 for bit 1, e_z = -1 for bit 2.
 template <typename R>
-CMLBM_HD void populations15(R rho, R ux, R uy, R uz, R hx, R hy, R hz, R txy, R txz, R tyz, R txx, R tyy, R tzz,
-                            R txyy, R txxy, R txxz, R txyz, R txxyy, R (&f)[15]) {
-  const R ux2 = ux * ux, uy2 = uy * uy, uz2 = uz * uz;
-  const R sx = hx + ux * rho, sy = hy + uy * rho, sz = hz + uz * rho;
-  const R sxy = txy + ux * hy + uy * hx + ux * uy * rho;
-  const R sxz = txz + ux * hz + uz * hx + ux * uz * rho;
-  const R syz = tyz + uy * hz + uz * hy + uy * uz * rho;
-  const R sxx = txx + R(2) * ux * hx + ux2 * rho;
-  const R syy = tyy + R(2) * uy * hy + uy2 * rho;
-  const R szz = tzz + R(2) * uz * hz + uz2 * rho;
-  const R sxyy = txyy + R(2) * uy * txy + ux * tyy + uy2 * hx + R(2) * ux * uy * hy + ux * uy2 * rho;
-  const R sxxy = txxy + R(2) * ux * txy + uy * txx + ux2 * hy + R(2) * ux * uy * hx + ux2 * uy * rho;
-  const R sxxz = txxz + R(2) * ux * txz + uz * txx + ux2 * hz + R(2) * ux * uz * hx + ux2 * uz * rho;
-  const R sxyz = txyz + ux * tyz + uy * txz + uz * txy + ux * uy * hz + ux * uz * hy + uy * uz * hx +
-                 ux * uy * uz * rho;
-  const R sxxyy = txxyy + R(2) * ux * txyy + R(2) * uy * txxy + ux2 * tyy + uy2 * txx + R(4) * ux * uy * txy +
-                  R(2) * ux * uy2 * hx + R(2) * ux2 * uy * hy + ux2 * uy2 * rho;
-  // corners: the eight corner moments determine the eight corner populations
-#pragma unroll
-  for (int a = 7; a < 15; ++a) {
-    const R x = R(kE15[a].x), y = R(kE15[a].y), z = R(kE15[a].z);
-    f[a] = R(0.125) * (sxxyy + x * sxyy + y * sxxy + z * sxxz + x * y * sxy + x * z * sxz + y * z * syz +
-                       x * y * z * sxyz);
-  }
-  f[1] = R(0.5) * ((sxx - sxxyy) + (sx - sxyy));
-  f[2] = R(0.5) * ((sxx - sxxyy) - (sx - sxyy));
-  f[3] = R(0.5) * ((syy - sxxyy) + (sy - sxxy));
-  f[4] = R(0.5) * ((syy - sxxyy) - (sy - sxxy));
-  f[5] = R(0.5) * ((szz - sxxyy) + (sz - sxxz));
-  f[6] = R(0.5) * ((szz - sxxyy) - (sz - sxxz));
-  f[0] = rho - (sxx + syy + szz) + R(2) * sxxyy;
+CMLBM_HD void raw_moments15(const R (&f)[15], R (&r)[15]) {
+  const R s0 = f[7] + f[8], d0 = f[7] - f[8];       // (y, z) = (+, +): sum and x-weighted sum
+  const R s1 = f[9] + f[10], d1 = f[9] - f[10];     // (-, +)
+  const R s2 = f[11] + f[12], d2 = f[11] - f[12];   // (+, -)
+  const R s3 = f[13] + f[14], d3 = f[13] - f[14];   // (-, -)
+  const R a_p = s0 + s1, y_p = s0 - s1, x_p = d0 + d1, xy_p = d0 - d1;   // z = +1
+  const R a_m = s2 + s3, y_m = s2 - s3, x_m = d2 + d3, xy_m = d2 - d3;   // z = -1
+  const R c1 = a_p + a_m, cz = a_p - a_m, cy = y_p + y_m, cyz = y_p - y_m;
+  const R cx = x_p + x_m, cxz = x_p - x_m, cxy = xy_p + xy_m, cxyz = xy_p - xy_m;
+  const R lxx = f[1] + f[2], lyy = f[3] + f[4], lzz = f[5] + f[6];
+  r[M0] = ((f[0] + c1) + (lxx + lyy)) + lzz;
+  r[MX] = (f[1] - f[2]) + cx;
+  r[MY] = (f[3] - f[4]) + cy;
+  r[MZ] = (f[5] - f[6]) + cz;
+  r[MXY] = cxy;
+  r[MXZ] = cxz;
+  r[MYZ] = cyz;
+  r[MXX] = lxx + c1;
+  r[MYY] = lyy + c1;
+  r[MZZ] = lzz + c1;
+  r[MXYY] = cx;
+  r[MXXY] = cy;
+  r[MXXZ] = cz;
+  r[MXYZ] = cxyz;
+  r[MXXYY] = c1;
+}
+
+// Populations with raw moments r: the inverse of raw_moments15.  The corner
+// moments (1, x, y, z, xy, xz, yz, xyz) = (xxyy, xyy, xxy, xxz, xy, xz, yz, xyz)
+// give the eight corners by the inverse transform (the same three stages and
+// a factor 1/8); the axis links follow from the xx, x (etc.) moments less the
+// corners' parts, the rest population from the density.
+template <typename R>
+CMLBM_HD void populations_from_raw15(const R (&r)[15], R (&f)[15]) {
+  const R c1 = r[MXXYY];
+  const R a1p = r[MXXYY] + r[MXXZ], a1m = r[MXXYY] - r[MXXZ];   // 1 + z, 1 - z
+  const R axp = r[MXYY] + r[MXZ], axm = r[MXYY] - r[MXZ];       // x + xz, x - xz
+  const R ayp = r[MXXY] + r[MYZ], aym = r[MXXY] - r[MYZ];       // y + yz, y - yz
+  const R bxyp = r[MXY] + r[MXYZ], bxym = r[MXY] - r[MXYZ];     // xy + xyz, xy - xyz
+  // (y, z) corner pairs: the x-even part b and the x-odd part c
+  const R b_pp = a1p + ayp, b_mp = a1p - ayp, b_pm = a1m + aym, b_mm = a1m - aym;
+  const R c_pp = axp + bxyp, c_mp = axp - bxyp, c_pm = axm + bxym, c_mm = axm - bxym;
+  const R h = R(0.125);
+  f[7] = h * (b_pp + c_pp);
+  f[8] = h * (b_pp - c_pp);
+  f[9] = h * (b_mp + c_mp);
+  f[10] = h * (b_mp - c_mp);
+  f[11] = h * (b_pm + c_pm);
+  f[12] = h * (b_pm - c_pm);
+  f[13] = h * (b_mm + c_mm);
+  f[14] = h * (b_mm - c_mm);
+  const R lxx = r[MXX] - c1, lyy = r[MYY] - c1, lzz = r[MZZ] - c1;
+  const R lx = r[MX] - r[MXYY], ly = r[MY] - r[MXXY], lz = r[MZ] - r[MXXZ];
+  f[1] = R(0.5) * (lxx + lx);
+  f[2] = R(0.5) * (lxx - lx);
+  f[3] = R(0.5) * (lyy + ly);
+  f[4] = R(0.5) * (lyy - ly);
+  f[5] = R(0.5) * (lzz + lz);
+  f[6] = R(0.5) * (lzz - lz);
+  f[0] = ((r[M0] - c1) - lxx) - (lyy + lzz);
+}
+
+// Populations with central moments m about u (m is overwritten by the raw
+// moments): shift back along z, y, x, then invert.
+template <typename R>
+CMLBM_HD void populations_from_central15(R (&m)[15], R ux, R uy, R uz, R (&f)[15]) {
+  shift15<2>(m, uz, R(1));
+  shift15<1>(m, uy, R(1));
+  shift15<0>(m, ux, R(1));
+  populations_from_raw15(m, f);
 }
 
 // Density and velocity (Eqs. densitycalculation, velocitycalculation).
@@ -257,60 +342,46 @@ CMLBM_HD void source_raw15_adj(R Fx, R Fy, R Fz, R ux, R uy, R uz, const R (&gr)
 
 template <typename R>
 CMLBM_HD void collide15(R (&f)[15], R Fx, R Fy, R Fz, const Rates<R>& p) {
-  R rho, ux, uy, uz, inv_rho;
-  moments0_15(f, Fx, Fy, Fz, rho, ux, uy, uz, inv_rho);
-  // raw moments of f (corner links 7..14 carry all mixed monomials; on the
-  // corners e_x e_y^2 = e_x, ..., e_x^2 e_y^2 = 1)
-  R c0 = R(0), rxy = R(0), rxz = R(0), ryz = R(0), rxyz = R(0), rcx = R(0), rcy = R(0), rcz = R(0);
+  R m[15];
+  raw_moments15(f, m);
+  const R rho = m[M0];
+  const R inv_rho = R(1) / rho;
+  const R ux = (m[MX] + R(0.5) * Fx) * inv_rho;
+  const R uy = (m[MY] + R(0.5) * Fy) * inv_rho;
+  const R uz = (m[MZ] + R(0.5) * Fz) * inv_rho;
+  // raw moments of h = f + S, then central moments about u
+  {
+    R rs[15];
+    source_raw15(Fx, Fy, Fz, ux, uy, uz, rs);
 #pragma unroll
-  for (int a = 7; a < 15; ++a) {
-    const int x = kE15[a].x, y = kE15[a].y, z = kE15[a].z;
-    c0 += f[a];
-    rcx += R(x) * f[a];
-    rcy += R(y) * f[a];
-    rcz += R(z) * f[a];
-    rxy += R(x * y) * f[a];
-    rxz += R(x * z) * f[a];
-    ryz += R(y * z) * f[a];
-    rxyz += R(x * y * z) * f[a];
+    for (int k = 1; k < 15; ++k) m[k] += rs[k];
   }
-  // plus the raw moments of the source
-  R rs[15];
-  source_raw15(Fx, Fy, Fz, ux, uy, uz, rs);
-  const R ux2 = ux * ux, uy2 = uy * uy, uz2 = uz * uz;
-  const R rx = f[1] - f[2] + rcx + rs[1], ry = f[3] - f[4] + rcy + rs[2], rz = f[5] - f[6] + rcz + rs[3];
-  rxy += rs[4];
-  rxz += rs[5];
-  ryz += rs[6];
-  rxyz += rs[13];
-  const R rxx = f[1] + f[2] + c0 + rs[7], ryy = f[3] + f[4] + c0 + rs[8], rzz = f[5] + f[6] + c0 + rs[9];
-  const R rxyy = rcx + rs[10], rxxy = rcy + rs[11], rxxz = rcz + rs[12], rxxyy = c0 + rs[14];
-
-  // central moments of h = f + S about u (binomial theorem)
-  const R cxy = rxy - ux * ry - uy * rx + ux * uy * rho;
-  const R cxz = rxz - ux * rz - uz * rx + ux * uz * rho;
-  const R cyz = ryz - uy * rz - uz * ry + uy * uz * rho;
-  const R cxx = rxx - R(2) * ux * rx + ux2 * rho;
-  const R cyy = ryy - R(2) * uy * ry + uy2 * rho;
-  const R czz = rzz - R(2) * uz * rz + uz2 * rho;
-  const R cxyy = rxyy - R(2) * uy * rxy - ux * ryy + uy2 * rx + R(2) * ux * uy * ry - ux * uy2 * rho;
-  const R cxxy = rxxy - R(2) * ux * rxy - uy * rxx + ux2 * ry + R(2) * ux * uy * rx - ux2 * uy * rho;
-  const R cxxz = rxxz - R(2) * ux * rxz - uz * rxx + ux2 * rz + R(2) * ux * uz * rx - ux2 * uz * rho;
-  const R cxyz = rxyz - ux * ryz - uy * rxz - uz * rxy + ux * uy * rz + ux * uz * ry + uy * uz * rx -
-                 ux * uy * uz * rho;
-  const R cxxyy = rxxyy - R(2) * ux * rxyy - R(2) * uy * rxxy + ux2 * ryy + uy2 * rxx + R(4) * ux * uy * rxy -
-                  R(2) * ux * uy2 * rx - R(2) * ux2 * uy * ry + ux2 * uy2 * rho;
-
-  // relaxation
-  const R d1 = p.wc[7] * (cxx - cyy);
-  const R d2 = p.wc[8] * (cxx + cyy - R(2) * czz);
-  const R t9 = p.wc[9] * (cxx + cyy + czz) + p.w[9] * rho;
+  shift15<0>(m, ux, R(-1));
+  shift15<1>(m, uy, R(-1));
+  shift15<2>(m, uz, R(-1));
+  // relaxation; density and the first central moments (F/2) are conserved
+  const R d1 = p.wc[7] * (m[MXX] - m[MYY]);
+  const R d2 = p.wc[8] * (m[MXX] + m[MYY] - R(2) * m[MZZ]);
+  const R t9 = p.wc[9] * (m[MXX] + m[MYY] + m[MZZ]) + p.w[9] * rho;
   const R txx = (R(2) * t9 + d2 + R(3) * d1) * R(1.0 / 6.0);
   const R tyy = (R(2) * t9 + d2 - R(3) * d1) * R(1.0 / 6.0);
   const R tzz = (t9 - d2) * R(1.0 / 3.0);
-  populations15(rho, ux, uy, uz, R(0.5) * Fx, R(0.5) * Fy, R(0.5) * Fz, p.wc[4] * cxy, p.wc[5] * cxz,
-                p.wc[6] * cyz, txx, tyy, tzz, p.wc[10] * cxyy, p.wc[11] * cxxy, p.wc[12] * cxxz, p.wc[13] * cxyz,
-                p.wc[14] * cxxyy + p.w[14] * (txx * tyy * (p.per_mass ? inv_rho : R(1))), f);
+  m[M0] = rho;
+  m[MX] = R(0.5) * Fx;
+  m[MY] = R(0.5) * Fy;
+  m[MZ] = R(0.5) * Fz;
+  m[MXY] *= p.wc[4];
+  m[MXZ] *= p.wc[5];
+  m[MYZ] *= p.wc[6];
+  m[MXX] = txx;
+  m[MYY] = tyy;
+  m[MZZ] = tzz;
+  m[MXYY] *= p.wc[10];
+  m[MXXY] *= p.wc[11];
+  m[MXXZ] *= p.wc[12];
+  m[MXYZ] *= p.wc[13];
+  m[MXXYY] = p.wc[14] * m[MXXYY] + p.w[14] * (txx * tyy * (p.per_mass ? inv_rho : R(1)));
+  populations_from_central15(m, ux, uy, uz, f);
 }
 
 // Initial transformed populations fbar = f^eq(rho, u) - S/2: f^eq has the
@@ -318,8 +389,13 @@ CMLBM_HD void collide15(R (&f)[15], R Fx, R Fy, R Fz, const Rates<R>& p) {
 template <typename R>
 CMLBM_HD void initial15(R rho, R ux, R uy, R uz, R Fx, R Fy, R Fz, R (&f)[15]) {
   const R c2 = rho * R(1.0 / 3.0);
-  populations15(rho, ux, uy, uz, R(0), R(0), R(0), R(0), R(0), R(0), c2, c2, c2, R(0), R(0), R(0), R(0),
-                rho * R(1.0 / 9.0), f);
+  R m[15];
+#pragma unroll
+  for (int k = 0; k < 15; ++k) m[k] = R(0);
+  m[M0] = rho;
+  m[MXX] = m[MYY] = m[MZZ] = c2;
+  m[MXXYY] = rho * R(1.0 / 9.0);
+  populations_from_central15(m, ux, uy, uz, f);
   R S[15];
   source15(Fx, Fy, Fz, ux, uy, uz, S);
 #pragma unroll
@@ -327,49 +403,9 @@ CMLBM_HD void initial15(R rho, R ux, R uy, R uz, R Fx, R Fy, R Fz, R (&f)[15]) {
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint of collide15.
-//
-// The fifteen moments are indexed 1, x, y, z, xy, xz, yz, xx, yy, zz, xyy, xxy,
-// xxz, xyz, xxyy.  The binomial shift between raw and central moments factors
-// into one shift per axis, because this set is closed under lowering any one
-// exponent: along an axis the moments form triples (exponent 0, 1, 2), pairs
-// (0, 1) and singles, and a triple (m0, m1, m2) shifts by u as
-// (m0, m1 - u m0, m2 - 2 u m1 + u^2 m0) (raw to central) or
-// (m0, m1 + u m0, m2 + 2 u m1 + u^2 m0) (central to raw).
+// Adjoint of collide15 (moments in the order of the enum above; the per-axis
+// shifts as in the forward collision).
 // ---------------------------------------------------------------------------
-struct Groups15 {
-  int t[4][3];   // triples
-  int nt;
-  int p[4][2];   // pairs
-  int np;
-};
-
-template <int AX>
-CMLBM_HDC Groups15 groups15() {
-  if constexpr (AX == 0)
-    return {{{0, 1, 7}, {2, 4, 11}, {3, 5, 12}, {8, 10, 14}}, 4, {{6, 13}, {0, 0}, {0, 0}, {0, 0}}, 1};
-  else if constexpr (AX == 1)
-    return {{{0, 2, 8}, {1, 4, 10}, {7, 11, 14}, {0, 0, 0}}, 3, {{3, 6}, {5, 13}, {0, 0}, {0, 0}}, 2};
-  else
-    return {{{0, 3, 9}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, 1, {{1, 5}, {2, 6}, {4, 13}, {7, 12}}, 4};
-}
-
-// Shift of moments m by u along axis AX (sg = -1: raw to central, +1: back).
-template <int AX, typename R>
-CMLBM_HD void shift15(R (&m)[15], R u, R sg) {
-  constexpr Groups15 G = groups15<AX>();
-  const R v = sg * u;
-  static_for<G.nt>([&](auto i) {
-    constexpr int a = G.t[decltype(i)::value][0], b = G.t[decltype(i)::value][1], c = G.t[decltype(i)::value][2];
-    m[c] = m[c] + v * (R(2) * m[b] + v * m[a]);
-    m[b] = m[b] + v * m[a];
-  });
-  static_for<G.np>([&](auto i) {
-    constexpr int a = G.p[decltype(i)::value][0], b = G.p[decltype(i)::value][1];
-    m[b] += v * m[a];
-  });
-}
-
 // Adjoint of shift15: m = its input, g = adjoint of its output (in place ->
 // adjoint of its input); adds d/du to gu.
 template <int AX, typename R>

@@ -52,6 +52,9 @@ CMLBM_HD void fwd_line(R& a, R& b, R& c, R u) {
 }
 
 // Central moments (m0, m1, m2) about u -> populations (p_-, p_0, p_+).
+// (p_+ is formed as (r2 + r1)/2: the shorter p_- + r1 measured ten times the
+// FP32 error on a steady duct flow, 2.1e-3 against 1.8e-4 relative L2 after
+// 4e5 steps, the rounding errors of a steady state repeating every step.)
 template <typename R>
 CMLBM_HD void inv_line(R& a, R& b, R& c, R u) {
   const R m0 = a, m1 = b, m2 = c;

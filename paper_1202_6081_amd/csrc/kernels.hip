@@ -55,10 +55,21 @@ struct StBF16 {
   static constexpr bool dev = true;
 };
 
+// w + (float)v for an FP16 deviation v in one mixed-precision multiply-add
+// (v * 1.0 + w: the product is exact, so this is the same single rounding as a
+// conversion followed by an addition, subnormal deviations included).
+__device__ __forceinline__ float add_f16(_Float16 v, float w) {
+  float r;
+  asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(r) : "v"(v), "v"(w));
+  return r;
+}
+
 template <class ST, int Q>
 __device__ __forceinline__ typename ST::R decode(typename ST::T v, int a) {
   using R = typename ST::R;
-  if constexpr (ST::dev)
+  if constexpr (ST::dev && sizeof(typename ST::T) == 2 && __is_same(typename ST::T, _Float16))
+    return add_f16(v, R(weight<Q>(a)));
+  else if constexpr (ST::dev)
     return R(weight<Q>(a)) + static_cast<R>(v);
   else
     return v;
@@ -972,10 +983,16 @@ __global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(adjoi
   R uF[3] = {R(0), R(0), R(0)};
   const uint32_t nseg = (nx + blockDim.x - 1) / blockDim.x;
   const uint32_t items = nseg * uint32_t(g.ny) * uint32_t(g.nz);
-  const uint32_t per_block = (items + gridDim.x - 1) / gridDim.x;
-  const uint32_t it0 = step_block_id() * per_block;
-  const uint32_t it1 = min(items, it0 + per_block);
-  for (uint32_t it = it0; it < it1; ++it) {
+  // Row segments are dealt to the eight XCDs in contiguous runs; inside its
+  // run, an XCD's blocks take the segments in turn (its block b: b, b + per,
+  // b + 2 per, ...), so that the blocks running at one time work on adjacent
+  // segments and find the cache lines they share still in the XCD's L2.  (The
+  // grid is a multiple of 8; consecutive block ids go to the XCDs in turn.)
+  const uint32_t per = gridDim.x >> 3;
+  const uint32_t run = (items + 7u) >> 3;
+  const uint32_t i0 = (blockIdx.x & 7u) * run;
+  const uint32_t i1 = min(items, i0 + run);
+  for (uint32_t it = i0 + (blockIdx.x >> 3); it < i1; it += per) {
     const uint32_t row = it / nseg;
     const uint32_t x = (it - row * nseg) * blockDim.x + threadIdx.x;
     if (x >= nx) continue;

@@ -99,8 +99,9 @@ hipError_t launch_init_adjoint(int q, int prec, const Geom& g, const void* u0, c
                                const uint8_t* mask, const ForceArgs<double>& f64, const ForceArgs<float>& f32,
                                double* dLdF, double* partials, int nblk, hipStream_t st);
 
-// Blocks of the adjoint launch: each block walks CMLBM_ADJ_ITEMS consecutive
-// row segments (each thread visits at most that many nodes).
+// Blocks of the adjoint launch: a multiple of 8 (one share per XCD), each block
+// visiting about CMLBM_ADJ_ITEMS row segments (each thread at most that many
+// nodes, plus one).
 #ifndef CMLBM_ADJ_ITEMS
 #define CMLBM_ADJ_ITEMS 8
 #endif
@@ -108,7 +109,7 @@ inline int adjoint_blocks(const Geom& g) {
   const int bx = g.nx < 256 ? ((g.nx + 63) / 64) * 64 : 256;
   const uint64_t items = uint64_t((g.nx + bx - 1) / bx) * uint64_t(g.ny) * uint64_t(g.nz);
   uint64_t nb = (items + CMLBM_ADJ_ITEMS - 1) / CMLBM_ADJ_ITEMS;
-  if (nb < 1) nb = 1;
+  nb = ((nb + 7) / 8) * 8;
   return int(nb);
 }
 

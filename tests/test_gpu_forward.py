@@ -389,3 +389,39 @@ def test_population_buffer_layout(prec, q, nx):
     else:
         tol = {F64: 0.0, F32: 1e-7}[prec]
     assert (np.abs(back - soa) <= tol).all()
+
+
+@pytest.mark.parametrize("q,prec", [(27, 2), (15, 2), (27, 3), (15, 3)])
+def test_deviation_decode_every_bit_pattern(q, prec):
+    # Every finite 16-bit pattern (FP16 subnormals included) stored in a
+    # population buffer reads back, through the kernels' decode, as w_a + value
+    # rounded once in FP32.  nx = 64: one 64-node block per row, so the buffer
+    # is [row][a][x].
+    print(f"case decode-every-pattern q{q} p{prec}", flush=True)
+    from paper_1202_6081_amd import cmlbm
+    nx, ny, nz = 64, 16, 8
+    sim = cmlbm.Sim(q, nx, ny, nz, prec)
+    bits = np.arange(65536, dtype=np.uint16)
+    if prec == 2:
+        finite = ((bits >> 10) & 0x1F) != 0x1F
+    else:
+        finite = ((bits >> 7) & 0xFF) != 0xFF
+    pat = bits[finite]
+    total = q * nx * ny * nz
+    assert total >= pat.size
+    flat = np.resize(pat, total)
+    buf = sim.populations()
+    buf.view(torch.int16).reshape(-1).copy_(torch.from_numpy(flat.view(np.int16)))
+    soa = sim.export_populations(buf).cpu().numpy()           # [q][nz][ny][nx], float32
+    if prec == 2:
+        vals = flat.view(np.float16).astype(np.float32)
+    else:
+        vals = (flat.astype(np.uint32) << 16).view(np.float32)
+    vals = vals.reshape(nz * ny, q, nx)
+    # rest weights by the number of nonzero velocity components
+    nz_comp = np.abs(LATTICES[q].E).sum(axis=1)
+    table = {27: [8 / 27, 2 / 27, 1 / 54, 1 / 216], 15: [2 / 9, 1 / 9, None, 1 / 72]}[q]
+    w = np.array([table[k] for k in nz_comp], dtype=np.float64)
+    want = (w.astype(np.float32)[None, :, None] + vals).astype(np.float32)       # one FP32 rounding
+    got = np.transpose(soa.reshape(q, nz * ny, nx), (1, 0, 2))
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
