@@ -13,6 +13,12 @@ force loads), the FP64 CPU oracle timed on a bounded sample, the
 adjoint/forward time ratio of a 100-step checkpointed adjoint, and the
 per-launch step time of every lattice/storage variant on the same workload,
 two-buffer and in-place, and of the FP32 adjoint step of both lattices.
+
+Accuracy, measured in the same run: every variant's state after its timed
+steps against the FP64 variant's (velocity relative L2, kinetic energy), the
+FP16 deviations' subnormal fraction, and (`accuracy`) every variant and the
+FP64/FP32 adjoint on the CPU-baseline sample against the oracle's own result
+of that sample, which the CPU-baseline leg computes beside its timing.
 """
 import argparse
 import hashlib
@@ -75,42 +81,162 @@ def measured_traffic(n_nodes):
     return rec.get("hbm_bytes_per_dispatch")
 
 
-def cpu_baseline(seconds_target=12.0):
-    """The FP64 oracle on a bounded sample of the same workload: single steps of
-    a 40^3 D3Q27 box with the same rates and a Kolmogorov force."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(seconds_target=12.0, n=48, max_steps=48, adjoint_steps=8):
+    """The FP64 oracle on the host's cores, on a bounded sample of the same
+    workload: an n^3 D3Q27 periodic box from rest with the benchmark's rates
+    and Kolmogorov force F_x = 1e-6 sin(2 pi 4 y / n), stepped until about
+    `seconds_target` seconds have passed.  The oracle code is unchanged; its
+    per-node collisions are spread over a process pool (oracle/pool.py), one
+    worker per host CPU up to 16.
+
+    Also returns, untimed, the oracle references of the accuracy checks on the
+    same sample: the final D3Q27 state, the same number of D3Q15 steps, and the
+    complex-step derivative of the mean kinetic energy after `adjoint_steps`
+    steps along the unit direction of the force field itself."""
     import numpy as np
     from oracle import lbm
-    from oracle.lattice import D3Q27
+    from oracle.lattice import D3Q15, D3Q27
+    from oracle.pool import Pool
     import lbm_inputs as inp
-    n = 40
     F = inp.kolmogorov_force(n, waves=4)
-    om = [1.9] * 5 + [1.0] * 18
-    f = lbm.initial_state(D3Q27, np.ones((n, n, n)), np.zeros((3, n, n, n)), F)
-    t0 = time.perf_counter()
-    c0 = time.process_time()
-    steps = 0
-    while True:
-        f = lbm.step(D3Q27, f, F, om)
-        steps += 1
-        el = time.perf_counter() - t0
-        if el > seconds_target or steps >= 16:
-            break
-    cores = max(1, round((time.process_time() - c0) / el))     # threads the oracle actually kept busy
-    return {"value": n**3 * steps / el / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
-            "sample": f"{steps} step(s) of a {n}^3 D3Q27 periodic box, FP64 NumPy oracle, "
-                      f"Kolmogorov force, shear rate 1.9 ({el:.1f} s)"}
+    om27 = [1.9] * 5 + [1.0] * 18
+    om15 = [1.9] * 5 + [1.0] * 6
+    rho0, u0 = np.ones((n, n, n)), np.zeros((3, n, n, n))
+    with Pool() as pool:
+        f = lbm.initial_state(D3Q27, rho0, u0, F)
+        f = pool.step(D3Q27, f, F, om27)             # starts the workers (untimed)
+        t0 = time.perf_counter()
+        steps = 0
+        while True:
+            f = pool.step(D3Q27, f, F, om27)
+            steps += 1
+            el = time.perf_counter() - t0
+            if el > seconds_target or steps >= max_steps:
+                break
+        total = steps + 1
+        record = {"value": n**3 * steps / el / 1e6, "unit": "MLUPS", "cores": pool.workers, "kind": "oracle",
+                  "host_cpus": os.cpu_count(), "cpu_model": _cpu_model(),
+                  "sample": f"{steps} timed step(s) of a {n}^3 D3Q27 periodic box from rest, FP64 NumPy oracle, "
+                            f"collisions over {pool.workers} worker processes, Kolmogorov force, shear rate 1.9 "
+                            f"({el:.1f} s)"}
+        g = lbm.initial_state(D3Q15, rho0, u0, F)
+        g = pool.run(D3Q15, g, F, om15, total)
+        v = F / np.sqrt((F * F).sum())             # along the force itself: d L / d (force amplitude)
+        h = 1e-30
+        Fc = F + 1j * h * v
+        fc = pool.run(D3Q27, lbm.initial_state(D3Q27, rho0, u0, Fc), Fc, om27, adjoint_steps)
+        loss = lbm.kinetic_energy(D3Q27, fc, Fc)
+    ref = {"n": n, "steps": total, "F": F, "f27": f, "f15": g,
+           "u27": lbm.macroscopic_fields(D3Q27, f, F)[1], "u15": lbm.macroscopic_fields(D3Q15, g, F)[1],
+           "adjoint_steps": adjoint_steps, "direction": v, "loss": float(loss.real),
+           "dL_dF_dot_v": float(loss.imag / h)}
+    return record, ref
+
+
+def _rel_l2(a, b):
+    import numpy as np
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def accuracy_vs_oracle(ref):
+    """Every lattice/storage variant on the cpu_baseline sample against the
+    oracle's result of the same steps (velocity relative L2, largest population
+    error), and the FP64 and FP32 adjoint gradients along the sample's direction
+    against the oracle's complex step."""
+    import numpy as np
+    import torch
+    from paper_1202_6081_amd import autograd as ag
+    from paper_1202_6081_amd import cmlbm
+    n, steps, dev = ref["n"], ref["steps"], torch.device("cuda", 0)
+    out = {"sample": f"{n}^3 D3Q27/D3Q15 periodic box, the benchmark's recipe, {steps} steps from rest; "
+                     f"adjoint: {ref['adjoint_steps']} steps, loss = mean kinetic energy, derivative along the "
+                     "force field's own direction; FP32 gradient field also against the FP64 one (relative L2)",
+           "variants": []}
+    for q in (27, 15):
+        fo, uo = ref[f"f{q}"], ref[f"u{q}"]
+        for prec in (cmlbm.F64, cmlbm.F32, cmlbm.F32_F16DEV, cmlbm.F32_BF16DEV):
+            sim = cmlbm.Sim(q, n, n, n, prec)
+            sim.set_rates([1.9] * 5 + [1.0] * (q - 9))
+            sim.set_force(torch.from_numpy(ref["F"]).to(dev, sim.real))
+            a, _ = sim.init_equilibrium(torch.ones((n, n, n), device=dev, dtype=sim.real),
+                                        torch.zeros((3, n, n, n), device=dev, dtype=sim.real))
+            last = sim.run(a, sim.populations(), steps)
+            fg = sim.gather(last).double().cpu().numpy()
+            ug = sim.macroscopic(last)[1].double().cpu().numpy()
+            out["variants"].append({"lattice": f"D3Q{q}", "storage": cmlbm.PRECISION_NAMES[prec],
+                                    "u_rel_l2": _rel_l2(ug, uo),
+                                    "f_max_abs_err": float(np.abs(fg - fo).max())})
+            del sim, a, last
+    v = ref["direction"]
+    adj = {"oracle_dL_dF_dot_v": ref["dL_dF_dot_v"]}
+    grads = {}
+    for prec in (cmlbm.F64, cmlbm.F32):
+        sim = cmlbm.Sim(27, n, n, n, prec)
+        F = torch.from_numpy(ref["F"]).to(dev, sim.real).requires_grad_(True)
+        omega = torch.tensor([1.9] * 5 + [1.0] * 18, dtype=torch.float64, requires_grad=True)
+        rho0 = torch.ones((n, n, n), device=dev, dtype=sim.real)
+        u0 = torch.zeros((3, n, n, n), device=dev, dtype=sim.real)
+        pre = ag.run(sim, rho0, u0, F, omega, ref["adjoint_steps"], every=ref["adjoint_steps"])
+        ag.kinetic_energy(sim, pre, F).backward()
+        # F.grad: the run's adjoint plus the loss's own dependence on F (rho u includes F/2)
+        grads[prec] = F.grad.double().cpu().numpy()
+        d = float((grads[prec] * v).sum())
+        adj[f"{cmlbm.PRECISION_NAMES[prec]}_rel_err"] = abs(d / ref["dL_dF_dot_v"] - 1)
+        del sim, F, pre
+    adj["f32_grad_rel_l2_vs_f64"] = _rel_l2(grads[cmlbm.F32], grads[cmlbm.F64])
+    out["adjoint"] = adj
+    torch.cuda.empty_cache()
+    return out
+
+
+def _velocity_and_ke(sim, f_post):
+    """Velocity (FP64, on the device) and mean kinetic energy of the state
+    pulled from f_post, from the library's own read-out."""
+    rho, u = sim.macroscopic(f_post)
+    u = u.double()
+    ke = float((0.5 * rho.double() * (u * u).sum(dim=0)).mean())
+    del rho
+    return u, ke
+
+
+def _f16_exposure(buf):
+    """Fractions of the stored FP16 deviations that are subnormal (nonzero,
+    below 2^-14 = 6.1e-5 in magnitude) and that are zero."""
+    import torch
+    bits = buf.view(torch.int16).reshape(-1)
+    expo = (bits >> 10) & 0x1F
+    mant = bits & 0x3FF
+    sub = int(((expo == 0) & (mant != 0)).sum())
+    zero = int(((expo == 0) & (mant == 0)).sum())
+    return sub / bits.numel(), zero / bits.numel()
 
 
 def variant_sweep(n, steps=30, warmup=3):
     """Per-launch step time of every lattice and storage variant on the same
     512^3 workload (events around each launch on its stream), for the
-    two-buffer step and for the in-place step (mean of its two phases)."""
+    two-buffer step and for the in-place step (mean of its two phases).  Each
+    variant's state after its warmup + timed two-buffer steps is compared with
+    the FP64 variant's state after the same steps (velocity relative L2, mean
+    kinetic energy), and for FP16 deviation storage the stored values'
+    subnormal and zero fractions are counted."""
     import torch
     import lbm_inputs as inp
     from paper_1202_6081_amd import cmlbm
     dev = torch.device("cuda", 0)
     out = []
     for q in (27, 15):
+        u64 = ke64 = None
         for prec, name, tb in ((cmlbm.F64, "f64", 8), (cmlbm.F32, "f32", 4), (cmlbm.F32_F16DEV, "f16dev", 2),
                                (cmlbm.F32_BF16DEV, "bf16dev", 2)):
             sim = cmlbm.Sim(q, n, n, n, prec)
@@ -124,6 +250,18 @@ def variant_sweep(n, steps=30, warmup=3):
             for i in range(warmup):
                 sim.step(bufs[i & 1], bufs[(i + 1) & 1])
             ms = _launch_ms(lambda i: sim.step(bufs[(warmup + i) & 1], bufs[(warmup + i + 1) & 1]), steps)
+            last = bufs[(warmup + steps) & 1]
+            u, ke = _velocity_and_ke(sim, last)
+            acc = {"steps": warmup + steps, "ke": ke}
+            if prec == cmlbm.F64:
+                u64, ke64 = u, ke
+            else:
+                acc["u_rel_l2_vs_f64"] = float(torch.linalg.vector_norm(u - u64) / torch.linalg.vector_norm(u64))
+                acc["ke_rel_err_vs_f64"] = abs(ke / ke64 - 1)
+                del u
+            if prec == cmlbm.F32_F16DEV:
+                acc["f16_subnormal_frac"], acc["f16_zero_frac"] = _f16_exposure(last)
+            del last
             # the in-place (one-buffer) step from the same initial state
             sim.import_populations(pre, b)
             del pre
@@ -137,7 +275,7 @@ def variant_sweep(n, steps=30, warmup=3):
             gbs_in = bpn * n**3 / (ms_in * 1e-3) / 1e9
             out.append({"lattice": f"D3Q{q}", "storage": name, "ms": round(ms, 4),
                         "MLUPS": round(n**3 / (ms * 1e-3) / 1e6, 1), "bytes_per_node": bpn,
-                        "GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                        "GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4), "accuracy": acc,
                         "inplace": {"ms": round(ms_in, 4), "ms_collide_phase": round(ms_even, 4),
                                     "ms_scatter_phase": round(ms_odd, 4),
                                     "MLUPS": round(n**3 / (ms_in * 1e-3) / 1e6, 1),
@@ -145,6 +283,7 @@ def variant_sweep(n, steps=30, warmup=3):
                                     "state_GiB": round(q * tb * n**3 / 2**30, 2)}})
             del a, b, bufs, sim
             torch.cuda.empty_cache()
+        del u64
     return out
 
 
@@ -218,6 +357,9 @@ def main():
         sys.exit(2)
 
     ceiling = None if (args.no_ceiling or args.copy_calibration) else hbm_ceiling(args.n)
+    # the oracle's timing and references first, in worker processes of its own,
+    # before this process touches the device
+    cpu, ref = (None, None) if (args.no_cpu_baseline or args.copy_calibration) else cpu_baseline()
 
     import torch
     import lbm_inputs as inp
@@ -297,9 +439,11 @@ def main():
             "read_GBs": ceiling["read_GBs"], "write_GBs": ceiling["write_GBs"], "copy_GBs": ceiling["copy_GBs"],
             "kernel_over_ceiling": round(achieved / ceiling["step_traffic_pull_GBs"], 4),
             "adjoint_traffic_GBs": ceiling.get("adjoint_traffic_GBs"),
-            "probe": "paper_1202_6081_amd/hbm_probe: the step's loads and stores (27 pull loads, 3 force "
-                     "loads, 27 stores per node) and the adjoint's (384 B per node), no arithmetic, same "
-                     "layouts, one node per thread"},
+            "stream_flavours_GBs": ceiling.get("stream_flavours_GBs"),
+            "probe": "paper_1202_6081_amd/hbm_probe: plain read/write/copy streams over 4 GiB (best of 4/8/16 B "
+                     "per lane, plain/nontemporal/sc1 policies, one-pass or grid-stride), the step's loads and "
+                     "stores (27 pull loads, 3 force loads, 27 stores per node) and the adjoint's (384 B per "
+                     "node), no arithmetic, same layouts, one node per thread"},
     }
     del a, b, bufs, last
     torch.cuda.empty_cache()
@@ -320,8 +464,9 @@ def main():
     # the same workload stepped in place (one population buffer)
     result["inplace"] = None if args.no_variants else next(
         v["inplace"] for v in result["variants"] if v["lattice"] == "D3Q27" and v["storage"] == "f32")
-    if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline()
+    if cpu is not None:
+        result["cpu_baseline"] = cpu
+        result["accuracy"] = accuracy_vs_oracle(ref)
     print(json.dumps(result), flush=True)
 
 

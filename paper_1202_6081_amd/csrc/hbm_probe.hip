@@ -8,22 +8,23 @@
 // prints one JSON line.
 //
 //   hbm_probe [n]        n^3 nodes for the stencil probes (n a multiple of 256; default 512)
-//   hbm_probe placement  the step's traffic at 512^3 on buffers placed three ways (one
-//                        JSON line each): the process's first allocations, buffers carved
-//                        from one 150 GiB allocation, and new allocations made after all of
-//                        that memory was released
+//
+// The plain streams come in several flavours (4, 8 and 16 bytes per lane;
+// plain, nontemporal and system-coherent cache policies; one pass over the
+// buffer, each work-group moving one contiguous chunk, or a grid-stride loop
+// of 8192 work-groups); each stream's best flavour is the ceiling reported.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <string>
 
 namespace {
 
 constexpr int kQ = 27;
 constexpr int kBlock = 256;
-typedef float f4 __attribute__((ext_vector_type(4)));
 
 #define PROBE_CHECK(x)                                                                   \
   do {                                                                                   \
@@ -34,23 +35,61 @@ typedef float f4 __attribute__((ext_vector_type(4)));
     }                                                                                    \
   } while (0)
 
-__global__ __launch_bounds__(kBlock) void k_read(const f4* a, size_t n4, float* sink) {
-  float s = 0.f;
-  for (size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x; i < n4; i += size_t(gridDim.x) * kBlock) {
-    const f4 v = a[i];
-    s += (v.x + v.y) + (v.z + v.w);
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Cache-policy bits of gfx950 buffer instructions: 0 plain, 2 nontemporal,
+// 16 system coherent (sc1), 17 sc0 + sc1.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t chunk_rsrc(const char* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(base), (short)0, int(bytes), 0x00020000);
+}
+
+template <int W, int AUX>
+__device__ __forceinline__ void st_lane(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t v) {
+  if constexpr (W == 4)
+    __builtin_amdgcn_raw_buffer_store_b32(v, r, voff, 0, AUX);
+  else if constexpr (W == 8)
+    __builtin_amdgcn_raw_buffer_store_b64(u32x2{v, v}, r, voff, 0, AUX);
+  else
+    __builtin_amdgcn_raw_buffer_store_b128(u32x4{v, v, v, v}, r, voff, 0, AUX);
+}
+
+template <int W, int AUX>
+__device__ __forceinline__ uint32_t ld_lane(__amdgpu_buffer_rsrc_t r, uint32_t voff) {
+  if constexpr (W == 4) {
+    return __builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, AUX);
+  } else if constexpr (W == 8) {
+    const u32x2 t = __builtin_amdgcn_raw_buffer_load_b64(r, voff, 0, AUX);
+    return t.x ^ t.y;
+  } else {
+    const u32x4 t = __builtin_amdgcn_raw_buffer_load_b128(r, voff, 0, AUX);
+    return (t.x ^ t.y) ^ (t.z ^ t.w);
   }
-  if (s == -1.f) sink[0] = s;   // the buffer holds zeros: never taken, keeps the loads live
 }
 
-__global__ __launch_bounds__(kBlock) void k_write(f4* b, size_t n4) {
-  for (size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x; i < n4; i += size_t(gridDim.x) * kBlock)
-    __builtin_nontemporal_store(f4{0.f, 0.f, 0.f, 0.f}, &b[i]);
+// Plain streams over nchunks chunks of kBlock * W bytes; work-group g moves
+// chunks g, g + gridDim.x, ... (one pass when the grid has a work-group per
+// chunk).  The read stream's sink store is never taken (the buffer holds
+// zeros) but keeps the loads live.
+template <int W, int AUX>
+__global__ __launch_bounds__(kBlock) void k_read(const char* a, size_t nchunks, uint32_t* sink) {
+  uint32_t s = 0;
+  for (size_t c = blockIdx.x; c < nchunks; c += gridDim.x)
+    s ^= ld_lane<W, AUX>(chunk_rsrc(a + c * (kBlock * W), kBlock * W), threadIdx.x * W);
+  if (s == 0x5a5a5a5au) sink[0] = s;
 }
 
-__global__ __launch_bounds__(kBlock) void k_copy(const f4* a, f4* b, size_t n4) {
-  for (size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x; i < n4; i += size_t(gridDim.x) * kBlock)
-    __builtin_nontemporal_store(a[i], &b[i]);
+template <int W, int AUX>
+__global__ __launch_bounds__(kBlock) void k_write(char* b, size_t nchunks) {
+  for (size_t c = blockIdx.x; c < nchunks; c += gridDim.x)
+    st_lane<W, AUX>(chunk_rsrc(b + c * (kBlock * W), kBlock * W), threadIdx.x * W, uint32_t(c));
+}
+
+template <int W, int LAUX, int SAUX>
+__global__ __launch_bounds__(kBlock) void k_copy(const char* a, char* b, size_t nchunks) {
+  for (size_t c = blockIdx.x; c < nchunks; c += gridDim.x)
+    st_lane<W, SAUX>(chunk_rsrc(b + c * (kBlock * W), kBlock * W), threadIdx.x * W,
+                     ld_lane<W, LAUX>(chunk_rsrc(a + c * (kBlock * W), kBlock * W), threadIdx.x * W));
 }
 
 __device__ __forceinline__ uint32_t wrap(int v, uint32_t n) {
@@ -151,59 +190,9 @@ double time_ms(hipEvent_t e0, hipEvent_t e1, int reps, Launch launch) {
   return double(ms) / reps;
 }
 
-// The step's traffic at 512^3 (both directions between the two buffers) on
-// buffers placed three ways.  The same kernel, the same bytes: only where the
-// pages lie differs.
-int placement_study() {
-  const uint32_t n = 512;
-  const uint64_t N = uint64_t(n) * n * n;
-  const size_t pop = size_t(kQ) * N * sizeof(float), fb = size_t(3) * N * sizeof(float);
-  hipEvent_t e0, e1;
-  PROBE_CHECK(hipEventCreate(&e0));
-  PROBE_CHECK(hipEventCreate(&e1));
-  const dim3 grid(unsigned(N / kBlock)), block(kBlock);
-  auto run = [&](const char* name, float* fa, float* fb_, float* force) {
-    PROBE_CHECK(hipMemset(fa, 0, pop));
-    PROBE_CHECK(hipMemset(fb_, 0, pop));
-    PROBE_CHECK(hipMemset(force, 0, fb));
-    const double ab = time_ms(e0, e1, 20, [&] {
-      hipLaunchKernelGGL(k_stencil<true>, grid, block, 0, 0, fa, force, fb_, n, n, n);
-    });
-    const double ba = time_ms(e0, e1, 20, [&] {
-      hipLaunchKernelGGL(k_stencil<true>, grid, block, 0, 0, fb_, force, fa, n, n, n);
-    });
-    std::printf("{\"placement\": \"%s\", \"ms_a_to_b\": %.4f, \"ms_b_to_a\": %.4f, \"GBs\": %.1f}\n", name, ab,
-                ba, 228.0 * double(N) / (0.5 * (ab + ba) * 1e-3) / 1e9);
-    std::fflush(stdout);
-  };
-  float *a = nullptr, *b = nullptr, *f = nullptr;
-  PROBE_CHECK(hipMalloc(&a, pop));
-  PROBE_CHECK(hipMalloc(&b, pop));
-  PROBE_CHECK(hipMalloc(&f, fb));
-  run("first allocations", a, b, f);
-  const size_t big = size_t(150) << 30;   // room for the three buffers many times over
-  char* pool = nullptr;
-  PROBE_CHECK(hipMalloc(&pool, big));
-  run("carved from one 150 GiB allocation", reinterpret_cast<float*>(pool), reinterpret_cast<float*>(pool + pop),
-      reinterpret_cast<float*>(pool + 2 * pop));
-  PROBE_CHECK(hipFree(a));
-  PROBE_CHECK(hipFree(b));
-  PROBE_CHECK(hipFree(f));
-  PROBE_CHECK(hipFree(pool));
-  PROBE_CHECK(hipMalloc(&a, pop));
-  PROBE_CHECK(hipMalloc(&b, pop));
-  PROBE_CHECK(hipMalloc(&f, fb));
-  run("allocated after releasing the above", a, b, f);
-  PROBE_CHECK(hipFree(a));
-  PROBE_CHECK(hipFree(b));
-  PROBE_CHECK(hipFree(f));
-  return 0;
-}
-
 }  // namespace
 
 int main(int argc, char** argv) {
-  if (argc > 1 && std::strcmp(argv[1], "placement") == 0) return placement_study();
   const long n = argc > 1 ? std::atol(argv[1]) : 512;
   if (n < kBlock || n % kBlock != 0 || n > 1024) {
     std::fprintf(stderr, "hbm_probe: n must be a multiple of %d in [%d, 1024]\n", kBlock, kBlock);
@@ -213,11 +202,12 @@ int main(int argc, char** argv) {
   const uint64_t N = uint64_t(nx) * ny * nz;
   const size_t pop_bytes = size_t(kQ) * N * sizeof(float);
   const size_t force_bytes = size_t(3) * N * sizeof(float);
-  float *fin = nullptr, *fout = nullptr, *force = nullptr, *sink = nullptr;
+  float *fin = nullptr, *fout = nullptr, *force = nullptr;
+  uint32_t* sink = nullptr;
   PROBE_CHECK(hipMalloc(&fin, pop_bytes));
   PROBE_CHECK(hipMalloc(&fout, pop_bytes));
   PROBE_CHECK(hipMalloc(&force, force_bytes));
-  PROBE_CHECK(hipMalloc(&sink, sizeof(float)));
+  PROBE_CHECK(hipMalloc(&sink, sizeof(uint32_t)));
   PROBE_CHECK(hipMemset(fin, 0, pop_bytes));
   PROBE_CHECK(hipMemset(fout, 0, pop_bytes));
   PROBE_CHECK(hipMemset(force, 0, force_bytes));
@@ -225,15 +215,47 @@ int main(int argc, char** argv) {
   PROBE_CHECK(hipEventCreate(&e0));
   PROBE_CHECK(hipEventCreate(&e1));
 
-  // plain streams over the first 4 GiB (at most) of the population buffers
-  const size_t stream_bytes = (pop_bytes < (size_t(4) << 30) ? pop_bytes : (size_t(4) << 30)) & ~size_t(15);
-  const size_t n4 = stream_bytes / sizeof(f4);
-  const dim3 sgrid(8192), block(kBlock);
-  const auto* a4 = reinterpret_cast<const f4*>(fin);
-  auto* b4 = reinterpret_cast<f4*>(fout);
-  const double ms_read = time_ms(e0, e1, 20, [&] { hipLaunchKernelGGL(k_read, sgrid, block, 0, 0, a4, n4, sink); });
-  const double ms_write = time_ms(e0, e1, 20, [&] { hipLaunchKernelGGL(k_write, sgrid, block, 0, 0, b4, n4); });
-  const double ms_copy = time_ms(e0, e1, 20, [&] { hipLaunchKernelGGL(k_copy, sgrid, block, 0, 0, a4, b4, n4); });
+  // plain streams over the first 4 GiB (at most) of the population buffers,
+  // each in several flavours: "name" -> GB/s, and the best of each stream
+  const size_t stream_bytes = (pop_bytes < (size_t(4) << 30) ? pop_bytes : (size_t(4) << 30)) & ~size_t(4095);
+  const dim3 block(kBlock);
+  const char* ca = reinterpret_cast<const char*>(fin);
+  char* cb = reinterpret_cast<char*>(fout);
+  std::string flavours;
+  double best_read = 0, best_write = 0, best_copy = 0;
+  auto flavour = [&](const char* name, double bytes, double ms, double& best) {
+    const double g = bytes / (ms * 1e-3) / 1e9;
+    if (g > best) best = g;
+    char buf[96];
+    std::snprintf(buf, sizeof(buf), "%s\"%s\": %.1f", flavours.empty() ? "" : ", ", name, g);
+    flavours += buf;
+  };
+#define PROBE_STREAMS(W, ONEPASS, TAG)                                                                           \
+  {                                                                                                              \
+    const size_t nc = stream_bytes / (kBlock * W);                                                               \
+    const dim3 g(ONEPASS ? unsigned(nc) : 8192u);                                                                \
+    const double sb = double(stream_bytes);                                                                      \
+    flavour("read_" TAG "_plain", sb, time_ms(e0, e1, 10, [&] {                                                  \
+      hipLaunchKernelGGL((k_read<W, 0>), g, block, 0, 0, ca, nc, sink); }), best_read);                           \
+    flavour("read_" TAG "_nt", sb, time_ms(e0, e1, 10, [&] {                                                     \
+      hipLaunchKernelGGL((k_read<W, 2>), g, block, 0, 0, ca, nc, sink); }), best_read);                           \
+    flavour("write_" TAG "_plain", sb, time_ms(e0, e1, 10, [&] {                                                 \
+      hipLaunchKernelGGL((k_write<W, 0>), g, block, 0, 0, cb, nc); }), best_write);                               \
+    flavour("write_" TAG "_nt", sb, time_ms(e0, e1, 10, [&] {                                                    \
+      hipLaunchKernelGGL((k_write<W, 2>), g, block, 0, 0, cb, nc); }), best_write);                               \
+    flavour("write_" TAG "_sc1", sb, time_ms(e0, e1, 10, [&] {                                                   \
+      hipLaunchKernelGGL((k_write<W, 16>), g, block, 0, 0, cb, nc); }), best_write);                              \
+    flavour("copy_" TAG "_plain", 2 * sb, time_ms(e0, e1, 10, [&] {                                              \
+      hipLaunchKernelGGL((k_copy<W, 0, 0>), g, block, 0, 0, ca, cb, nc); }), best_copy);                          \
+    flavour("copy_" TAG "_nt", 2 * sb, time_ms(e0, e1, 10, [&] {                                                 \
+      hipLaunchKernelGGL((k_copy<W, 2, 2>), g, block, 0, 0, ca, cb, nc); }), best_copy);                          \
+  }
+  PROBE_STREAMS(4, false, "w4_stride")
+  PROBE_STREAMS(8, true, "w8_onepass")
+  PROBE_STREAMS(8, false, "w8_stride")
+  PROBE_STREAMS(16, true, "w16_onepass")
+  PROBE_STREAMS(16, false, "w16_stride")
+#undef PROBE_STREAMS
 
   // the step's traffic: 228 bytes per node
   const dim3 grid(unsigned(N / kBlock));
@@ -277,10 +299,9 @@ int main(int argc, char** argv) {
   std::printf(
       "{\"nodes\": %llu, \"read_GBs\": %.1f, \"write_GBs\": %.1f, \"copy_GBs\": %.1f, "
       "\"step_traffic_pull_ms\": %.4f, \"step_traffic_pull_GBs\": %.1f, "
-      "\"step_traffic_own_node_ms\": %.4f, \"step_traffic_own_node_GBs\": %.1f, %s}\n",
-      static_cast<unsigned long long>(N), gbs(double(stream_bytes), ms_read), gbs(double(stream_bytes), ms_write),
-      gbs(2.0 * double(stream_bytes), ms_copy), ms_pull, gbs(node_bytes * double(N), ms_pull), ms_own,
-      gbs(node_bytes * double(N), ms_own), adj_json);
+      "\"step_traffic_own_node_ms\": %.4f, \"step_traffic_own_node_GBs\": %.1f, %s, \"stream_flavours_GBs\": {%s}}\n",
+      static_cast<unsigned long long>(N), best_read, best_write, best_copy, ms_pull, gbs(node_bytes * double(N), ms_pull),
+      ms_own, gbs(node_bytes * double(N), ms_own), adj_json, flavours.c_str());
   PROBE_CHECK(hipFree(fin));
   PROBE_CHECK(hipFree(force));
   PROBE_CHECK(hipFree(sink));

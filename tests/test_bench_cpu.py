@@ -43,3 +43,17 @@ def test_traffic_record_tied_to_sources(tmp_path, monkeypatch):
     assert bench.measured_traffic(256**3) is None
     # algorithmic vs measured: within 1% for the step
     assert abs(rec["hbm_bytes_per_dispatch"] / (bench.BYTES_PER_NODE * n) - 1) < 0.01
+
+
+def test_cpu_baseline_reports_host_and_references():
+    # The oracle's timing leg on a tiny sample: the record names the worker
+    # count, the host's CPU count and model, and the untimed references of the
+    # accuracy checks have the sample's shapes.
+    import bench
+    rec, ref = bench.cpu_baseline(seconds_target=0.2, n=8, max_steps=2, adjoint_steps=2)
+    assert rec["kind"] == "oracle" and rec["unit"] == "MLUPS" and rec["value"] > 0
+    assert rec["cores"] == min(os.cpu_count(), 16) and rec["host_cpus"] == os.cpu_count()
+    assert "cpu_model" in rec and "worker processes" in rec["sample"]
+    assert ref["f27"].shape == (27, 8, 8, 8) and ref["f15"].shape == (15, 8, 8, 8)
+    assert ref["u27"].shape == (3, 8, 8, 8) and ref["steps"] >= 2
+    assert ref["dL_dF_dot_v"] != 0.0 and ref["loss"] > 0.0
