@@ -171,8 +171,9 @@ CMLBM_HD void shift15(R (&m)[15], R u, R sg) {
   const R v = sg * u;
   static_for<G.nt>([&](auto i) {
     constexpr int a = G.t[decltype(i)::value][0], b = G.t[decltype(i)::value][1], c = G.t[decltype(i)::value][2];
-    m[c] = m[c] + v * (R(2) * m[b] + v * m[a]);
-    m[b] = m[b] + v * m[a];
+    const R nb = m[b] + v * m[a];           // m2 + 2 v m1 + v^2 m0 = m2 + v (m1 + nb)
+    m[c] = m[c] + v * (m[b] + nb);
+    m[b] = nb;
   });
   static_for<G.np>([&](auto i) {
     constexpr int a = G.p[decltype(i)::value][0], b = G.p[decltype(i)::value][1];
@@ -272,7 +273,7 @@ CMLBM_HD void moments0_15(const R (&f)[15], R Fx, R Fy, R Fz, R& rho, R& ux, R& 
     cy += R(kE15[a].y) * f[a];
     cz += R(kE15[a].z) * f[a];
   }
-  const R inv = R(1) / rho;
+  const R inv = recip(rho);
   inv_rho = inv;
   ux = (f[1] - f[2] + cx + R(0.5) * Fx) * inv;
   uy = (f[3] - f[4] + cy + R(0.5) * Fy) * inv;
@@ -345,10 +346,11 @@ CMLBM_HD void collide15(R (&f)[15], R Fx, R Fy, R Fz, const Rates<R>& p) {
   R m[15];
   raw_moments15(f, m);
   const R rho = m[M0];
-  const R inv_rho = R(1) / rho;
-  const R ux = (m[MX] + R(0.5) * Fx) * inv_rho;
-  const R uy = (m[MY] + R(0.5) * Fy) * inv_rho;
-  const R uz = (m[MZ] + R(0.5) * Fz) * inv_rho;
+  const R inv_rho = recip(rho);
+  // (explicit fused multiply-adds, as in the D3Q27 collision)
+  const R ux = fma_r(R(0.5), Fx, m[MX]) * inv_rho;
+  const R uy = fma_r(R(0.5), Fy, m[MY]) * inv_rho;
+  const R uz = fma_r(R(0.5), Fz, m[MZ]) * inv_rho;
   // raw moments of h = f + S, then central moments about u
   {
     R rs[15];

@@ -55,14 +55,22 @@ CMLBM_HD void fwd_line(R& a, R& b, R& c, R u) {
 // (p_+ is formed as (r2 + r1)/2: the shorter p_- + r1 measured ten times the
 // FP32 error on a steady duct flow, 2.1e-3 against 1.8e-4 relative L2 after
 // 4e5 steps, the rounding errors of a steady state repeating every step.)
-template <typename R>
+// With HALVE = false, p_- and p_+ come out doubled (r2 -+ r1): the caller
+// applies the power-of-two factors of all passes at once (exact, so the
+// result is the same bit for bit).
+template <bool HALVE = true, typename R>
 CMLBM_HD void inv_line(R& a, R& b, R& c, R u) {
   const R m0 = a, m1 = b, m2 = c;
   const R r1 = m1 + u * m0;              // raw first moment
   const R r2 = m2 + u * (m1 + r1);       // raw second moment
-  a = R(0.5) * (r2 - r1);
+  if constexpr (HALVE) {
+    a = R(0.5) * (r2 - r1);
+    c = R(0.5) * (r2 + r1);
+  } else {
+    a = r2 - r1;
+    c = r2 + r1;
+  }
   b = m0 - r2;
-  c = R(0.5) * (r2 + r1);
 }
 
 // Adjoint of fwd_line: (a, b, c) are the forward inputs, (ga, gb, gc) hold
@@ -104,6 +112,27 @@ CMLBM_HD void inv_line_adj(R m0, R m1, R m2, R u, R& ga, R& gb, R& gc, R& gu) {
   gc = gm2;
 }
 
+// The forward transform of the step in two halves: raw moments first, one
+// axis at a time, (p_-, p_0, p_+) -> (sum, p_+ - p_-, p_+ + p_-) (3 operations
+// per line), then the binomial shift to central moments about u, one axis at a
+// time (the shifts along different axes act on different exponents and
+// commute).  Density and momentum are then the raw moments 000, 100, 010, 001.
+template <typename R>
+CMLBM_HD void raw_line(R& a, R& b, R& c) {
+  const R s2 = c + a, s1 = c - a;
+  a = s2 + b;
+  b = s1;
+  c = s2;
+}
+
+// Raw (r0, r1, r2) along an axis -> central (r0, r1 - u r0, r2 - 2 u r1 + u^2 r0).
+template <typename R>
+CMLBM_HD void shift_line(R a, R& b, R& c, R u) {
+  const R k1 = b - u * a;
+  c = c - u * (b + k1);
+  b = k1;
+}
+
 // Base index and stride of line l (0..8) along an axis (0 = x, 1 = y, 2 = z).
 template <int AXIS>
 CMLBM_HDC int line_base(int l) {
@@ -125,12 +154,32 @@ CMLBM_HD void fwd_pass(R (&m)[27], R u) {
 }
 
 template <int AXIS, typename R>
+CMLBM_HD void raw_pass(R (&m)[27]) {
+  constexpr int S = line_stride<AXIS>();
+#pragma unroll
+  for (int l = 0; l < 9; ++l) {
+    const int o = line_base<AXIS>(l);
+    raw_line(m[o], m[o + S], m[o + 2 * S]);
+  }
+}
+
+template <int AXIS, typename R>
+CMLBM_HD void shift_pass(R (&m)[27], R u) {
+  constexpr int S = line_stride<AXIS>();
+#pragma unroll
+  for (int l = 0; l < 9; ++l) {
+    const int o = line_base<AXIS>(l);
+    shift_line(m[o], m[o + S], m[o + 2 * S], u);
+  }
+}
+
+template <int AXIS, bool HALVE = true, typename R>
 CMLBM_HD void inv_pass(R (&m)[27], R u) {
   constexpr int S = line_stride<AXIS>();
 #pragma unroll
   for (int l = 0; l < 9; ++l) {
     const int o = line_base<AXIS>(l);
-    inv_line(m[o], m[o + S], m[o + 2 * S], u);
+    inv_line<HALVE>(m[o], m[o + S], m[o + 2 * S], u);
   }
 }
 
@@ -240,7 +289,7 @@ CMLBM_HD void first_pass27(R (&m)[27], R Fx, R Fy, R Fz, R& rho, R& ux, R& uy, R
   const R jx = (s0[6] + s0[7] + s0[8]) - (s0[0] + s0[1] + s0[2]);
   const R jy = (s0[2] + s0[5] + s0[8]) - (s0[0] + s0[3] + s0[6]);
   const R jz = ((s1[0] + s1[1] + s1[2]) + (s1[3] + s1[4] + s1[5])) + (s1[6] + s1[7] + s1[8]);
-  const R inv = R(1) / rho;
+  const R inv = recip(rho);
   inv_rho = inv;
   ux = (jx + R(0.5) * Fx) * inv;
   uy = (jy + R(0.5) * Fy) * inv;
@@ -259,14 +308,31 @@ CMLBM_HD void first_pass27(R (&m)[27], R Fx, R Fy, R Fz, R& rho, R& ux, R& uy, R
 // Full collision: cube-ordered pre-collision populations in, post-collision out.
 template <typename R>
 CMLBM_HD void collide27(R (&m)[27], R Fx, R Fy, R Fz, const Rates<R>& p) {
-  R rho, ux, uy, uz, inv_rho;
-  first_pass27(m, Fx, Fy, Fz, rho, ux, uy, uz, inv_rho);
-  fwd_pass<1>(m, uy);
-  fwd_pass<0>(m, ux);
+  raw_pass<2>(m);
+  raw_pass<1>(m);
+  raw_pass<0>(m);
+  const R rho = m[K3(0, 0, 0)];
+  const R inv_rho = recip(rho);
+  // (explicit fused multiply-adds: the rounding of u must not depend on what
+  // else the kernel computes from 0.5 F)
+  const R ux = fma_r(R(0.5), Fx, m[K3(1, 0, 0)]) * inv_rho;
+  const R uy = fma_r(R(0.5), Fy, m[K3(0, 1, 0)]) * inv_rho;
+  const R uz = fma_r(R(0.5), Fz, m[K3(0, 0, 1)]) * inv_rho;
+  shift_pass<0>(m, ux);
+  shift_pass<1>(m, uy);
+  shift_pass<2>(m, uz);
   relax27(m, rho, inv_rho, Fx, Fy, Fz, p);
-  inv_pass<0>(m, ux);
-  inv_pass<1>(m, uy);
-  inv_pass<2>(m, uz);
+  // the three inverse passes without their halvings, then population e scaled
+  // by 2^-(number of nonzero components of e) (one multiply each, which a
+  // 16-bit store fuses with its subtraction of the rest weight)
+  inv_pass<0, false>(m, ux);
+  inv_pass<1, false>(m, uy);
+  inv_pass<2, false>(m, uz);
+#pragma unroll
+  for (int i = 0; i < 27; ++i) {
+    const int k = (i / 9 != 1) + ((i / 3) % 3 != 1) + (i % 3 != 1);
+    if (k) m[i] *= R(k == 1 ? 0.5 : k == 2 ? 0.25 : 0.125);
+  }
 }
 
 // Adjoint of relax27.  m: pre-relaxation central moments (unchanged).  g: on

@@ -24,6 +24,7 @@
 
 #include <cstdint>
 #include <mutex>
+#include <type_traits>
 
 #include "collide_d3q15.hpp"
 #include "collide_d3q27.hpp"
@@ -55,21 +56,10 @@ struct StBF16 {
   static constexpr bool dev = true;
 };
 
-// w + (float)v for an FP16 deviation v in one mixed-precision multiply-add
-// (v * 1.0 + w: the product is exact, so this is the same single rounding as a
-// conversion followed by an addition, subnormal deviations included).
-__device__ __forceinline__ float add_f16(_Float16 v, float w) {
-  float r;
-  asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(r) : "v"(v), "v"(w));
-  return r;
-}
-
 template <class ST, int Q>
 __device__ __forceinline__ typename ST::R decode(typename ST::T v, int a) {
   using R = typename ST::R;
-  if constexpr (ST::dev && sizeof(typename ST::T) == 2 && __is_same(typename ST::T, _Float16))
-    return add_f16(v, R(weight<Q>(a)));
-  else if constexpr (ST::dev)
+  if constexpr (ST::dev)
     return R(weight<Q>(a)) + static_cast<R>(v);
   else
     return v;
@@ -82,6 +72,29 @@ __device__ __forceinline__ typename ST::T encode(typename ST::R v, int a) {
     return static_cast<typename ST::T>(v - R(weight<Q>(a)));
   else
     return v;
+}
+
+// All Q stored values of one node (the hot paths): as encode, with FP16
+// deviations converted two at a time by the packed conversion (the same
+// round-to-nearest-even of each FP32 value; measured as fast as or faster than
+// the mixed-precision multiply-add-and-round the compiler otherwise forms).
+template <class ST, int Q>
+__device__ __forceinline__ void encode_all(const typename ST::R (&f)[Q], typename ST::T (&v)[Q]) {
+  using R = typename ST::R;
+  if constexpr (ST::dev && __is_same(typename ST::T, _Float16)) {
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+    for (int a = 0; a + 1 < Q; a += 2) {
+      const f16x2 h = __builtin_convertvector((f32x2){f[a] - R(weight<Q>(a)), f[a + 1] - R(weight<Q>(a + 1))}, f16x2);
+      v[a] = h.x;
+      v[a + 1] = h.y;
+    }
+    if constexpr (Q & 1) v[Q - 1] = encode<ST, Q>(f[Q - 1], Q - 1);
+  } else {
+#pragma unroll
+    for (int a = 0; a < Q; ++a) v[a] = encode<ST, Q>(f[a], a);
+  }
 }
 
 // Element idx of an array whose byte size fits in 32 bits: a uniform base
@@ -98,6 +111,12 @@ __device__ __forceinline__ T ld32(const T* base, uint32_t idx) {
 struct Coord {
   int x, y, z;
 };
+
+// Node x of row `row` (row = z*ny + y).
+__device__ __forceinline__ Coord row_coord(const RowMap& rm, const Geom& g, uint32_t row, uint32_t x) {
+  const uint32_t z = rm.ny.div(row);
+  return {int(x), int(row - z * uint32_t(g.ny)), int(z)};
+}
 
 __device__ __forceinline__ Coord coord_of(const Geom& g, uint32_t n) {
   const uint32_t z = n / g.nxy;
@@ -174,19 +193,30 @@ __device__ __forceinline__ void pull(const typename ST::T* __restrict__ fin, con
       nlen[i] = min(64u, nx - bb) * sz;
     }
     const T* own = fin + uint64_t(row0) * rowQ;
+    // When every block of a row is full (nx a multiple of 64), the blocks of
+    // the x-neighbours have the same direction stride lenB, and that part of
+    // their offsets is wave-uniform too.
+    auto gather = [&](auto full) {
 #pragma unroll
-    for (int a = 0; a < Q; ++a) {
-      const Vel e = Lattice<Q>::e(a);
-      const T* rp = fin + uint64_t(st.row[e.y + 1][e.z + 1]) * rowQ;
-      T v;
-      if (MASK && mask[st.node(e, nx)])
-        v = ldb<T>(reinterpret_cast<const char*>(own) + uint32_t(opposite<Q>(a)) * lenB, cbase);
-      else if (e.x == 0)
-        v = ldb<T>(reinterpret_cast<const char*>(rp) + uint32_t(a) * lenB, cbase);
-      else
-        v = ldb<T>(rp, nbase[e.x + 1] + uint32_t(a) * nlen[e.x + 1]);
-      f[a] = decode<ST, Q>(v, a);
-    }
+      for (int a = 0; a < Q; ++a) {
+        const Vel e = Lattice<Q>::e(a);
+        const T* rp = fin + uint64_t(st.row[e.y + 1][e.z + 1]) * rowQ;
+        T v;
+        if (MASK && mask[st.node(e, nx)])
+          v = ldb<T>(reinterpret_cast<const char*>(own) + uint32_t(opposite<Q>(a)) * lenB, cbase);
+        else if (e.x == 0)
+          v = ldb<T>(reinterpret_cast<const char*>(rp) + uint32_t(a) * lenB, cbase);
+        else if constexpr (decltype(full)::value)
+          v = ldb<T>(reinterpret_cast<const char*>(rp) + uint32_t(a) * lenB, nbase[e.x + 1]);
+        else
+          v = ldb<T>(rp, nbase[e.x + 1] + uint32_t(a) * nlen[e.x + 1]);
+        f[a] = decode<ST, Q>(v, a);
+      }
+    };
+    if ((nx & 63u) == 0)
+      gather(std::true_type{});
+    else
+      gather(std::false_type{});
   } else {
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
@@ -337,7 +367,7 @@ template <int Q, class ST, bool MASK>
 __device__ __forceinline__ void load_node(const StepArgs<typename ST::R>& args, const Geom& g, uint32_t row,
                                           uint32_t x, typename ST::R (&f)[Q], typename ST::R& Fx,
                                           typename ST::R& Fy, typename ST::R& Fz) {
-  const Coord c{int(x), int(row % uint32_t(g.ny)), int(row / uint32_t(g.ny))};
+  const Coord c = row_coord(args.rm, g, row, x);
   const Stencil st(g, c, +1);
   pull<Q, ST, MASK, true>(static_cast<const typename ST::T*>(args.fin), g, args.mask, st, row, x, f);
   force_row(args, g, row, x, Fx, Fy, Fz);
@@ -356,8 +386,10 @@ __device__ __forceinline__ void store_node(const StepArgs<typename ST::R>& args,
   const uint32_t b0 = __builtin_amdgcn_readfirstlane(x & ~63u);
   const uint32_t lenB = min(64u, nx - b0) * sz;
   const uint32_t cbase = (b0 * uint32_t(Q) + (x - b0)) * sz;
+  T v[Q];
+  encode_all<ST, Q>(f, v);
 #pragma unroll
-  for (int a = 0; a < Q; ++a) buf_store(encode<ST, Q>(f[a], a), rs, cbase, uint32_t(a) * lenB);
+  for (int a = 0; a < Q; ++a) buf_store(v[a], rs, cbase, uint32_t(a) * lenB);
 }
 
 // With TOT, the step also writes its block's FP64 totals of the input state to
@@ -366,10 +398,9 @@ template <int Q, class ST, bool MASK, bool TOT>
 __global__ __launch_bounds__(CMLBM_STEP_BLOCK) void k_step(StepArgs<typename ST::R> args) {
   using R = typename ST::R;
   const Geom g = args.g;
-  const uint32_t nseg = (uint32_t(g.nx) + blockDim.x - 1) / blockDim.x;
   const uint32_t L = step_block_id();
-  const uint32_t row = L / nseg;                  // row = z * ny + y, uniform over the block
-  const uint32_t x = (L - row * nseg) * blockDim.x + threadIdx.x;
+  const uint32_t row = args.rm.seg.div(L);        // row = z * ny + y, uniform over the block
+  const uint32_t x = (L - row * args.rm.nseg) * blockDim.x + threadIdx.x;
   const bool active = x < uint32_t(g.nx) && !(MASK && args.mask[row * uint32_t(g.nx) + x]);
   double acc[4] = {0, 0, 0, 0};
   if constexpr (!TOT) {
@@ -424,10 +455,9 @@ __global__ __launch_bounds__(CMLBM_STEP_BLOCK) void k_step_inplace(StepArgs<type
   constexpr uint32_t sz = uint32_t(sizeof(T));
   const Geom g = args.g;
   const uint32_t nx = uint32_t(g.nx);
-  const uint32_t nseg = (nx + blockDim.x - 1) / blockDim.x;
   const uint32_t L = step_block_id();
-  const uint32_t row = L / nseg;                  // uniform over the block
-  const uint32_t x = (L - row * nseg) * blockDim.x + threadIdx.x;
+  const uint32_t row = args.rm.seg.div(L);        // uniform over the block
+  const uint32_t x = (L - row * args.rm.nseg) * blockDim.x + threadIdx.x;
   const bool active = x < nx && !(MASK && args.mask[row * nx + x]);
   double acc[4] = {0, 0, 0, 0};
   if constexpr (!TOT) {
@@ -449,10 +479,12 @@ __global__ __launch_bounds__(CMLBM_STEP_BLOCK) void k_step_inplace(StepArgs<type
       if constexpr (TOT) add_node_totals<Q>(f, Fx, Fy, Fz, acc);
       collide<Q>(f, Fx, Fy, Fz, args.rates);
       const __amdgpu_buffer_rsrc_t rs = array_rsrc(buf + uint64_t(row) * rowQ, rowQ * sz);
+      T v[Q];
+      encode_all<ST, Q>(f, v);
 #pragma unroll
-      for (int a = 0; a < Q; ++a) buf_store<kInplaceAux>(encode<ST, Q>(f[a], a), rs, cbase, uint32_t(opposite<Q>(a)) * lenB);
+      for (int a = 0; a < Q; ++a) buf_store<kInplaceAux>(v[a], rs, cbase, uint32_t(opposite<Q>(a)) * lenB);
     } else {
-      const Coord c{int(x), int(row % uint32_t(g.ny)), int(row / uint32_t(g.ny))};
+      const Coord c = row_coord(args.rm, g, row, x);
       const Stencil st(g, c, +1);      // row[ey+1][ez+1], xs[ex+1]: x - e; index with -e for x + e
       uint32_t nbase[3], nlen[3];      // blocked offsets of x - 1 ([2]) and x + 1 ([0]), and their block strides
 #pragma unroll
@@ -467,27 +499,36 @@ __global__ __launch_bounds__(CMLBM_STEP_BLOCK) void k_step_inplace(StepArgs<type
 #pragma unroll
         for (int a = 0; a < Q; ++a) solid |= uint32_t(args.mask[st.node(Lattice<Q>::e(a), nx)] != 0) << a;
       }
+      // (full rows: the x-neighbours' direction stride is lenB, as in pull)
+      const bool full = (nx & 63u) == 0;
+      auto gather = [&](auto fullrow) {
 #pragma unroll
-      for (int a = 0; a < Q; ++a) {
-        const Vel e = Lattice<Q>::e(a);
-        const char* rp = reinterpret_cast<const char*>(buf + uint64_t(st.row[e.y + 1][e.z + 1]) * rowQ);
-        const uint32_t ab = uint32_t(opposite<Q>(a));
-        T v;
-        if (MASK && ((solid >> a) & 1u))
-          v = ldb<T>(own + uint32_t(a) * lenB, cbase);
-        else if (e.x == 0)
-          v = ldb<T>(rp + ab * lenB, cbase);
-        else
-          v = ldb<T>(rp, nbase[e.x + 1] + ab * nlen[e.x + 1]);
-        f[a] = decode<ST, Q>(v, a);
-      }
+        for (int a = 0; a < Q; ++a) {
+          const Vel e = Lattice<Q>::e(a);
+          const char* rp = reinterpret_cast<const char*>(buf + uint64_t(st.row[e.y + 1][e.z + 1]) * rowQ);
+          const uint32_t ab = uint32_t(opposite<Q>(a));
+          T v;
+          if (MASK && ((solid >> a) & 1u))
+            v = ldb<T>(own + uint32_t(a) * lenB, cbase);
+          else if (e.x == 0)
+            v = ldb<T>(rp + ab * lenB, cbase);
+          else if constexpr (decltype(fullrow)::value)
+            v = ldb<T>(rp + ab * lenB, nbase[e.x + 1]);
+          else
+            v = ldb<T>(rp, nbase[e.x + 1] + ab * nlen[e.x + 1]);
+          f[a] = decode<ST, Q>(v, a);
+        }
+      };
+      if (full)
+        gather(std::true_type{});
+      else
+        gather(std::false_type{});
       R Fx, Fy, Fz;
       force_row(args, g, row, x, Fx, Fy, Fz);
       if constexpr (TOT) add_node_totals<Q>(f, Fx, Fy, Fz, acc);
       collide<Q>(f, Fx, Fy, Fz, args.rates);
       T v[Q];
-#pragma unroll
-      for (int a = 0; a < Q; ++a) v[a] = encode<ST, Q>(f[a], a);
+      encode_all<ST, Q>(f, v);
       if constexpr (MASK) {
         // Finish the collision before the per-lane store branches: otherwise the
         // compiler sinks its last operations into them, where multiplies and adds
@@ -496,21 +537,29 @@ __global__ __launch_bounds__(CMLBM_STEP_BLOCK) void k_step_inplace(StepArgs<type
 #pragma unroll
         for (int a = 0; a < Q; ++a) asm volatile("" : "+v"(v[a]));
       }
+      auto scatter = [&](auto fullrow) {
 #pragma unroll
-      for (int a = 0; a < Q; ++a) {
-        const Vel e = Lattice<Q>::e(a);
-        const int ab = opposite<Q>(a);
-        if (MASK && ((solid >> ab) & 1u)) {            // x + e_a = x - e_abar is solid
-          buf_store<kInplaceAux>(v[a], array_rsrc(buf + uint64_t(row) * rowQ, rowQ * sz), cbase, uint32_t(ab) * lenB);
-        } else {
-          const __amdgpu_buffer_rsrc_t rt =
-              array_rsrc(buf + uint64_t(st.row[1 - e.y][1 - e.z]) * rowQ, rowQ * sz);
-          if (e.x == 0)
-            buf_store<kInplaceAux>(v[a], rt, cbase, uint32_t(a) * lenB);
-          else
-            buf_store<kInplaceAux>(v[a], rt, nbase[1 - e.x] + uint32_t(a) * nlen[1 - e.x], 0u);
+        for (int a = 0; a < Q; ++a) {
+          const Vel e = Lattice<Q>::e(a);
+          const int ab = opposite<Q>(a);
+          if (MASK && ((solid >> ab) & 1u)) {            // x + e_a = x - e_abar is solid
+            buf_store<kInplaceAux>(v[a], array_rsrc(buf + uint64_t(row) * rowQ, rowQ * sz), cbase, uint32_t(ab) * lenB);
+          } else {
+            const __amdgpu_buffer_rsrc_t rt =
+                array_rsrc(buf + uint64_t(st.row[1 - e.y][1 - e.z]) * rowQ, rowQ * sz);
+            if (e.x == 0)
+              buf_store<kInplaceAux>(v[a], rt, cbase, uint32_t(a) * lenB);
+            else if constexpr (decltype(fullrow)::value)
+              buf_store<kInplaceAux>(v[a], rt, nbase[1 - e.x], uint32_t(a) * lenB);
+            else
+              buf_store<kInplaceAux>(v[a], rt, nbase[1 - e.x] + uint32_t(a) * nlen[1 - e.x], 0u);
+          }
         }
-      }
+      };
+      if (full)
+        scatter(std::true_type{});
+      else
+        scatter(std::false_type{});
     }
   }
   if constexpr (TOT) {
@@ -523,22 +572,48 @@ __global__ __launch_bounds__(CMLBM_STEP_BLOCK) void k_step_inplace(StepArgs<type
   }
 }
 
-// Value of `v` held by lane `src` of the wavefront (cross-lane permute; a
-// source outside 0..63 wraps, and the caller discards what it returns there).
-template <typename T>
-__device__ __forceinline__ T lane_value(T v, int src) {
-  const int addr = src << 2;
+// Whole-wavefront shifts by one lane (DPP wave_shr:1 / wave_shl:1): lane i
+// gets v from lane i - 1 (from_lane_below) or i + 1 (from_lane_above); the
+// lane with no source (0, resp. 63) gets `edge` instead.
+template <int CTRL, typename T>
+__device__ __forceinline__ T wave_shift(T v, T edge) {
   if constexpr (sizeof(T) == 8) {
-    const uint64_t u = __builtin_bit_cast(uint64_t, v);
-    const uint32_t lo = uint32_t(__builtin_amdgcn_ds_bpermute(addr, int(uint32_t(u))));
-    const uint32_t hi = uint32_t(__builtin_amdgcn_ds_bpermute(addr, int(uint32_t(u >> 32))));
+    const uint64_t u = __builtin_bit_cast(uint64_t, v), w = __builtin_bit_cast(uint64_t, edge);
+    const uint32_t lo = uint32_t(__builtin_amdgcn_update_dpp(int(uint32_t(w)), int(uint32_t(u)), CTRL, 0xF, 0xF, false));
+    const uint32_t hi =
+        uint32_t(__builtin_amdgcn_update_dpp(int(uint32_t(w >> 32)), int(uint32_t(u >> 32)), CTRL, 0xF, 0xF, false));
     return __builtin_bit_cast(T, (uint64_t(hi) << 32) | lo);
   } else if constexpr (sizeof(T) == 4) {
-    return __builtin_bit_cast(T, __builtin_amdgcn_ds_bpermute(addr, __builtin_bit_cast(int, v)));
+    return __builtin_bit_cast(
+        T, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, edge), __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
   } else {
-    const int r = __builtin_amdgcn_ds_bpermute(addr, int(__builtin_bit_cast(uint16_t, v)));
+    const int r = __builtin_amdgcn_update_dpp(int(__builtin_bit_cast(uint16_t, edge)), int(__builtin_bit_cast(uint16_t, v)),
+                                              CTRL, 0xF, 0xF, false);
     return __builtin_bit_cast(T, uint16_t(r));
   }
+}
+// Value of v in lane 63 (any lane may ask; EXEC does not matter).
+template <typename T>
+__device__ __forceinline__ T read_lane63(T v) {
+  if constexpr (sizeof(T) == 8) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(u)), 63));
+    const uint32_t hi = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(u >> 32)), 63));
+    return __builtin_bit_cast(T, (uint64_t(hi) << 32) | lo);
+  } else if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+  } else {
+    return __builtin_bit_cast(T, uint16_t(__builtin_amdgcn_readlane(int(__builtin_bit_cast(uint16_t, v)), 63)));
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T from_lane_below(T v, T edge) {
+  return wave_shift<0x138>(v, edge);
+}
+template <typename T>
+__device__ __forceinline__ T from_lane_above(T v, T edge) {
+  return wave_shift<0x130>(v, edge);
 }
 
 // Scatter phase of the in-place step on a lattice without walls, with aligned
@@ -561,10 +636,9 @@ __global__ __launch_bounds__(CMLBM_STEP_BLOCK) void k_scatter_periodic(StepArgs<
   __shared__ T edge_dn[kWaves][Q];   // lane 0 of each wavefront (e_x = -1 directions)
   const Geom g = args.g;
   const uint32_t nx = uint32_t(g.nx);
-  const uint32_t nseg = (nx + blockDim.x - 1) / blockDim.x;
   const uint32_t L = step_block_id();
-  const uint32_t row = L / nseg;                         // uniform over the block
-  const uint32_t x0 = (L - row * nseg) * blockDim.x;     // the block's row segment [x0, xend)
+  const uint32_t row = args.rm.seg.div(L);               // uniform over the block
+  const uint32_t x0 = (L - row * args.rm.nseg) * blockDim.x;   // the block's row segment [x0, xend)
   const uint32_t xend = min(x0 + blockDim.x, nx);
   const uint32_t x = x0 + threadIdx.x;
   const bool active = x < nx;
@@ -574,7 +648,7 @@ __global__ __launch_bounds__(CMLBM_STEP_BLOCK) void k_scatter_periodic(StepArgs<
   const uint32_t b0 = __builtin_amdgcn_readfirstlane(x & ~63u);
   const uint32_t lenB = (b0 < nx ? min(64u, nx - b0) : 64u) * sz;
   const uint32_t cbase = (b0 * uint32_t(Q) + (x - b0)) * sz;
-  const Coord c{int(active ? x : nx - 1), int(row % uint32_t(g.ny)), int(row / uint32_t(g.ny))};
+  const Coord c = row_coord(args.rm, g, row, active ? x : nx - 1);
   const Stencil st(g, c, +1);
   uint32_t nbase[3], nlen[3];
 #pragma unroll
@@ -590,54 +664,73 @@ __global__ __launch_bounds__(CMLBM_STEP_BLOCK) void k_scatter_periodic(StepArgs<
   double acc[4] = {0, 0, 0, 0};
   if (active) {
     R f[Q];
+    // (full rows: the x-neighbours' direction stride is lenB, as in pull)
+    auto gather = [&](auto fullrow) {
 #pragma unroll
-    for (int a = 0; a < Q; ++a) {
-      const Vel e = Lattice<Q>::e(a);
-      const char* rp = reinterpret_cast<const char*>(buf + uint64_t(st.row[e.y + 1][e.z + 1]) * rowQ);
-      const uint32_t ab = uint32_t(opposite<Q>(a));
-      f[a] = decode<ST, Q>(e.x == 0 ? ldb<T>(rp + ab * lenB, cbase) : ldb<T>(rp, nbase[e.x + 1] + ab * nlen[e.x + 1]),
-                           a);
-    }
+      for (int a = 0; a < Q; ++a) {
+        const Vel e = Lattice<Q>::e(a);
+        const char* rp = reinterpret_cast<const char*>(buf + uint64_t(st.row[e.y + 1][e.z + 1]) * rowQ);
+        const uint32_t ab = uint32_t(opposite<Q>(a));
+        T v;
+        if (e.x == 0)
+          v = ldb<T>(rp + ab * lenB, cbase);
+        else if constexpr (decltype(fullrow)::value)
+          v = ldb<T>(rp + ab * lenB, nbase[e.x + 1]);
+        else
+          v = ldb<T>(rp, nbase[e.x + 1] + ab * nlen[e.x + 1]);
+        f[a] = decode<ST, Q>(v, a);
+      }
+    };
+    if ((nx & 63u) == 0)
+      gather(std::true_type{});
+    else
+      gather(std::false_type{});
     R Fx, Fy, Fz;
     force_row(args, g, row, x, Fx, Fy, Fz);
     if constexpr (TOT) add_node_totals<Q>(f, Fx, Fy, Fz, acc);
     collide<Q>(f, Fx, Fy, Fz, args.rates);
-#pragma unroll
-    for (int a = 0; a < Q; ++a) v[a] = encode<ST, Q>(f[a], a);
+    encode_all<ST, Q>(f, v);
     // Finish the collision here, ahead of the barrier and the store branches
     // (same contraction as the two-buffer step; no instruction is emitted).
 #pragma unroll
     for (int a = 0; a < Q; ++a) asm volatile("" : "+v"(v[a]));
   }
-  if (lane == 63) {
-#pragma unroll
-    for (int a = 0; a < Q; ++a)
-      if (Lattice<Q>::e(a).x > 0) edge_up[wave][a] = v[a];
-  }
+  // One lane writes both edges (lane 63's values read across the wavefront).
   if (lane == 0) {
 #pragma unroll
-    for (int a = 0; a < Q; ++a)
+    for (int a = 0; a < Q; ++a) {
+      if (Lattice<Q>::e(a).x > 0) edge_up[wave][a] = read_lane63(v[a]);
       if (Lattice<Q>::e(a).x < 0) edge_dn[wave][a] = v[a];
+    }
   }
   __syncthreads();
-  if (active) {
+  // The stores are predicated without branches: a lane that has nothing to
+  // write at a slot gets the byte offset kDrop, past the row's bound, and the
+  // raw buffer store drops it.  The one node that writes across the segment's
+  // end (to x + 1 after the last node, x - 1 before the first) is the same for
+  // the whole block, so that target's offsets are wave-uniform.
+  constexpr uint32_t kDrop = 0x80000000u;
+  const uint32_t xn = xend == nx ? 0u : xend, xp = x0 == 0 ? nx - 1 : x0 - 1;   // periodic
+  const uint32_t bn = xn & ~63u, bp = xp & ~63u;
+  const uint32_t off_own = active ? cbase : kDrop;
+  const uint32_t off_prev = active && x > x0 ? cbase : kDrop;        // e_x = +1: from x - 1
+  const uint32_t off_next = active && x + 1 < xend ? cbase : kDrop;  // e_x = -1: from x + 1
+  const uint32_t off_after = x == xend - 1 ? (bn * uint32_t(Q) + (xn - bn)) * sz : kDrop;
+  const uint32_t off_before = x == x0 ? (bp * uint32_t(Q) + (xp - bp)) * sz : kDrop;
+  const uint32_t len_after = min(64u, nx - bn) * sz, len_before = min(64u, nx - bp) * sz;
+  const int wprev = wave > 0 ? wave - 1 : 0, wnext = wave + 1 < kWaves ? wave + 1 : wave;
 #pragma unroll
-    for (int a = 0; a < Q; ++a) {
-      const Vel e = Lattice<Q>::e(a);
-      const __amdgpu_buffer_rsrc_t rt = array_rsrc(buf + uint64_t(st.row[1 - e.y][1 - e.z]) * rowQ, rowQ * sz);
-      if (e.x == 0) {
-        buf_store<kInplaceAux>(v[a], rt, cbase, uint32_t(a) * lenB);
-      } else if (e.x > 0) {            // slot a of x receives fbar~_a(x - 1)
-        T s = lane_value(v[a], lane - 1);
-        if (lane == 0 && wave > 0) s = edge_up[wave - 1][a];
-        if (x > x0) buf_store<kInplaceAux>(s, rt, cbase, uint32_t(a) * lenB);
-        if (x == xend - 1) buf_store<kInplaceAux>(v[a], rt, nbase[0] + uint32_t(a) * nlen[0], 0u);   // to x + 1
-      } else {                         // slot a of x receives fbar~_a(x + 1)
-        T s = lane_value(v[a], lane + 1);
-        if (lane == 63 && x + 1 < xend) s = edge_dn[wave + 1][a];
-        if (x + 1 < xend) buf_store<kInplaceAux>(s, rt, cbase, uint32_t(a) * lenB);
-        if (x == x0) buf_store<kInplaceAux>(v[a], rt, nbase[2] + uint32_t(a) * nlen[2], 0u);          // to x - 1
-      }
+  for (int a = 0; a < Q; ++a) {
+    const Vel e = Lattice<Q>::e(a);
+    const __amdgpu_buffer_rsrc_t rt = array_rsrc(buf + uint64_t(st.row[1 - e.y][1 - e.z]) * rowQ, rowQ * sz);
+    if (e.x == 0) {
+      buf_store<kInplaceAux>(v[a], rt, off_own, uint32_t(a) * lenB);
+    } else if (e.x > 0) {              // slot a of x receives fbar~_a(x - 1)
+      buf_store<kInplaceAux>(from_lane_below(v[a], edge_up[wprev][a]), rt, off_prev, uint32_t(a) * lenB);
+      buf_store<kInplaceAux>(v[a], rt, off_after, uint32_t(a) * len_after);      // to x + 1
+    } else {                           // slot a of x receives fbar~_a(x + 1)
+      buf_store<kInplaceAux>(from_lane_above(v[a], edge_dn[wnext][a]), rt, off_next, uint32_t(a) * lenB);
+      buf_store<kInplaceAux>(v[a], rt, off_before, uint32_t(a) * len_before);    // to x - 1
     }
   }
   if constexpr (TOT) {
@@ -1289,10 +1382,17 @@ inline unsigned aux_grid(const Geom& g) {
   return unsigned(need < 8192 ? (need == 0 ? 1 : need) : 8192);
 }
 
+inline RowMap row_map(const Geom& g, int bx) {
+  const uint32_t nseg = uint32_t((g.nx + bx - 1) / bx);
+  return {nseg, Divider::of(nseg), Divider::of(uint32_t(g.ny))};
+}
+
 template <int Q, class ST>
-hipError_t step_impl(const StepArgs<typename ST::R>& a, hipStream_t st) {
-  const int bx = step_block(a.g);
-  const dim3 grid = step_grid(a.g, bx);
+hipError_t step_impl(const StepArgs<typename ST::R>& args, hipStream_t st) {
+  const int bx = step_block(args.g);
+  const dim3 grid = step_grid(args.g, bx);
+  StepArgs<typename ST::R> a = args;
+  a.rm = row_map(a.g, bx);
   if (!a.partials) {
     if (a.mask)
       hipLaunchKernelGGL((k_step<Q, ST, true, false>), grid, dim3(bx), 0, st, a);
@@ -1328,9 +1428,11 @@ void inplace_launch(const StepArgs<typename ST::R>& a, int parity, dim3 grid, in
 }
 
 template <int Q, class ST>
-hipError_t inplace_impl(const StepArgs<typename ST::R>& a, int parity, hipStream_t st) {
-  const int bx = step_block(a.g);
-  const dim3 grid = step_grid(a.g, bx);
+hipError_t inplace_impl(const StepArgs<typename ST::R>& args, int parity, hipStream_t st) {
+  const int bx = step_block(args.g);
+  const dim3 grid = step_grid(args.g, bx);
+  StepArgs<typename ST::R> a = args;
+  a.rm = row_map(a.g, bx);
   if (!a.partials) {
     inplace_launch<Q, ST, false>(a, parity, grid, bx, st);
     return hipGetLastError();
@@ -1410,9 +1512,10 @@ hipError_t init_impl(const Geom& g, const void* rho0, const void* u0, const Forc
 }
 
 template <int Q, class ST>
-hipError_t adjoint_impl(const AdjArgs<typename ST::R>& a, double* partials, int nblk, double* dLdomega,
+hipError_t adjoint_impl(const AdjArgs<typename ST::R>& args, double* partials, int nblk, double* dLdomega,
                         double* dLdF_uniform, hipStream_t st) {
-  const dim3 grid(nblk), block(adjoint_block(a.g));
+  const dim3 grid(nblk), block(adjoint_block(args.g));
+  const AdjArgs<typename ST::R>& a = args;
   if (a.rates.per_mass) {
     if (a.mask)
       hipLaunchKernelGGL((k_adjoint<Q, ST, true, 1>), grid, block, 0, st, a, partials);

@@ -15,6 +15,16 @@ struct Geom {
   uint64_t N;   // nodes
 };
 
+// The launch's map from a block's linear index to its row segment: rows
+// r = z*ny + y of nx nodes are cut into nseg segments of one block each, so
+// block L works on row L / nseg, segment L % nseg, and row r is (y, z) =
+// (r % ny, r / ny).  The dividers are set up on the host (Divider), which keeps
+// these divisions on the scalar unit.  Filled by the launchers.
+struct RowMap {
+  uint32_t nseg;
+  Divider seg, ny;
+};
+
 // Body force: a uniform vector (already multiplied by the time scale) or a
 // field [3][nz][ny][nx] times `scale`.
 template <typename FT>
@@ -38,6 +48,7 @@ struct StepArgs {
   double* partials;
   double* stage;
   double* totals;
+  RowMap rm;
 };
 
 template <typename R>

@@ -74,6 +74,43 @@ CMLBM_HDC double weight(int a) {
   return n == 0 ? 2.0 / 9 : n == 1 ? 1.0 / 9 : 1.0 / 72;
 }
 
+// Division of a 32-bit index n < 2^31 by a fixed d >= 1 without a divide:
+// with l = ceil(log2 d) and m = floor(2^(31+l) / d) + 1 (which fits 32 bits),
+// n / d = floor(n m / 2^(31+l)) for every n < 2^31 (Granlund and Montgomery,
+// 1994, Thm. 4.2), i.e. the high word of n m shifted right by l - 1.  d = 1 is
+// kept as m = 0.  For a wave-uniform n this is two scalar instructions.
+struct Divider {
+  uint32_t m, s;
+  static Divider of(uint32_t d) {
+    if (d <= 1) return {0u, 0u};
+    uint32_t l = 0;
+    while ((uint64_t(1) << l) < d) ++l;
+    return {uint32_t((uint64_t(1) << (31 + l)) / d + 1), l - 1};
+  }
+  CMLBM_HD uint32_t div(uint32_t n) const {
+    return m ? uint32_t((uint64_t(n) * m) >> 32) >> s : n;
+  }
+};
+
+// a * b + c with one rounding.
+CMLBM_HD float fma_r(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+CMLBM_HD double fma_r(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// 1/x.  In FP32 device code: the hardware reciprocal (within one ulp) refined
+// by one Newton step, r + r (1 - x r), which leaves it within an ulp of the
+// correctly rounded quotient in 3 instructions instead of the ~10 of an IEEE
+// division.  Elsewhere (FP64, and the CPU build of these headers) the division.
+template <typename R>
+CMLBM_HD R recip(R x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  if constexpr (sizeof(R) == 4) {
+    const float r = __builtin_amdgcn_rcpf(x);
+    return __builtin_fmaf(r, __builtin_fmaf(-x, r, 1.0f), r);
+  }
+#endif
+  return R(1) / x;
+}
+
 // D3Q27 directions as a 3x3x3 cube: index (e_x+1)*9 + (e_y+1)*3 + (e_z+1).
 CMLBM_HDC int cube27(int a) {
   return (kE27[a].x + 1) * 9 + (kE27[a].y + 1) * 3 + (kE27[a].z + 1);
