@@ -133,6 +133,36 @@ CMLBM_HD void shift_line(R a, R& b, R& c, R u) {
   b = k1;
 }
 
+// Inverse of shift_line: central (k0, k1, k2) about u -> raw (r0, r1, r2).
+template <typename R>
+CMLBM_HD void unshift_line(R a, R& b, R& c, R u) {
+  const R r1 = b + u * a;
+  c = c + u * (r1 + b);
+  b = r1;
+}
+
+// Adjoint of shift_line from its output (k0, k1): (g0, g1, g2) hold the
+// adjoints of (k0, k1, k2) on entry and of (r0, r1, r2) on exit; with
+// k1 = r1 - u r0 and k2 = r2 - u (r1 + k1), dk2/du = -2 k1 and dk1/du = -k0.
+template <typename R>
+CMLBM_HD void shift_line_adj(R k0, R k1, R u, R& g0, R& g1, R g2, R& gu) {
+  gu -= k0 * g1 + R(2) * k1 * g2;
+  const R t = g1 - u * g2;
+  g0 = g0 - u * t;
+  g1 = t - u * g2;
+}
+
+// Adjoint of raw_line (a linear map): (ga, gb, gc) hold the adjoints of
+// (sum, p_+ - p_-, p_+ + p_-) on entry and of (p_-, p_0, p_+) on exit.
+template <typename R>
+CMLBM_HD void raw_line_adj(R& ga, R& gb, R& gc) {
+  const R g0 = ga, g1 = gb, g2 = gc;
+  const R t = g0 + g2;
+  ga = t - g1;
+  gb = g0;
+  gc = t + g1;
+}
+
 // Base index and stride of line l (0..8) along an axis (0 = x, 1 = y, 2 = z).
 template <int AXIS>
 CMLBM_HDC int line_base(int l) {
@@ -170,6 +200,37 @@ CMLBM_HD void shift_pass(R (&m)[27], R u) {
   for (int l = 0; l < 9; ++l) {
     const int o = line_base<AXIS>(l);
     shift_line(m[o], m[o + S], m[o + 2 * S], u);
+  }
+}
+
+template <int AXIS, typename R>
+CMLBM_HD void unshift_pass(R (&m)[27], R u) {
+  constexpr int S = line_stride<AXIS>();
+#pragma unroll
+  for (int l = 0; l < 9; ++l) {
+    const int o = line_base<AXIS>(l);
+    unshift_line(m[o], m[o + S], m[o + 2 * S], u);
+  }
+}
+
+// m: the output of shift_pass<AXIS> (central moments along AXIS).
+template <int AXIS, typename R>
+CMLBM_HD void shift_pass_adj(const R (&m)[27], R u, R (&g)[27], R& gu) {
+  constexpr int S = line_stride<AXIS>();
+#pragma unroll
+  for (int l = 0; l < 9; ++l) {
+    const int o = line_base<AXIS>(l);
+    shift_line_adj(m[o], m[o + S], u, g[o], g[o + S], g[o + 2 * S], gu);
+  }
+}
+
+template <int AXIS, typename R>
+CMLBM_HD void raw_pass_adj(R (&g)[27]) {
+  constexpr int S = line_stride<AXIS>();
+#pragma unroll
+  for (int l = 0; l < 9; ++l) {
+    const int o = line_base<AXIS>(l);
+    raw_line_adj(g[o], g[o + S], g[o + 2 * S]);
   }
 }
 
@@ -450,19 +511,30 @@ CMLBM_HD void relax27_adj(const R (&m)[27], R rho, const Rates<R>& p, R (&g)[27]
 }
 
 // Adjoint of collide27.  f: cube-ordered pre-collision populations on entry;
-// on exit it holds their central moments (pre-relaxation).  g: on entry the
-// adjoint of the post-collision populations, on exit the adjoint of f.  s:
-// scratch.  Adds the force and rate adjoints.  Only the central moments c are
-// kept: the input of each forward pass is recovered from c by the inverse
-// passes, which undo the forward ones exactly (up to rounding).
+// on exit it holds scratch.  g: on entry the adjoint of the post-collision
+// populations, on exit the adjoint of f.  s: scratch.  Adds the force and rate
+// adjoints.  The forward transform is replayed as collide27 computes it (raw
+// sums, u, shifts) and only the central moments c are kept.  The inverse
+// passes are differentiated with their inputs recovered from the relaxed
+// moments; the shifts in reverse order from their outputs (each shift's
+// output is the next one's input, recovered by undoing the later shift); the
+// raw sums are linear and need no inputs; rho and u enter through the raw
+// moments 000, 100, 010, 001.
 template <int PM = -1, typename R, typename W>
 CMLBM_HD void collide27_adj(R (&f)[27], R Fx, R Fy, R Fz, const Rates<R>& p, R (&g)[27], R (&s)[27],
                                               R& gFx, R& gFy, R& gFz, W& gw) {
-  R rho, ux, uy, uz, inv_rho;
   R(&cm)[27] = f;
-  first_pass27(cm, Fx, Fy, Fz, rho, ux, uy, uz, inv_rho);
-  fwd_pass<1>(cm, uy);
-  fwd_pass<0>(cm, ux);
+  raw_pass<2>(cm);
+  raw_pass<1>(cm);
+  raw_pass<0>(cm);
+  const R rho = cm[K3(0, 0, 0)];
+  const R inv_rho = recip(rho);
+  const R ux = fma_r(R(0.5), Fx, cm[K3(1, 0, 0)]) * inv_rho;
+  const R uy = fma_r(R(0.5), Fy, cm[K3(0, 1, 0)]) * inv_rho;
+  const R uz = fma_r(R(0.5), Fz, cm[K3(0, 0, 1)]) * inv_rho;
+  shift_pass<0>(cm, ux);
+  shift_pass<1>(cm, uy);
+  shift_pass<2>(cm, uz);
   R gux = R(0), guy = R(0), guz = R(0), grho = R(0);
 
   // relaxed moments, then replay the inverse passes to get each pass's input
@@ -479,30 +551,26 @@ CMLBM_HD void collide27_adj(R (&f)[27], R Fx, R Fy, R Fz, const Rates<R>& p, R (
 
   relax27_adj<PM>(cm, rho, p, g, grho, gFx, gFy, gFz, gw);
 
-  // forward passes x, y, z in reverse order
-#pragma unroll
-  for (int k = 0; k < 27; ++k) s[k] = cm[k];
-  inv_pass<0>(s, ux);                        // s = input of the x forward pass
-  fwd_pass_adj<0>(s, ux, g, gux);
-  inv_pass<1>(s, uy);                        // s = input of the y forward pass
-  fwd_pass_adj<1>(s, uy, g, guy);
-  inv_pass<2>(s, uz);                        // s = f
-  fwd_pass_adj<2>(s, uz, g, guz);
+  // the shifts z, y, x in reverse; cm holds the output of the shift being
+  // differentiated
+  shift_pass_adj<2>(cm, uz, g, guz);
+  unshift_pass<2>(cm, uz);
+  shift_pass_adj<1>(cm, uy, g, guy);
+  unshift_pass<1>(cm, uy);
+  shift_pass_adj<0>(cm, ux, g, gux);
 
-  // u = (sum f e + F/2) / rho, rho = sum f
-  const R inv = inv_rho;
-  const R gjx = gux * inv, gjy = guy * inv, gjz = guz * inv;
-  grho -= (ux * gux + uy * guy + uz * guz) * inv;
+  // u = (j + F/2) / rho with j and rho the raw moments 100, 010, 001 and 000
+  const R gjx = gux * inv_rho, gjy = guy * inv_rho, gjz = guz * inv_rho;
+  g[K3(0, 0, 0)] += grho - (ux * gux + uy * guy + uz * guz) * inv_rho;
+  g[K3(1, 0, 0)] += gjx;
+  g[K3(0, 1, 0)] += gjy;
+  g[K3(0, 0, 1)] += gjz;
   gFx += R(0.5) * gjx;
   gFy += R(0.5) * gjy;
   gFz += R(0.5) * gjz;
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b)
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-        g[K3(a, b, c)] += grho + R(a - 1) * gjx + R(b - 1) * gjy + R(c - 1) * gjz;
+  raw_pass_adj<0>(g);
+  raw_pass_adj<1>(g);
+  raw_pass_adj<2>(g);
 }
 
 

@@ -1052,15 +1052,21 @@ struct LdsColumn {
 
 // Waves per SIMD the adjoint is compiled for: three 27-vectors and the line
 // transforms fit 168 VGPRs in FP32 (3 waves); FP64 needs twice the registers.
-template <class ST>
+#ifndef CMLBM_ADJ_WAVES_F32
+#define CMLBM_ADJ_WAVES_F32 3
+#endif
+#ifndef CMLBM_ADJ_WAVES_F64
+#define CMLBM_ADJ_WAVES_F64 1
+#endif
+template <class ST, bool MASK>
 constexpr int adjoint_waves() {
-  return sizeof(typename ST::R) == 8 ? 1 : 3;
+  return sizeof(typename ST::R) == 8 ? CMLBM_ADJ_WAVES_F64 : (MASK ? 3 : CMLBM_ADJ_WAVES_F32);
 }
 
 // PM: attractor form compiled in (0 literal, 1 per unit mass); the host picks
 // the instance that matches the rates' per_mass flag.
 template <int Q, class ST, bool MASK, int PM>
-__global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(adjoint_waves<ST>()))) void k_adjoint(
+__global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(adjoint_waves<ST, MASK>()))) void k_adjoint(
     AdjArgs<typename ST::R> args, double* partials) {
   using R = typename ST::R;
   using T = typename ST::T;

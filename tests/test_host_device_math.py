@@ -33,7 +33,9 @@ H = 1e-30   # complex step
 
 @pytest.fixture(scope="module")
 def lib():
-    if not os.path.exists(_b.HOST_LIB):
+    # (re)build when missing or older than the headers it compiles
+    srcs = [_b.HOST_SRC] + [os.path.join(_b.CSRC, n) for n in os.listdir(_b.CSRC) if n.endswith(".hpp")]
+    if not os.path.exists(_b.HOST_LIB) or os.path.getmtime(_b.HOST_LIB) < max(map(os.path.getmtime, srcs)):
         _b.build_host_math()
     L = ctypes.CDLL(_b.HOST_LIB)
     dp, fp, i, d = (ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_float), ctypes.c_int,
