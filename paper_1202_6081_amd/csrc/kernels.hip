@@ -97,6 +97,29 @@ __device__ __forceinline__ void encode_all(const typename ST::R (&f)[Q], typenam
   }
 }
 
+// Marks the encoded populations as computed here (an empty statement per
+// register: no instruction is emitted), so that the compiler does not sink the
+// end of the collision into later branches, where it would fuse its multiplies
+// and adds differently.  FP16 deviations are pinned in the pairs that the
+// packed conversion writes, so that they stay packed.
+template <class ST, int Q>
+__device__ __forceinline__ void pin_all(typename ST::T (&v)[Q]) {
+  using T = typename ST::T;
+  if constexpr (ST::dev && __is_same(T, _Float16)) {
+#pragma unroll
+    for (int a = 0; a + 1 < Q; a += 2) {
+      uint32_t p = uint32_t(__builtin_bit_cast(uint16_t, v[a])) | (uint32_t(__builtin_bit_cast(uint16_t, v[a + 1])) << 16);
+      asm volatile("" : "+v"(p));
+      v[a] = __builtin_bit_cast(T, uint16_t(p));
+      v[a + 1] = __builtin_bit_cast(T, uint16_t(p >> 16));
+    }
+    if constexpr (Q & 1) asm volatile("" : "+v"(v[Q - 1]));
+  } else {
+#pragma unroll
+    for (int a = 0; a < Q; ++a) asm volatile("" : "+v"(v[a]));
+  }
+}
+
 // Element idx of an array whose byte size fits in 32 bits: a uniform base
 // pointer plus a 32-bit byte offset, which maps onto the scalar-base form of
 // the global load instructions.
@@ -157,6 +180,28 @@ struct Stencil {
   }
 };
 
+// Raw buffer access: a resource over one row (base in SGPRs, size bound) plus a
+// 32-bit byte offset.  Stores past the bound are dropped by the hardware.
+// Word 3 = 0x00020000 is the raw-buffer descriptor of the gfx9 family.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t array_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, int(bytes), 0x00020000);
+}
+
+// Load through a buffer resource: base in scalar registers, 32-bit per-lane
+// and wave-uniform byte offsets, so that no 64-bit per-lane address is formed
+// (with plain pointers the compiler factors the per-lane offset out of a group
+// of loads and adds each uniform part back with a 64-bit vector add).
+template <typename T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+  } else if constexpr (sizeof(T) == 8) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  } else {
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
+  }
+}
+
 // Element of a byte offset from a uniform base (scalar-base load form).
 template <typename T>
 __device__ __forceinline__ T ldb(const void* base, uint32_t byte_off) {
@@ -172,8 +217,10 @@ __device__ __forceinline__ T ldb(const void* base, uint32_t byte_off) {
 // start and length of the node's own x are wave-uniform, and the byte offset
 // of direction a splits into a per-lane part and a scalar part a*len, folded
 // into the base pointer; only the x-neighbour directions keep a per-lane
-// multiply-add.
-template <int Q, class ST, bool MASK, bool WAVE = false>
+// multiply-add.  BUF: load through buffer resources over the source rows
+// (where the caller's register pressure makes the compiler rebuild 64-bit
+// per-lane addresses for the plain loads).
+template <int Q, class ST, bool MASK, bool WAVE = false, bool BUF = false>
 __device__ __forceinline__ void pull(const typename ST::T* __restrict__ fin, const Geom& g, const uint8_t* mask,
                                      const Stencil& st, uint32_t row0, uint32_t x, typename ST::R (&f)[Q]) {
   using T = typename ST::T;
@@ -202,14 +249,26 @@ __device__ __forceinline__ void pull(const typename ST::T* __restrict__ fin, con
         const Vel e = Lattice<Q>::e(a);
         const T* rp = fin + uint64_t(st.row[e.y + 1][e.z + 1]) * rowQ;
         T v;
-        if (MASK && mask[st.node(e, nx)])
-          v = ldb<T>(reinterpret_cast<const char*>(own) + uint32_t(opposite<Q>(a)) * lenB, cbase);
-        else if (e.x == 0)
-          v = ldb<T>(reinterpret_cast<const char*>(rp) + uint32_t(a) * lenB, cbase);
-        else if constexpr (decltype(full)::value)
-          v = ldb<T>(reinterpret_cast<const char*>(rp) + uint32_t(a) * lenB, nbase[e.x + 1]);
-        else
-          v = ldb<T>(rp, nbase[e.x + 1] + uint32_t(a) * nlen[e.x + 1]);
+        if constexpr (BUF) {
+          const uint32_t rowB = uint32_t(rowQ) * sz;
+          if (MASK && mask[st.node(e, nx)])
+            v = buf_load<T>(array_rsrc(own, rowB), cbase, uint32_t(opposite<Q>(a)) * lenB);
+          else if (e.x == 0)
+            v = buf_load<T>(array_rsrc(rp, rowB), cbase, uint32_t(a) * lenB);
+          else if constexpr (decltype(full)::value)
+            v = buf_load<T>(array_rsrc(rp, rowB), nbase[e.x + 1], uint32_t(a) * lenB);
+          else
+            v = buf_load<T>(array_rsrc(rp, rowB), nbase[e.x + 1] + uint32_t(a) * nlen[e.x + 1], 0u);
+        } else {
+          if (MASK && mask[st.node(e, nx)])
+            v = ldb<T>(reinterpret_cast<const char*>(own) + uint32_t(opposite<Q>(a)) * lenB, cbase);
+          else if (e.x == 0)
+            v = ldb<T>(reinterpret_cast<const char*>(rp) + uint32_t(a) * lenB, cbase);
+          else if constexpr (decltype(full)::value)
+            v = ldb<T>(reinterpret_cast<const char*>(rp) + uint32_t(a) * lenB, nbase[e.x + 1]);
+          else
+            v = ldb<T>(rp, nbase[e.x + 1] + uint32_t(a) * nlen[e.x + 1]);
+        }
         f[a] = decode<ST, Q>(v, a);
       }
     };
@@ -296,14 +355,7 @@ __device__ __forceinline__ uint32_t step_block_id() {
   return L;
 }
 
-// Raw buffer store: a resource over one row (base in SGPRs, size bound) plus a
-// 32-bit byte offset.  Stores past the bound are dropped by the hardware.
-// Word 3 = 0x00020000 is the raw-buffer descriptor of the gfx9 family.
 constexpr int kStoreAux = CMLBM_NT_STORE ? 2 : 0;   // 2: nontemporal (streaming) store
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t array_rsrc(void* base, uint32_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, int(bytes), 0x00020000);
-}
 
 // voff: per-lane byte offset; soff: wave-uniform byte offset; AUX: cache
 // policy bits (kStoreAux streams past the caches; 0 keeps the line).
@@ -469,7 +521,9 @@ __global__ __launch_bounds__(CMLBM_STEP_BLOCK) void k_step_inplace(StepArgs<type
     const uint32_t b0 = __builtin_amdgcn_readfirstlane(x & ~63u);
     const uint32_t lenB = min(64u, nx - b0) * sz;            // wave-uniform direction stride
     const uint32_t cbase = (b0 * uint32_t(Q) + (x - b0)) * sz;
+    // the node's own row (plain loads measured faster here than buffer loads)
     const char* own = reinterpret_cast<const char*>(buf + uint64_t(row) * rowQ);
+    const __amdgpu_buffer_rsrc_t rs = array_rsrc(own, rowQ * sz);
     R f[Q];
     if constexpr (!ODD) {
 #pragma unroll
@@ -478,7 +532,6 @@ __global__ __launch_bounds__(CMLBM_STEP_BLOCK) void k_step_inplace(StepArgs<type
       force_row(args, g, row, x, Fx, Fy, Fz);
       if constexpr (TOT) add_node_totals<Q>(f, Fx, Fy, Fz, acc);
       collide<Q>(f, Fx, Fy, Fz, args.rates);
-      const __amdgpu_buffer_rsrc_t rs = array_rsrc(buf + uint64_t(row) * rowQ, rowQ * sz);
       T v[Q];
       encode_all<ST, Q>(f, v);
 #pragma unroll
@@ -505,17 +558,17 @@ __global__ __launch_bounds__(CMLBM_STEP_BLOCK) void k_step_inplace(StepArgs<type
 #pragma unroll
         for (int a = 0; a < Q; ++a) {
           const Vel e = Lattice<Q>::e(a);
-          const char* rp = reinterpret_cast<const char*>(buf + uint64_t(st.row[e.y + 1][e.z + 1]) * rowQ);
+          const __amdgpu_buffer_rsrc_t rr = array_rsrc(buf + uint64_t(st.row[e.y + 1][e.z + 1]) * rowQ, rowQ * sz);
           const uint32_t ab = uint32_t(opposite<Q>(a));
           T v;
           if (MASK && ((solid >> a) & 1u))
-            v = ldb<T>(own + uint32_t(a) * lenB, cbase);
+            v = buf_load<T>(rs, cbase, uint32_t(a) * lenB);
           else if (e.x == 0)
-            v = ldb<T>(rp + ab * lenB, cbase);
+            v = buf_load<T>(rr, cbase, ab * lenB);
           else if constexpr (decltype(fullrow)::value)
-            v = ldb<T>(rp + ab * lenB, nbase[e.x + 1]);
+            v = buf_load<T>(rr, nbase[e.x + 1], ab * lenB);
           else
-            v = ldb<T>(rp, nbase[e.x + 1] + ab * nlen[e.x + 1]);
+            v = buf_load<T>(rr, nbase[e.x + 1] + ab * nlen[e.x + 1], 0u);
           f[a] = decode<ST, Q>(v, a);
         }
       };
@@ -529,21 +582,17 @@ __global__ __launch_bounds__(CMLBM_STEP_BLOCK) void k_step_inplace(StepArgs<type
       collide<Q>(f, Fx, Fy, Fz, args.rates);
       T v[Q];
       encode_all<ST, Q>(f, v);
-      if constexpr (MASK) {
-        // Finish the collision before the per-lane store branches: otherwise the
-        // compiler sinks its last operations into them, where multiplies and adds
-        // in different blocks are not fused, and the rounding departs from the
-        // two-buffer step's.  (Empty statements: no instruction is emitted.)
-#pragma unroll
-        for (int a = 0; a < Q; ++a) asm volatile("" : "+v"(v[a]));
-      }
+      // Finish the collision before the per-lane store branches: otherwise the
+      // compiler sinks its last operations into them, and the rounding departs
+      // from the two-buffer step's.
+      if constexpr (MASK) pin_all<ST, Q>(v);
       auto scatter = [&](auto fullrow) {
 #pragma unroll
         for (int a = 0; a < Q; ++a) {
           const Vel e = Lattice<Q>::e(a);
           const int ab = opposite<Q>(a);
           if (MASK && ((solid >> ab) & 1u)) {            // x + e_a = x - e_abar is solid
-            buf_store<kInplaceAux>(v[a], array_rsrc(buf + uint64_t(row) * rowQ, rowQ * sz), cbase, uint32_t(ab) * lenB);
+            buf_store<kInplaceAux>(v[a], rs, cbase, uint32_t(ab) * lenB);
           } else {
             const __amdgpu_buffer_rsrc_t rt =
                 array_rsrc(buf + uint64_t(st.row[1 - e.y][1 - e.z]) * rowQ, rowQ * sz);
@@ -669,15 +718,15 @@ __global__ __launch_bounds__(CMLBM_STEP_BLOCK) void k_scatter_periodic(StepArgs<
 #pragma unroll
       for (int a = 0; a < Q; ++a) {
         const Vel e = Lattice<Q>::e(a);
-        const char* rp = reinterpret_cast<const char*>(buf + uint64_t(st.row[e.y + 1][e.z + 1]) * rowQ);
+        const __amdgpu_buffer_rsrc_t rr = array_rsrc(buf + uint64_t(st.row[e.y + 1][e.z + 1]) * rowQ, rowQ * sz);
         const uint32_t ab = uint32_t(opposite<Q>(a));
         T v;
         if (e.x == 0)
-          v = ldb<T>(rp + ab * lenB, cbase);
+          v = buf_load<T>(rr, cbase, ab * lenB);
         else if constexpr (decltype(fullrow)::value)
-          v = ldb<T>(rp + ab * lenB, nbase[e.x + 1]);
+          v = buf_load<T>(rr, nbase[e.x + 1], ab * lenB);
         else
-          v = ldb<T>(rp, nbase[e.x + 1] + ab * nlen[e.x + 1]);
+          v = buf_load<T>(rr, nbase[e.x + 1] + ab * nlen[e.x + 1], 0u);
         f[a] = decode<ST, Q>(v, a);
       }
     };
@@ -690,10 +739,9 @@ __global__ __launch_bounds__(CMLBM_STEP_BLOCK) void k_scatter_periodic(StepArgs<
     if constexpr (TOT) add_node_totals<Q>(f, Fx, Fy, Fz, acc);
     collide<Q>(f, Fx, Fy, Fz, args.rates);
     encode_all<ST, Q>(f, v);
-    // Finish the collision here, ahead of the barrier and the store branches
-    // (same contraction as the two-buffer step; no instruction is emitted).
-#pragma unroll
-    for (int a = 0; a < Q; ++a) asm volatile("" : "+v"(v[a]));
+    // Finish the collision here, ahead of the barrier and the edge branch
+    // (same contraction as the two-buffer step).
+    pin_all<ST, Q>(v);
   }
   // One lane writes both edges (lane 63's values read across the wavefront).
   if (lane == 0) {
@@ -1032,6 +1080,7 @@ __device__ __forceinline__ void st32_out(T* base, uint32_t idx, T v) {
 }
 
 constexpr int kAdjBlock = 256;   // largest adjoint block (smaller for nx < 256)
+constexpr int kAdjAux = CMLBM_ADJ_NT ? 2 : 0;   // cache policy of the adjoint's stores (2: streaming)
 
 // Register slot of direction a in the adjoint's population vectors: cube
 // order for D3Q27 (the axis passes), the paper's order for D3Q15.
@@ -1061,6 +1110,16 @@ struct LdsColumn {
 template <class ST, bool MASK>
 constexpr int adjoint_waves() {
   return sizeof(typename ST::R) == 8 ? CMLBM_ADJ_WAVES_F64 : (MASK ? 3 : CMLBM_ADJ_WAVES_F32);
+}
+
+// The node count as a value the compiler must take as new at each use (an
+// empty statement: no instruction).  The adjoint addresses 2Q direction planes
+// of the [Q][N] adjoint arrays; hoisted out of its loop, their 64-bit bases
+// overflow the scalar registers and are spilled and reloaded on every pass.
+// Recomputed at the point of use they cost a few scalar instructions instead.
+__device__ __forceinline__ uint64_t per_item(uint64_t n) {
+  asm volatile("" : "+s"(n));
+  return n;
 }
 
 // PM: attractor form compiled in (0 literal, 1 per unit mass); the host picks
@@ -1095,6 +1154,7 @@ __global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(adjoi
     const uint32_t row = it / nseg;
     const uint32_t x = (it - row * nseg) * blockDim.x + threadIdx.x;
     if (x >= nx) continue;
+    const uint32_t rowB = nx * uint32_t(sizeof(R)), xB = x * uint32_t(sizeof(R));   // one row of a [Q][N] plane
     const Coord c{int(x), int(row % uint32_t(g.ny)), int(row / uint32_t(g.ny))};
     if (MASK && args.mask[row * nx + x]) continue;
     // forward pre-collision populations (D3Q27: in cube order)
@@ -1102,7 +1162,7 @@ __global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(adjoi
     {
       const Stencil st(g, c, +1);
       R fa[Q];
-      pull<Q, ST, MASK, true>(static_cast<const T*>(args.fpost), g, args.mask, st, row, x, fa);
+      pull<Q, ST, MASK, true, true>(static_cast<const T*>(args.fpost), g, args.mask, st, row, x, fa);
 #pragma unroll
       for (int a = 0; a < Q; ++a) f[slot<Q>(a)] = fa[a];
     }
@@ -1110,15 +1170,17 @@ __global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(adjoi
     R gm[Q];
     {
       const Stencil st(g, c, -1);
+      const uint64_t N = per_item(g.N);
 #pragma unroll
       for (int a = 0; a < Q; ++a) {
         const Vel e = Lattice<Q>::e(a);
         R v;
         if (MASK && args.mask[st.node(e, nx)])
-          v = ld32(args.lam_next + uint64_t(opposite<Q>(a)) * g.N + uint64_t(row) * nx, x);
+          v = buf_load<R>(array_rsrc(args.lam_next + uint64_t(opposite<Q>(a)) * N + uint64_t(row) * nx, rowB),
+                          xB, 0u);
         else
-          v = ld32(args.lam_next + uint64_t(a) * g.N + uint64_t(st.row[e.y + 1][e.z + 1]) * nx,
-                   st.xs[e.x + 1]);
+          v = buf_load<R>(array_rsrc(args.lam_next + uint64_t(a) * N + uint64_t(st.row[e.y + 1][e.z + 1]) * nx, rowB),
+                          st.xs[e.x + 1] * uint32_t(sizeof(R)), 0u);
         gm[slot<Q>(a)] = v;
       }
     }
@@ -1141,14 +1203,19 @@ __global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(adjoi
     } else {
       collide15_adj<PM>(f, Fx, Fy, Fz, args.rates, gm, gFx, gFy, gFz, wacc);
     }
+    const uint64_t N = per_item(g.N);
 #pragma unroll
-    for (int a = 0; a < Q; ++a) st32_out(args.lam + uint64_t(a) * g.N + uint64_t(row) * nx, x, gm[slot<Q>(a)]);
+    for (int a = 0; a < Q; ++a)
+      buf_store<kAdjAux>(gm[slot<Q>(a)], array_rsrc(args.lam + uint64_t(a) * N + uint64_t(row) * nx, rowB), xB, 0u);
     if (args.force.field) {
       const double sc = double(args.force.scale);
-      double* d = args.dLdF + uint64_t(row) * nx;
-      st32_out(d, x, ld32(d, x) + sc * double(gFx));
-      st32_out(d + g.N, x, ld32(d + g.N, x) + sc * double(gFy));
-      st32_out(d + 2 * g.N, x, ld32(d + 2 * g.N, x) + sc * double(gFz));
+      const uint32_t xD = x * uint32_t(sizeof(double));
+      const double gF[3] = {double(gFx), double(gFy), double(gFz)};
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const __amdgpu_buffer_rsrc_t rd = array_rsrc(args.dLdF + uint64_t(k) * N + uint64_t(row) * nx, nx * 8u);
+        buf_store<kAdjAux>(buf_load<double>(rd, xD, 0u) + sc * gF[k], rd, xD, 0u);
+      }
     } else {
       uF[0] += gFx;
       uF[1] += gFy;
