@@ -12,7 +12,9 @@ Prints ONE JSON line: MLUPS (whole job), the HBM roofline of the step kernel
 force loads), the FP64 CPU oracle timed on a bounded sample, the
 adjoint/forward time ratio of a 100-step checkpointed adjoint, and the
 per-launch step time of every lattice/storage variant on the same workload,
-two-buffer and in-place, and of the FP32 adjoint step of both lattices.
+two-buffer and in-place, of the FP32 adjoint step of both lattices, and
+(`walls`) of the step, the adjoint step and the wall-layout sensitivity of
+the same workload inside a square duct.
 
 Accuracy, measured in the same run: every variant's state after its timed
 steps against the FP64 variant's (velocity relative L2, kinetic energy), the
@@ -319,6 +321,48 @@ def adjoint_sweep(n, launches=6):
     return out
 
 
+def wall_sweep(n, launches=6):
+    """Per-call time of the masked FP32 D3Q27 step, adjoint step and wall-layout
+    sensitivity (gather form) on the 512^3 workload inside a square duct
+    (solid planes y, z in {0, n-1}, as in Sec. 9), with algorithmic bytes per
+    node over all n^3 nodes: step 228 and adjoint 384 as without walls; the
+    wall term 26 (4 + 4 + 4) + 16 = 328 (for each moving direction the
+    source's collided population and lambda_abar, the target's lambda_a;
+    FP64 dL/dphi read-modify-write)."""
+    import torch
+    import lbm_inputs as inp
+    from paper_1202_6081_amd import cmlbm
+    dev = torch.device("cuda", 0)
+    q = 27
+    sim = cmlbm.Sim(q, n, n, n, cmlbm.F32)
+    sim.set_rates([1.9] * 5 + [1.0] * (q - 9))
+    sim.set_force(torch.from_numpy(inp.kolmogorov_force(n, amplitude=1e-6, waves=4)).to(dev, torch.float32))
+    sim.set_mask(torch.from_numpy(inp.duct_mask(n, n, n)))
+    x, x1 = sim.populations(), sim.populations()
+    lam_a, lam_b = sim.real_populations(), sim.real_populations()
+    sim.init_equilibrium(torch.ones((n, n, n), device=dev), torch.zeros((3, n, n, n), device=dev),
+                         f_post=x, f_pre=lam_a)
+    sim.step(x, x1)
+    dLdF = torch.zeros((3, n, n, n), dtype=torch.float64, device=dev)
+    dLdw = torch.zeros(q - 4, dtype=torch.float64, device=dev)
+    dphi = torch.zeros((n, n, n), dtype=torch.float64, device=dev)
+    bufs, xs = [lam_a, lam_b], [x, x1]
+    out = {"workload": f"D3Q27 {n}^3 FP32, square duct along x (solid planes y, z in {{0, {n - 1}}}), "
+                       "Kolmogorov force field, shear rate 1.9"}
+    for name, bpn, launch in (
+            ("step", 228, lambda i: sim.step(xs[i & 1], xs[(i + 1) & 1])),
+            ("adjoint_step", 384, lambda i: sim.adjoint_step(x, bufs[i & 1], bufs[(i + 1) & 1], dLdF, dLdw)),
+            ("wall_sensitivity", 328, lambda i: sim.wall_sensitivity_post(x1, lam_a, dphi))):
+        launch(0)
+        ms = _launch_ms(launch, launches)
+        gbs = bpn * n**3 / (ms * 1e-3) / 1e9
+        out[name] = {"ms": round(ms, 4), "bytes_per_node": bpn, "GBs": round(gbs, 1),
+                     "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    del sim, x, x1, lam_a, lam_b, bufs, xs, dLdF, dphi
+    torch.cuda.empty_cache()
+    return out
+
+
 def _launch_ms(launch, count, per_launch=False):
     """Duration of each of `count` launches (event pair around each on the
     launch stream); their mean, or the list with per_launch."""
@@ -457,6 +501,7 @@ def main():
     torch.cuda.empty_cache()
     result["variants"] = None if args.no_variants else variant_sweep(n)
     result["adjoint_variants"] = None if args.no_variants else adjoint_sweep(n)
+    result["walls"] = None if args.no_variants else wall_sweep(n)
     hc = result["hbm_ceiling"]
     if hc is not None and hc["adjoint_traffic_GBs"] and result["adjoint_variants"]:
         adj27 = next(v for v in result["adjoint_variants"] if v["lattice"] == "D3Q27")

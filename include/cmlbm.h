@@ -295,6 +295,21 @@ cmlbm_status cmlbm_adjoint_step(cmlbm_sim *sim, const void *f_post_prev, const v
 cmlbm_status cmlbm_wall_sensitivity(cmlbm_sim *sim, const void *f_post_prev, const void *lam_next,
                                     double *dLdphi_dev, void *stream);
 
+/* The same contribution from the state the streaming moves: f_post = fbar~
+ * of the step as cmlbm_step wrote it (storage type, the buffer layout of
+ * cmlbm_step's output), lam = dL/dfbar of the pre-collision state that
+ * streaming f_post produces ("real" SoA populations; lam_next above).  Each
+ * fluid node t gathers its own terms
+ *   dL/dphi(t) += sum_a fbar~_a(t - e_a) (lam_abar(t - e_a) - lam_a(t))
+ * (fluid neighbours t - e_a) in a fixed order, so the result is deterministic;
+ * no collision is recomputed, and with 16-bit storage the terms use the
+ * rounded populations the forward run streamed.  Call it with lam = the
+ * output of the adjoint step whose f_post_prev is f_post, or with the
+ * incoming gradient for the last state of a run.  Uses the current mask.
+ * Errors: EINVAL (NULL, aliasing). */
+cmlbm_status cmlbm_wall_sensitivity_post(cmlbm_sim *sim, const void *f_post, const void *lam,
+                                         double *dLdphi_dev, void *stream);
+
 /* Kinetic-energy loss of a pre-collision state: *out = sum over fluid nodes of
  * |rho u|^2 / (2 rho), rho u = sum fbar e + F/2 (Eqs. densitycalculation,
  * velocitycalculation), accumulated in FP64.  f_pre: "real" [q][nz][ny][nx]

@@ -130,27 +130,28 @@ class _Sweep:
         self.recomputed = 0
         self.adjoint_steps = 0
 
-    def adjoint(self, x):
-        # the wall-layout term of this step's streaming needs lam(n+1), which
-        # the adjoint step is about to replace
-        if self.dLdphi is not None:
-            self.sim.wall_sensitivity(x, self.lam, self.dLdphi)
+    def adjoint(self, x, t):
+        """Adjoint of the step from x = x(t): lam(t+1) -> lam(t)."""
         self.sim.adjoint_step(x, self.lam, self.lam_tmp, self.dLdF, self.dLdw)
         self.lam, self.lam_tmp = self.lam_tmp, self.lam
         self.adjoint_steps += 1
+        # wall-layout term of the streaming that moved x(t) (the collided state
+        # of step t - 1) into fbar(t): x(t) and lam(t) are both at hand now
+        if self.dLdphi is not None and t > 0:
+            self.sim.wall_sensitivity_post(x, self.lam, self.dLdphi)
 
     def binomial(self, l, r, xl, s):
         n = r - l
         if n <= 0:
             return
         if n == 1:
-            self.adjoint(xl)
+            self.adjoint(xl, l)
             return
         if s == 0:
             for t in range(r - 1, l - 1, -1):
                 x = _advance(self.sim, self.pool, xl, t - l)
                 self.recomputed += t - l
-                self.adjoint(x)
+                self.adjoint(x, t)
                 if x is not xl:
                     self.pool.put(x)
             return
@@ -173,8 +174,8 @@ class _Sweep:
             self.recomputed += 1
             states.append(nxt)
             cur = nxt
-        for x in reversed(states):
-            self.adjoint(x)
+        for t in range(r - 1, l - 1, -1):
+            self.adjoint(states[t - l], t)
         for x in states[1:]:
             self.pool.put(x)
 
@@ -260,7 +261,10 @@ class _Run(torch.autograd.Function):
         stored, last = forward_sweep(sim, pool, x0, nsteps, keep_positions(nsteps, every, snapshots),
                                      keep_x0=nsteps == 0)
         sim.gather(last, out=pre)
-        if not any(last is v for v in stored.values()):
+        # with a wall fraction, x(N) is kept for the wall term of the last
+        # streaming (the one gather just did), taken with the incoming gradient
+        ctx.x_last = last if wall is not None and nsteps > 0 else None
+        if ctx.x_last is None and not any(last is v for v in stored.values()):
             pool.put(last)
         ctx.sim, ctx.pool, ctx.stored = sim, pool, stored
         ctx.rho0 = rho0r
@@ -292,6 +296,11 @@ class _Run(torch.autograd.Function):
         dLdF = torch.zeros(ctx.F_shape, dtype=torch.float64, device=sim.device)
         dLdw = torch.zeros(sim.q - 4, dtype=torch.float64, device=sim.device)
         sw = _Sweep(sim, pool, lam, lam_tmp, dLdF, dLdw, dLdphi)
+        if ctx.x_last is not None:
+            sim.wall_sensitivity_post(ctx.x_last, lam, dLdphi)
+            if not any(ctx.x_last is v for v in stored.values()):
+                pool.put(ctx.x_last)
+            ctx.x_last = None
 
         def rebuild_x0():
             # lam_tmp is free between adjoint steps: scratch for the pre-collision state

@@ -63,6 +63,7 @@ def load_library():
         "cmlbm_totals_pre": (i, [vp, vp, ctypes.POINTER(d), vp]),
         "cmlbm_adjoint_step": (i, [vp, vp, vp, vp, vp, vp, vp]),
         "cmlbm_wall_sensitivity": (i, [vp, vp, vp, vp, vp]),
+        "cmlbm_wall_sensitivity_post": (i, [vp, vp, vp, vp, vp]),
         "cmlbm_kinetic_energy_sum": (i, [vp, vp, ctypes.POINTER(d), vp]),
         "cmlbm_kinetic_energy_seed": (i, [vp, vp, d, vp, vp, vp]),
         "cmlbm_init_adjoint": (i, [vp, vp, vp, vp, vp]),
@@ -86,7 +87,8 @@ def exported_symbols():
             "cmlbm_export_populations", "cmlbm_import_populations", "cmlbm_macroscopic", "cmlbm_totals",
             "cmlbm_init_equilibrium_inplace", "cmlbm_step_inplace", "cmlbm_step_inplace_totals",
             "cmlbm_run_inplace", "cmlbm_macroscopic_pre", "cmlbm_totals_pre",
-            "cmlbm_adjoint_step", "cmlbm_wall_sensitivity", "cmlbm_kinetic_energy_sum", "cmlbm_kinetic_energy_seed",
+            "cmlbm_adjoint_step", "cmlbm_wall_sensitivity", "cmlbm_wall_sensitivity_post",
+            "cmlbm_kinetic_energy_sum", "cmlbm_kinetic_energy_seed",
             "cmlbm_init_adjoint",
             "cmlbm_status_string", "cmlbm_last_error", "cmlbm_version"]
 
@@ -258,6 +260,10 @@ def cmlbm_adjoint_step(h, f_post_prev, lam_next, lam, dLdF, dLdomega, stream=Non
 def cmlbm_wall_sensitivity(h, f_post_prev, lam_next, dLdphi, stream=None):
     _check(load_library().cmlbm_wall_sensitivity(h, _ptr(f_post_prev), _ptr(lam_next), _ptr(dLdphi),
                                                   _stream(stream)), h)
+
+
+def cmlbm_wall_sensitivity_post(h, f_post, lam, dLdphi, stream=None):
+    _check(load_library().cmlbm_wall_sensitivity_post(h, _ptr(f_post), _ptr(lam), _ptr(dLdphi), _stream(stream)), h)
 
 
 def cmlbm_kinetic_energy_sum(h, f_pre, stream=None):
@@ -471,6 +477,12 @@ class Sim:
         self._realpop(lam_next, "lam_next")
         self._need(dLdphi, torch.float64, self.nodes, "dLdphi")
         cmlbm_wall_sensitivity(self.h, f_post_prev, lam_next, dLdphi, stream)
+
+    def wall_sensitivity_post(self, f_post, lam, dLdphi, stream=None):
+        self._pop(f_post, "f_post")
+        self._realpop(lam, "lam")
+        self._need(dLdphi, torch.float64, self.nodes, "dLdphi")
+        cmlbm_wall_sensitivity_post(self.h, f_post, lam, dLdphi, stream)
 
     def kinetic_energy_sum(self, f_pre, stream=None):
         return cmlbm_kinetic_energy_sum(self.h, self._realpop(f_pre, "f_pre"), stream)

@@ -560,8 +560,8 @@ cmlbm_status cmlbm_adjoint_step(cmlbm_sim* s, const void* f_post_prev, const voi
   return check_hip(s, e, "adjoint_step");
 }
 
-cmlbm_status cmlbm_wall_sensitivity(cmlbm_sim* s, const void* f_post_prev, const void* lam_next, double* dLdphi_dev,
-                                    void* stream) {
+static cmlbm_status wall_sensitivity(cmlbm_sim* s, const void* f_post_prev, const void* lam_next, double* dLdphi_dev,
+                                     bool post, void* stream) {
   CMLBM_WORK_ENTRY(s);
   if (!f_post_prev || !lam_next || !dLdphi_dev) return fail(s, CMLBM_EINVAL, "NULL buffer");
   if (f_post_prev == lam_next || static_cast<const void*>(dLdphi_dev) == lam_next ||
@@ -585,8 +585,19 @@ cmlbm_status cmlbm_wall_sensitivity(cmlbm_sim* s, const void* f_post_prev, const
     a32.force = make_force<float>(s);
     a32.rates = make_rates<float>(s);
   }
-  hipError_t e = cmlbm::launch_wall_sensitivity(s->q, s->prec, a64, a32, dLdphi_dev, static_cast<hipStream_t>(stream));
-  return check_hip(s, e, "wall_sensitivity");
+  hipError_t e =
+      cmlbm::launch_wall_sensitivity(s->q, s->prec, a64, a32, dLdphi_dev, post, static_cast<hipStream_t>(stream));
+  return check_hip(s, e, post ? "wall_sensitivity_post" : "wall_sensitivity");
+}
+
+cmlbm_status cmlbm_wall_sensitivity(cmlbm_sim* s, const void* f_post_prev, const void* lam_next, double* dLdphi_dev,
+                                    void* stream) {
+  return wall_sensitivity(s, f_post_prev, lam_next, dLdphi_dev, false, stream);
+}
+
+cmlbm_status cmlbm_wall_sensitivity_post(cmlbm_sim* s, const void* f_post, const void* lam, double* dLdphi_dev,
+                                         void* stream) {
+  return wall_sensitivity(s, f_post, lam, dLdphi_dev, true, stream);
 }
 
 cmlbm_status cmlbm_kinetic_energy_sum(cmlbm_sim* s, const void* f_pre, double* out, void* stream) {

@@ -250,10 +250,9 @@ __device__ __forceinline__ void pull(const typename ST::T* __restrict__ fin, con
         const T* rp = fin + uint64_t(st.row[e.y + 1][e.z + 1]) * rowQ;
         T v;
         if constexpr (BUF) {
+          static_assert(!MASK, "a per-lane choice of row must not select the descriptor");
           const uint32_t rowB = uint32_t(rowQ) * sz;
-          if (MASK && mask[st.node(e, nx)])
-            v = buf_load<T>(array_rsrc(own, rowB), cbase, uint32_t(opposite<Q>(a)) * lenB);
-          else if (e.x == 0)
+          if (e.x == 0)
             v = buf_load<T>(array_rsrc(rp, rowB), cbase, uint32_t(a) * lenB);
           else if constexpr (decltype(full)::value)
             v = buf_load<T>(array_rsrc(rp, rowB), nbase[e.x + 1], uint32_t(a) * lenB);
@@ -356,6 +355,8 @@ __device__ __forceinline__ uint32_t step_block_id() {
 }
 
 constexpr int kStoreAux = CMLBM_NT_STORE ? 2 : 0;   // 2: nontemporal (streaming) store
+// A per-lane byte offset past every row's bound: the raw buffer store drops it.
+constexpr uint32_t kDropOffset = 0x80000000u;
 
 // voff: per-lane byte offset; soff: wave-uniform byte offset; AUX: cache
 // policy bits (kStoreAux streams past the caches; 0 keeps the line).
@@ -561,14 +562,24 @@ __global__ __launch_bounds__(CMLBM_STEP_BLOCK) void k_step_inplace(StepArgs<type
           const __amdgpu_buffer_rsrc_t rr = array_rsrc(buf + uint64_t(st.row[e.y + 1][e.z + 1]) * rowQ, rowQ * sz);
           const uint32_t ab = uint32_t(opposite<Q>(a));
           T v;
-          if (MASK && ((solid >> a) & 1u))
-            v = buf_load<T>(rs, cbase, uint32_t(a) * lenB);
-          else if (e.x == 0)
+          if constexpr (MASK) {
+            // plain loads: a per-lane choice of row must not pick the descriptor
+            const char* rp = reinterpret_cast<const char*>(buf + uint64_t(st.row[e.y + 1][e.z + 1]) * rowQ);
+            if ((solid >> a) & 1u)
+              v = ldb<T>(own + uint32_t(a) * lenB, cbase);
+            else if (e.x == 0)
+              v = ldb<T>(rp + ab * lenB, cbase);
+            else if constexpr (decltype(fullrow)::value)
+              v = ldb<T>(rp + ab * lenB, nbase[e.x + 1]);
+            else
+              v = ldb<T>(rp, nbase[e.x + 1] + ab * nlen[e.x + 1]);
+          } else if (e.x == 0) {
             v = buf_load<T>(rr, cbase, ab * lenB);
-          else if constexpr (decltype(fullrow)::value)
+          } else if constexpr (decltype(fullrow)::value) {
             v = buf_load<T>(rr, nbase[e.x + 1], ab * lenB);
-          else
+          } else {
             v = buf_load<T>(rr, nbase[e.x + 1] + ab * nlen[e.x + 1], 0u);
+          }
           f[a] = decode<ST, Q>(v, a);
         }
       };
@@ -591,17 +602,28 @@ __global__ __launch_bounds__(CMLBM_STEP_BLOCK) void k_step_inplace(StepArgs<type
         for (int a = 0; a < Q; ++a) {
           const Vel e = Lattice<Q>::e(a);
           const int ab = opposite<Q>(a);
-          if (MASK && ((solid >> ab) & 1u)) {            // x + e_a = x - e_abar is solid
-            buf_store<kInplaceAux>(v[a], rs, cbase, uint32_t(ab) * lenB);
+          const __amdgpu_buffer_rsrc_t rt = array_rsrc(buf + uint64_t(st.row[1 - e.y][1 - e.z]) * rowQ, rowQ * sz);
+          uint32_t off, soff;
+          if (e.x == 0) {
+            off = cbase;
+            soff = uint32_t(a) * lenB;
+          } else if constexpr (decltype(fullrow)::value) {
+            off = nbase[1 - e.x];
+            soff = uint32_t(a) * lenB;
           } else {
-            const __amdgpu_buffer_rsrc_t rt =
-                array_rsrc(buf + uint64_t(st.row[1 - e.y][1 - e.z]) * rowQ, rowQ * sz);
-            if (e.x == 0)
-              buf_store<kInplaceAux>(v[a], rt, cbase, uint32_t(a) * lenB);
-            else if constexpr (decltype(fullrow)::value)
-              buf_store<kInplaceAux>(v[a], rt, nbase[1 - e.x], uint32_t(a) * lenB);
-            else
-              buf_store<kInplaceAux>(v[a], rt, nbase[1 - e.x] + uint32_t(a) * nlen[1 - e.x], 0u);
+            off = nbase[1 - e.x] + uint32_t(a) * nlen[1 - e.x];
+            soff = 0u;
+          }
+          if constexpr (MASK) {
+            // x + e_a = x - e_abar solid: the population returns into slot abar
+            // of x.  Both stores are issued and each lane drops the one that
+            // does not apply (offset past the bound): no branch, so neither the
+            // descriptor nor the uniform offset becomes a per-lane choice.
+            const bool back = (solid >> ab) & 1u;
+            buf_store<kInplaceAux>(v[a], rs, back ? cbase : kDropOffset, uint32_t(ab) * lenB);
+            buf_store<kInplaceAux>(v[a], rt, back ? kDropOffset : off, soff);
+          } else {
+            buf_store<kInplaceAux>(v[a], rt, off, soff);
           }
         }
       };
@@ -757,7 +779,7 @@ __global__ __launch_bounds__(CMLBM_STEP_BLOCK) void k_scatter_periodic(StepArgs<
   // raw buffer store drops it.  The one node that writes across the segment's
   // end (to x + 1 after the last node, x - 1 before the first) is the same for
   // the whole block, so that target's offsets are wave-uniform.
-  constexpr uint32_t kDrop = 0x80000000u;
+  constexpr uint32_t kDrop = kDropOffset;
   const uint32_t xn = xend == nx ? 0u : xend, xp = x0 == 0 ? nx - 1 : x0 - 1;   // periodic
   const uint32_t bn = xn & ~63u, bp = xp & ~63u;
   const uint32_t off_own = active ? cbase : kDrop;
@@ -1156,32 +1178,60 @@ __global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(adjoi
     if (x >= nx) continue;
     const uint32_t rowB = nx * uint32_t(sizeof(R)), xB = x * uint32_t(sizeof(R));   // one row of a [Q][N] plane
     const Coord c{int(x), int(row % uint32_t(g.ny)), int(row / uint32_t(g.ny))};
-    if (MASK && args.mask[row * nx + x]) continue;
-    // forward pre-collision populations (D3Q27: in cube order)
-    R f[Q];
-    {
-      const Stencil st(g, c, +1);
-      R fa[Q];
-      pull<Q, ST, MASK, true, true>(static_cast<const T*>(args.fpost), g, args.mask, st, row, x, fa);
+    const Stencil up(g, c, +1);    // up.node(e) = x - e
+    R f[Q], gm[Q];
+    if constexpr (MASK) {
+      // bit a: x - e_a is solid (bit 0: x itself).  x + e_a = x - e_abar, so
+      // the same bits serve the reverse gather; one round of mask loads, then
+      // both gathers' loads together.
+      uint32_t solid = 0;
 #pragma unroll
-      for (int a = 0; a < Q; ++a) f[slot<Q>(a)] = fa[a];
-    }
-    // adjoint of this node's post-collision populations (reverse streaming)
-    R gm[Q];
-    {
-      const Stencil st(g, c, -1);
+      for (int a = 0; a < Q; ++a) solid |= uint32_t(args.mask[up.node(Lattice<Q>::e(a), nx)] != 0) << a;
+      if (solid & 1u) continue;
+      const T* fin = static_cast<const T*>(args.fpost);
+      const uint64_t rowQ = uint64_t(nx) * Q;
+      constexpr uint32_t sz = uint32_t(sizeof(T));
+      const uint32_t b0 = __builtin_amdgcn_readfirstlane(x & ~63u);
+      const uint32_t lenB = min(64u, nx - b0) * sz;
+      const uint32_t cbase = (b0 * uint32_t(Q) + (x - b0)) * sz;
+      const char* own = reinterpret_cast<const char*>(fin + uint64_t(row) * rowQ);
+      const Stencil dn(g, c, -1);  // dn.node(e) = x + e
       const uint64_t N = per_item(g.N);
 #pragma unroll
       for (int a = 0; a < Q; ++a) {
         const Vel e = Lattice<Q>::e(a);
-        R v;
-        if (MASK && args.mask[st.node(e, nx)])
-          v = buf_load<R>(array_rsrc(args.lam_next + uint64_t(opposite<Q>(a)) * N + uint64_t(row) * nx, rowB),
-                          xB, 0u);
-        else
-          v = buf_load<R>(array_rsrc(args.lam_next + uint64_t(a) * N + uint64_t(st.row[e.y + 1][e.z + 1]) * nx, rowB),
-                          st.xs[e.x + 1] * uint32_t(sizeof(R)), 0u);
-        gm[slot<Q>(a)] = v;
+        const uint32_t ab = uint32_t(opposite<Q>(a));
+        // pull: fbar_a(x) = fbar~_a(x - e_a), or fbar~_abar(x) from x's own slot
+        T v;
+        if ((solid >> a) & 1u) {
+          v = ldb<T>(own + ab * lenB, cbase);
+        } else {
+          const uint32_t xs = up.xs[e.x + 1], bb = xs & ~63u;
+          v = ldb<T>(fin + uint64_t(up.row[e.y + 1][e.z + 1]) * rowQ,
+                     (bb * uint32_t(Q) + (xs - bb)) * sz + uint32_t(a) * min(64u, nx - bb) * sz);
+        }
+        f[slot<Q>(a)] = decode<ST, Q>(v, a);
+        // reverse gather: lam_a(x + e_a), or lam_abar(x) where x + e_a is solid
+        gm[slot<Q>(a)] = ((solid >> ab) & 1u)
+                             ? ld32(args.lam_next + uint64_t(ab) * N + uint64_t(row) * nx, x)
+                             : ld32(args.lam_next + uint64_t(a) * N + uint64_t(dn.row[e.y + 1][e.z + 1]) * nx,
+                                    dn.xs[e.x + 1]);
+      }
+    } else {
+      // forward pre-collision populations (D3Q27: in cube order)
+      R fa[Q];
+      pull<Q, ST, false, true, true>(static_cast<const T*>(args.fpost), g, args.mask, up, row, x, fa);
+#pragma unroll
+      for (int a = 0; a < Q; ++a) f[slot<Q>(a)] = fa[a];
+      // adjoint of this node's post-collision populations (reverse streaming)
+      const Stencil dn(g, c, -1);
+      const uint64_t N = per_item(g.N);
+#pragma unroll
+      for (int a = 0; a < Q; ++a) {
+        const Vel e = Lattice<Q>::e(a);
+        gm[slot<Q>(a)] =
+            buf_load<R>(array_rsrc(args.lam_next + uint64_t(a) * N + uint64_t(dn.row[e.y + 1][e.z + 1]) * nx, rowB),
+                        dn.xs[e.x + 1] * uint32_t(sizeof(R)), 0u);
       }
     }
     R Fx, Fy, Fz;
@@ -1274,6 +1324,44 @@ __global__ __launch_bounds__(256) void k_wall_sens(AdjArgs<typename ST::R> args,
       const double arrived = double(args.lam_next[uint64_t(a) * g.N + t]);
       atomicAdd(dLdphi + t, double(f[a]) * (own - arrived));
     }
+  }
+}
+
+// The same terms from the state the streaming moves: fpost = fbar~ as the
+// step stored it, lam_next = dL/dfbar of the pre-collision state that
+// streaming fpost produces.  Each fluid node t gathers its own terms, in a
+// fixed order and without atomics, and no collision is recomputed:
+//   dL/dphi(t) += sum_a fbar~_a(s) (lam_abar(s) - lam_a(t)),  s = t - e_a fluid.
+template <int Q, class ST, bool MASK>
+__global__ __launch_bounds__(256) void k_wall_gather(AdjArgs<typename ST::R> args, double* dLdphi) {
+  using T = typename ST::T;
+  const Geom g = args.g;
+  const uint32_t nx = uint32_t(g.nx);
+  const uint64_t rowQ = uint64_t(nx) * Q;
+  const T* fin = static_cast<const T*>(args.fpost);
+  for (uint32_t n = blockIdx.x * blockDim.x + threadIdx.x; n < g.N; n += gridDim.x * blockDim.x) {
+    if (MASK && args.mask[n]) continue;
+    const Stencil up(g, coord_of(g, n), +1);      // up.node(e) = t - e
+    // bit a: t - e_a solid (one round of mask loads; the value loads below
+    // do not wait on it, and a solid source's term is dropped by a select)
+    uint32_t solid = 0;
+    if constexpr (MASK) {
+#pragma unroll
+      for (int a = 1; a < Q; ++a) solid |= uint32_t(args.mask[up.node(Lattice<Q>::e(a), nx)] != 0) << a;
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int a = 1; a < Q; ++a) {
+      const Vel e = Lattice<Q>::e(a);
+      const uint32_t src = up.node(e, nx);
+      const double fs = double(decode<ST, Q>(
+          ld32(fin + uint64_t(up.row[e.y + 1][e.z + 1]) * rowQ, in_row<Q>(nx, a, up.xs[e.x + 1])), a));
+      const double own = double(args.lam_next[uint64_t(opposite<Q>(a)) * g.N + src]);
+      const double arrived = double(args.lam_next[uint64_t(a) * g.N + n]);
+      const double term = fs * (own - arrived);
+      acc += ((solid >> a) & 1u) ? 0.0 : term;   // (a solid node's slots hold no state)
+    }
+    dLdphi[n] += acc;
   }
 }
 
@@ -1611,11 +1699,19 @@ hipError_t adjoint_impl(const AdjArgs<typename ST::R>& args, double* partials, i
 }
 
 template <int Q, class ST>
-hipError_t wall_sens_impl(const AdjArgs<typename ST::R>& a, double* dLdphi, hipStream_t st) {
-  if (a.mask)
-    hipLaunchKernelGGL((k_wall_sens<Q, ST, true>), dim3(aux_grid(a.g)), dim3(kBlock), 0, st, a, dLdphi);
-  else
-    hipLaunchKernelGGL((k_wall_sens<Q, ST, false>), dim3(aux_grid(a.g)), dim3(kBlock), 0, st, a, dLdphi);
+hipError_t wall_sens_impl(const AdjArgs<typename ST::R>& a, double* dLdphi, bool post, hipStream_t st) {
+  const dim3 grid(aux_grid(a.g)), block(kBlock);
+  if (post) {
+    if (a.mask)
+      hipLaunchKernelGGL((k_wall_gather<Q, ST, true>), grid, block, 0, st, a, dLdphi);
+    else
+      hipLaunchKernelGGL((k_wall_gather<Q, ST, false>), grid, block, 0, st, a, dLdphi);
+  } else {
+    if (a.mask)
+      hipLaunchKernelGGL((k_wall_sens<Q, ST, true>), grid, block, 0, st, a, dLdphi);
+    else
+      hipLaunchKernelGGL((k_wall_sens<Q, ST, false>), grid, block, 0, st, a, dLdphi);
+  }
   return hipGetLastError();
 }
 
@@ -1724,13 +1820,15 @@ hipError_t launch_adjoint(int q, int prec, const AdjArgs<double>& a64, const Adj
 }
 
 hipError_t launch_wall_sensitivity(int q, int prec, const AdjArgs<double>& a64, const AdjArgs<float>& a32,
-                                   double* dLdphi, hipStream_t st) {
+                                   double* dLdphi, bool post, hipStream_t st) {
   if (q == 27) {
-    CMLBM_DISPATCH(prec, (wall_sens_impl<27, StF64>(a64, dLdphi, st)), (wall_sens_impl<27, StF32>(a32, dLdphi, st)),
-                   (wall_sens_impl<27, StF16>(a32, dLdphi, st)), (wall_sens_impl<27, StBF16>(a32, dLdphi, st)))
+    CMLBM_DISPATCH(prec, (wall_sens_impl<27, StF64>(a64, dLdphi, post, st)),
+                   (wall_sens_impl<27, StF32>(a32, dLdphi, post, st)), (wall_sens_impl<27, StF16>(a32, dLdphi, post, st)),
+                   (wall_sens_impl<27, StBF16>(a32, dLdphi, post, st)))
   }
-  CMLBM_DISPATCH(prec, (wall_sens_impl<15, StF64>(a64, dLdphi, st)), (wall_sens_impl<15, StF32>(a32, dLdphi, st)),
-                 (wall_sens_impl<15, StF16>(a32, dLdphi, st)), (wall_sens_impl<15, StBF16>(a32, dLdphi, st)))
+  CMLBM_DISPATCH(prec, (wall_sens_impl<15, StF64>(a64, dLdphi, post, st)),
+                 (wall_sens_impl<15, StF32>(a32, dLdphi, post, st)), (wall_sens_impl<15, StF16>(a32, dLdphi, post, st)),
+                 (wall_sens_impl<15, StBF16>(a32, dLdphi, post, st)))
 }
 
 #undef CMLBM_DISPATCH

@@ -97,8 +97,11 @@ hipError_t launch_adjoint(int q, int prec, const AdjArgs<double>& a64, const Adj
 
 // Wall-layout sensitivity of one step (fpost, lam_next, mask, force, rates of
 // the AdjArgs; lam and dLdF unused): accumulates into dLdphi[N] (FP64).
+// post = false: fpost is the step's input state and the collision is
+// recomputed (FP64 atomics); post = true: fpost is the collided state the
+// streaming moves, and each node gathers its own terms.
 hipError_t launch_wall_sensitivity(int q, int prec, const AdjArgs<double>& a64, const AdjArgs<float>& a32,
-                                   double* dLdphi, hipStream_t st);
+                                   double* dLdphi, bool post, hipStream_t st);
 
 hipError_t launch_ke_sum(int q, int prec, const Geom& g, const void* fpre, const uint8_t* mask,
                          const ForceArgs<double>& f64, const ForceArgs<float>& f32, double* partials, int nblk,

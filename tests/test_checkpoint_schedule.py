@@ -171,3 +171,41 @@ def test_run_rejects_negative_step_counts():
         ag.run(_Q(), None, None, None, [1.0] * 23, -1, every=1)
     with pytest.raises(ValueError):
         ag.run(_Q(), None, None, None, [1.0] * 23, 2.5, every=1)
+
+
+class WallFakeSim(FakeSim):
+    """Also tracks which adjoint each lam buffer holds, and the wall terms."""
+
+    def __init__(self):
+        super().__init__()
+        self.wall = []
+
+    def adjoint_step(self, x, lam, lam_tmp, dLdF, dLdw):
+        super().adjoint_step(x, lam, lam_tmp, dLdF, dLdw)
+        assert lam.t == x.t + 1          # lam(t + 1) in, lam(t) out
+        lam_tmp.t = x.t
+
+    def wall_sensitivity_post(self, x, lam, dLdphi):
+        assert lam.t == x.t              # the streaming of x(t) into fbar(t)
+        self.wall.append(x.t)
+
+
+@pytest.mark.parametrize("nsteps,schedule", [(12, {"every": 4}), (12, {"snapshots": 2}), (9, {"snapshots": 0}),
+                                             (1, {"every": 1}), (2, {"snapshots": 1})])
+def test_wall_terms_follow_their_adjoint_steps(nsteps, schedule):
+    # With a wall fraction every adjoint step from x(t), t > 0, is followed by
+    # the wall term of the streaming x(t) -> fbar(t), taken with lam(t) just
+    # computed; the last streaming's term (x(N), the incoming gradient) is the
+    # backward pass's own, before the sweep.
+    sim = WallFakeSim()
+    pool = ag._Pool(sim)
+    x0 = pool.get()
+    x0.t = 0
+    stored, last = ag.forward_sweep(sim, pool, x0, nsteps, ag.keep_positions(nsteps, schedule.get("every"),
+                                                                            schedule.get("snapshots")))
+    lam, lam_tmp = _State(), _State()
+    lam.t = nsteps
+    sw = ag._Sweep(sim, pool, lam, lam_tmp, None, None, dLdphi=object())
+    ag.backward_sweep(sw, stored, nsteps, schedule.get("every"), schedule.get("snapshots"))
+    assert sim.seen == list(range(nsteps - 1, -1, -1))
+    assert sim.wall == list(range(nsteps - 1, 0, -1))

@@ -4,9 +4,12 @@ derivatives of the FP64 oracle's wall-fraction step.
 The wall fraction phi(x) in [0, 1] blends plain streaming and half-way
 bounce-back, fbar_a(x) = (1 - phi(x)) fbar~_a(x - e_a) + phi(x - e_a)
 fbar~_abar(x) (oracle/lbm.py, stream_wall_fraction); with phi in {0, 1} it is the
-masked step.  cmlbm_wall_sensitivity accumulates dL/dphi at every fluid node,
-evaluated at the mask: one step's contribution against the oracle, and whole
-checkpointed runs (torch.autograd through ``autograd.run(..., wall=phi)``).
+masked step.  cmlbm_wall_sensitivity (from the step's input, recomputing the
+collision) and cmlbm_wall_sensitivity_post (from the collided state the
+streaming moves) accumulate dL/dphi at every fluid node, evaluated at the
+mask: one step's contribution against the oracle, and whole checkpointed runs
+(torch.autograd through ``autograd.run(..., wall=phi)``, which uses the
+second).
 """
 import numpy as np
 import pytest
@@ -58,10 +61,18 @@ def test_wall_sensitivity_one_step(q, per_mass):
     f_pre = sim.gather(x).cpu().numpy()
     mu = rng.standard_normal((q,) + shape)
     mu[:, solid] = 0.0
+    mu_d = torch.from_numpy(mu).cuda()
     g = torch.zeros(shape, dtype=torch.float64, device="cuda")
-    cmlbm.cmlbm_wall_sensitivity(sim.h, x, torch.from_numpy(mu).cuda(), g)
+    cmlbm.cmlbm_wall_sensitivity(sim.h, x, mu_d, g)
     g = g.cpu().numpy()
     assert np.all(g[solid] == 0.0)
+    # the gather form, from the collided state the streaming moves
+    x1 = sim.run(x, sim.populations(), 1)
+    gp = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    cmlbm.cmlbm_wall_sensitivity_post(sim.h, x1, mu_d, gp)
+    gp = gp.cpu().numpy()
+    assert np.all(gp[solid] == 0.0)
+    np.testing.assert_allclose(gp, g, rtol=1e-12, atol=1e-12 * np.abs(g).max())
 
     def L(p):
         return np.sum(mu * lbm.step_wall_fraction(lat, f_pre.astype(complex), F.astype(complex), om, p, per_mass))
@@ -71,6 +82,8 @@ def test_wall_sensitivity_one_step(q, per_mass):
         ref = L(phi + 1j * H * v).imag / H
         got = float(np.sum(g * v))
         assert abs(got - ref) <= 1e-10 * abs(ref), (k, got, ref)
+        got_post = float(np.sum(gp * v))
+        assert abs(got_post - ref) <= 1e-10 * abs(ref), (k, got_post, ref)
     # single fluid nodes: beside the bottom wall, beside the obstacle, in the bulk
     for z, y, xx in [(1, 3, 10), (shape[0] // 2, shape[1] // 2, shape[2] // 3 + 1), (4, 5, 50)]:
         assert not solid[z, y, xx]
@@ -78,6 +91,7 @@ def test_wall_sensitivity_one_step(q, per_mass):
         e[z, y, xx] = 1.0
         ref = L(phi + 1j * H * e).imag / H
         assert abs(g[z, y, xx] - ref) <= 1e-10 * abs(ref) + 1e-16, ((z, y, xx), g[z, y, xx], ref)
+        assert abs(gp[z, y, xx] - ref) <= 1e-10 * abs(ref) + 1e-16, ((z, y, xx), gp[z, y, xx], ref)
 
 
 def _oracle_loss(q, rho0, u0, F, om, nsteps, phi):
