@@ -1333,36 +1333,47 @@ __global__ __launch_bounds__(256) void k_wall_sens(AdjArgs<typename ST::R> args,
 // fixed order and without atomics, and no collision is recomputed:
 //   dL/dphi(t) += sum_a fbar~_a(s) (lam_abar(s) - lam_a(t)),  s = t - e_a fluid.
 template <int Q, class ST, bool MASK>
-__global__ __launch_bounds__(256) void k_wall_gather(AdjArgs<typename ST::R> args, double* dLdphi) {
+__global__ __launch_bounds__(CMLBM_STEP_BLOCK) void k_wall_gather(AdjArgs<typename ST::R> args, double* dLdphi) {
+  using R = typename ST::R;
   using T = typename ST::T;
+  constexpr uint32_t sz = uint32_t(sizeof(T)), rz = uint32_t(sizeof(R));
   const Geom g = args.g;
   const uint32_t nx = uint32_t(g.nx);
-  const uint64_t rowQ = uint64_t(nx) * Q;
-  const T* fin = static_cast<const T*>(args.fpost);
-  for (uint32_t n = blockIdx.x * blockDim.x + threadIdx.x; n < g.N; n += gridDim.x * blockDim.x) {
-    if (MASK && args.mask[n]) continue;
-    const Stencil up(g, coord_of(g, n), +1);      // up.node(e) = t - e
-    // bit a: t - e_a solid (one round of mask loads; the value loads below
-    // do not wait on it, and a solid source's term is dropped by a select)
-    uint32_t solid = 0;
-    if constexpr (MASK) {
+  // one block per row segment, as the step kernels: every source row of a
+  // direction is uniform over the block, so each direction's three loads go
+  // through buffer descriptors with per-lane x offsets only
+  const uint32_t nseg = (nx + blockDim.x - 1) / blockDim.x;
+  const uint32_t L = step_block_id();
+  const uint32_t row = L / nseg;
+  const uint32_t x = (L - row * nseg) * blockDim.x + threadIdx.x;
+  if (x >= nx) return;
+  if (MASK && args.mask[uint64_t(row) * nx + x]) return;
+  const Coord c{int(x), int(row % uint32_t(g.ny)), int(row / uint32_t(g.ny))};
+  const Stencil up(g, c, +1);      // up.node(e) = t - e
+  // bit a: t - e_a solid (one round of mask loads; the value loads below do
+  // not wait on it, and a solid source's term is dropped by a select: its
+  // slots hold no state)
+  uint32_t solid = 0;
+  if constexpr (MASK) {
 #pragma unroll
-      for (int a = 1; a < Q; ++a) solid |= uint32_t(args.mask[up.node(Lattice<Q>::e(a), nx)] != 0) << a;
-    }
-    double acc = 0.0;
-#pragma unroll
-    for (int a = 1; a < Q; ++a) {
-      const Vel e = Lattice<Q>::e(a);
-      const uint32_t src = up.node(e, nx);
-      const double fs = double(decode<ST, Q>(
-          ld32(fin + uint64_t(up.row[e.y + 1][e.z + 1]) * rowQ, in_row<Q>(nx, a, up.xs[e.x + 1])), a));
-      const double own = double(args.lam_next[uint64_t(opposite<Q>(a)) * g.N + src]);
-      const double arrived = double(args.lam_next[uint64_t(a) * g.N + n]);
-      const double term = fs * (own - arrived);
-      acc += ((solid >> a) & 1u) ? 0.0 : term;   // (a solid node's slots hold no state)
-    }
-    dLdphi[n] += acc;
+    for (int a = 1; a < Q; ++a) solid |= uint32_t(args.mask[up.node(Lattice<Q>::e(a), nx)] != 0) << a;
   }
+  const T* fin = static_cast<const T*>(args.fpost);
+  const uint32_t rowQB = nx * uint32_t(Q) * sz, rowB = nx * rz;
+  const uint64_t N = per_item(g.N);
+  double acc = 0.0;
+#pragma unroll
+  for (int a = 1; a < Q; ++a) {
+    const Vel e = Lattice<Q>::e(a);
+    const uint32_t ab = uint32_t(opposite<Q>(a));
+    const uint32_t srow = up.row[e.y + 1][e.z + 1], xs = up.xs[e.x + 1];
+    const T v = buf_load<T>(array_rsrc(fin + uint64_t(srow) * nx * Q, rowQB), in_row<Q>(nx, a, xs) * sz, 0u);
+    const R own = buf_load<R>(array_rsrc(args.lam_next + uint64_t(ab) * N + uint64_t(srow) * nx, rowB), xs * rz, 0u);
+    const R arrived = buf_load<R>(array_rsrc(args.lam_next + uint64_t(a) * N + uint64_t(row) * nx, rowB), x * rz, 0u);
+    const double term = double(decode<ST, Q>(v, a)) * (double(own) - double(arrived));
+    acc += ((solid >> a) & 1u) ? 0.0 : term;
+  }
+  dLdphi[uint64_t(row) * nx + x] += acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -1702,10 +1713,11 @@ template <int Q, class ST>
 hipError_t wall_sens_impl(const AdjArgs<typename ST::R>& a, double* dLdphi, bool post, hipStream_t st) {
   const dim3 grid(aux_grid(a.g)), block(kBlock);
   if (post) {
+    const int bx = step_block(a.g);
     if (a.mask)
-      hipLaunchKernelGGL((k_wall_gather<Q, ST, true>), grid, block, 0, st, a, dLdphi);
+      hipLaunchKernelGGL((k_wall_gather<Q, ST, true>), step_grid(a.g, bx), dim3(bx), 0, st, a, dLdphi);
     else
-      hipLaunchKernelGGL((k_wall_gather<Q, ST, false>), grid, block, 0, st, a, dLdphi);
+      hipLaunchKernelGGL((k_wall_gather<Q, ST, false>), step_grid(a.g, bx), dim3(bx), 0, st, a, dLdphi);
   } else {
     if (a.mask)
       hipLaunchKernelGGL((k_wall_sens<Q, ST, true>), grid, block, 0, st, a, dLdphi);
