@@ -326,9 +326,9 @@ def wall_sweep(n, launches=6):
     sensitivity (gather form) on the 512^3 workload inside a square duct
     (solid planes y, z in {0, n-1}, as in Sec. 9), with algorithmic bytes per
     node over all n^3 nodes: step 228 and adjoint 384 as without walls; the
-    wall term 26 (4 + 4 + 4) + 16 = 328 (for each moving direction the
-    source's collided population and lambda_abar, the target's lambda_a;
-    FP64 dL/dphi read-modify-write)."""
+    wall term 26 x 4 (collided state) + 26 x 4 (lambda) + 16 (FP64 dL/dphi
+    read-modify-write) = 224: each lambda value enters twice, as lambda_a of
+    its own node and as lambda_abar of the neighbour it feeds, and counts once."""
     import torch
     import lbm_inputs as inp
     from paper_1202_6081_amd import cmlbm
@@ -352,7 +352,7 @@ def wall_sweep(n, launches=6):
     for name, bpn, launch in (
             ("step", 228, lambda i: sim.step(xs[i & 1], xs[(i + 1) & 1])),
             ("adjoint_step", 384, lambda i: sim.adjoint_step(x, bufs[i & 1], bufs[(i + 1) & 1], dLdF, dLdw)),
-            ("wall_sensitivity", 328, lambda i: sim.wall_sensitivity_post(x1, lam_a, dphi))):
+            ("wall_sensitivity", 224, lambda i: sim.wall_sensitivity_post(x1, lam_a, dphi))):
         launch(0)
         ms = _launch_ms(launch, launches)
         gbs = bpn * n**3 / (ms * 1e-3) / 1e9
