@@ -1332,6 +1332,8 @@ __global__ __launch_bounds__(256) void k_wall_sens(AdjArgs<typename ST::R> args,
 // streaming fpost produces.  Each fluid node t gathers its own terms, in a
 // fixed order and without atomics, and no collision is recomputed:
 //   dL/dphi(t) += sum_a fbar~_a(s) (lam_abar(s) - lam_a(t)),  s = t - e_a fluid.
+constexpr uint32_t kWallTileZ = 8;   // planes per tile of the wall term's row order
+
 template <int Q, class ST, bool MASK>
 __global__ __launch_bounds__(CMLBM_STEP_BLOCK) void k_wall_gather(AdjArgs<typename ST::R> args, double* dLdphi) {
   using R = typename ST::R;
@@ -1341,14 +1343,25 @@ __global__ __launch_bounds__(CMLBM_STEP_BLOCK) void k_wall_gather(AdjArgs<typena
   const uint32_t nx = uint32_t(g.nx);
   // one block per row segment, as the step kernels: every source row of a
   // direction is uniform over the block, so each direction's three loads go
-  // through buffer descriptors with per-lane x offsets only
+  // through buffer descriptors with per-lane x offsets only.  Each lambda
+  // value is read twice, by its own node and by the neighbour it feeds; the
+  // rows are taken in tiles of kWallTileZ planes, z fastest inside a tile,
+  // so that a row's neighbours in the planes above and below are processed
+  // within a few blocks of it and its lambda values are still in L2 (in
+  // plain row order the planes are a whole plane of rows apart).
   const uint32_t nseg = (nx + blockDim.x - 1) / blockDim.x;
   const uint32_t L = step_block_id();
-  const uint32_t row = L / nseg;
-  const uint32_t x = (L - row * nseg) * blockDim.x + threadIdx.x;
+  const uint32_t q = L / nseg;                       // position in the tiled row order
+  const uint32_t x = (L - q * nseg) * blockDim.x + threadIdx.x;
   if (x >= nx) return;
+  const uint32_t ny = uint32_t(g.ny), nz = uint32_t(g.nz);
+  const uint32_t tile = q / (ny * kWallTileZ);
+  const uint32_t z0 = tile * kWallTileZ, h = min(kWallTileZ, nz - z0);
+  const uint32_t within = q - z0 * ny;
+  const uint32_t yy = within / h, zz = z0 + (within - yy * h);
+  const uint32_t row = zz * ny + yy;
   if (MASK && args.mask[uint64_t(row) * nx + x]) return;
-  const Coord c{int(x), int(row % uint32_t(g.ny)), int(row / uint32_t(g.ny))};
+  const Coord c{int(x), int(yy), int(zz)};
   const Stencil up(g, c, +1);      // up.node(e) = t - e
   // bit a: t - e_a solid (one round of mask loads; the value loads below do
   // not wait on it, and a solid source's term is dropped by a select: its
