@@ -137,3 +137,38 @@ def test_wall_gradient_of_a_run(q, prec, schedule):
         tol = 1e-9 if prec == F64 else 1e-3   # FP32: the populations round to 2^-24 every step (measured 2.4e-4)
         print(f"wall-grad q{q} p{prec}: dir {k}: {got:.10e} vs oracle {ref:.10e}", flush=True)
         assert abs(got - ref) <= tol * abs(ref), (k, got, ref)
+
+
+@pytest.mark.parametrize("q,prec,shape", [(27, F64, (19, 5, 70)), (15, F64, (17, 4, 64)), (27, F32, (9, 3, 300))])
+def test_wall_sensitivity_forms_agree(q, prec, shape):
+    # The gather form (taken in tiles of 8 planes, z fastest: several tiles and
+    # a ragged last one here) against the scatter form with atomics, on walls
+    # that cross tile boundaries; each fluid node's sum has the same terms.
+    print(f"case wall forms q{q} p{prec} {shape}", flush=True)
+    from paper_1202_6081_amd import cmlbm
+    rng = np.random.default_rng(47)
+    om = list(rng.uniform(0.7, 1.9, q - 4))
+    F = inp.gaussian_force(shape, 1e-4, 9)
+    solid = _walls(shape)
+    solid[7:9, 2, 10:20] = True           # a block across the first tile boundary (z = 8)
+    solid[-1] = True
+    sim = gpu_setup(q, shape, prec, om, F, solid)
+    real = torch.float64 if prec == F64 else torch.float32
+    rho0 = 1 + 0.01 * rng.standard_normal(shape)
+    u0 = 0.05 * rng.uniform(-1, 1, (3,) + shape)
+    x, _ = sim.init_equilibrium(torch.from_numpy(rho0).cuda().to(real), torch.from_numpy(u0).cuda().to(real))
+    x = sim.run(x, sim.populations(), 2)
+    x1 = sim.run(x, sim.populations(), 1)
+    mu = rng.standard_normal((q,) + shape)
+    mu[:, solid] = 0.0
+    mu_d = torch.from_numpy(mu).cuda().to(real)
+    g = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    gp = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    cmlbm.cmlbm_wall_sensitivity(sim.h, x, mu_d, g)
+    cmlbm.cmlbm_wall_sensitivity_post(sim.h, x1, mu_d, gp)
+    g, gp = g.cpu().numpy(), gp.cpu().numpy()
+    assert np.all(gp[solid] == 0.0) and np.any(gp != 0.0)
+    # FP64: rounding order only; FP32: the stored state is the collision's
+    # result rounded once, the recomputed one may fuse differently (2^-24 scale)
+    tol = 1e-12 if prec == F64 else 1e-5
+    np.testing.assert_allclose(gp, g, rtol=tol, atol=tol * np.abs(g).max())
