@@ -16,7 +16,7 @@ import pytest
 import torch
 
 import lbm_inputs as inp
-from gpu_helpers import gpu_setup
+from gpu_helpers import gpu_setup, shear_rates
 from oracle import lbm
 from oracle.lattice import LATTICES
 
@@ -172,3 +172,68 @@ def test_wall_sensitivity_forms_agree(q, prec, shape):
     # result rounded once, the recomputed one may fuse differently (2^-24 scale)
     tol = 1e-12 if prec == F64 else 1e-5
     np.testing.assert_allclose(gp, g, rtol=tol, atol=tol * np.abs(g).max())
+
+
+def test_full_size_wall_term_sampled_nodes():
+    # The wall-layout term of the benchmark's wall-bounded measurement (512^3
+    # D3Q27 FP32, square duct, Kolmogorov force, shear rate 1.9), in the launch
+    # configuration the benchmark times, at 384 sampled fluid nodes (beside the
+    # walls, in the duct's corners and in the bulk) against the complex step of
+    # the oracle's wall-fraction streaming on the 3x3x3 neighbourhood of each
+    # node, whose post-collision populations are the oracle's collision of the
+    # pre-collision state the GPU pulled.  (On a periodic 3-wide patch phi at
+    # the centre enters exactly the terms it enters on the lattice.)
+    from oracle import collision
+    print("case wall term full512", flush=True)
+    n, q = 512, 27
+    lat = LATTICES[q]
+    om = shear_rates(q, 1.9)
+    solid = inp.duct_mask(n, n, n)
+    sim = gpu_setup(q, (n, n, n), F32, om, None, solid)
+    F = torch.from_numpy(inp.kolmogorov_force(n)).to("cuda", torch.float32)
+    sim.set_force(F)
+    g = torch.Generator(device="cuda").manual_seed(5)
+    rho0 = torch.ones((n, n, n), device="cuda", dtype=torch.float32)
+    u0 = 0.03 * (torch.rand((3, n, n, n), device="cuda", generator=g) - 0.5)
+    sd = torch.from_numpy(solid).cuda()
+    u0[:, sd] = 0.0
+    x, pre = sim.init_equilibrium(rho0, u0)
+    del rho0, u0
+    x1 = sim.populations()
+    sim.step(x, x1)
+    pre = sim.gather(x, out=pre)                 # fbar at every node: what the step collided
+    lam = torch.randn((q, n, n, n), device="cuda", generator=g)
+    lam[:, sd] = 0.0
+    dphi = torch.zeros((n, n, n), dtype=torch.float64, device="cuda")
+    sim.wall_sensitivity_post(x1, lam, dphi)
+    del x, x1
+    rng = np.random.default_rng(6)
+    picks = [(1, 1, 0), (1, n - 2, n - 1), (n - 2, n - 2, 7), (1, 200, 31), (300, 1, 400), (n - 2, 100, 0)]
+    picks += [tuple(int(v) for v in (rng.integers(1, 4), rng.integers(1, n - 1), rng.integers(0, n))) for _ in range(90)]
+    picks += [tuple(int(v) for v in (rng.integers(1, n - 1), rng.integers(n - 4, n - 1), rng.integers(0, n))) for _ in range(90)]
+    picks += [tuple(int(v) for v in (rng.integers(1, n - 1), rng.integers(1, n - 1), rng.integers(0, n))) for _ in range(192)]
+    offs = [(dz, dy, dx) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
+    nodes = np.array([[((z + dz) % n) * n * n + ((y + dy) % n) * n + (xx + dx) % n for dz, dy, dx in offs]
+                      for z, y, xx in picks])                                          # (samples, 27)
+    flat = torch.from_numpy(nodes.reshape(-1)).to("cuda")
+    f_in = pre.reshape(q, -1)[:, flat].double().cpu().numpy().T                        # (samples*27, q)
+    Fs = F.reshape(3, -1)[:, flat].double().cpu().numpy().T
+    lam_p = lam.reshape(q, -1)[:, flat].double().cpu().numpy().T.reshape(len(picks), 27, q)
+    got = dphi.reshape(-1)[torch.from_numpy(nodes[:, 13]).to("cuda")].cpu().numpy()
+    del pre, lam, dphi
+    torch.cuda.empty_cache()
+    solid_p = solid.reshape(-1)[nodes]                                                 # (samples, 27)
+    fl = ~solid_p.reshape(-1)
+    post = np.zeros((len(picks) * 27, q))          # solid nodes hold no populations
+    post[fl] = collision.collide(lat, f_in[fl], Fs[fl], np.array(om))
+    post = post.reshape(len(picks), 27, q)
+    want = np.empty(len(picks))
+    for k in range(len(picks)):
+        phi = solid_p[k].reshape(3, 3, 3).astype(complex)
+        assert phi[1, 1, 1] == 0
+        phi[1, 1, 1] += 1j * H
+        out = lbm.stream_wall_fraction(lat, post[k].T.reshape(q, 3, 3, 3).astype(complex), phi)
+        want[k] = np.sum(lam_p[k].T.reshape(q, 3, 3, 3) * out).imag / H
+    err = np.abs(got - want).max() / np.abs(want).max()
+    print(f"wall term full512: rel err {err:.2e} over {len(picks)} nodes", flush=True)
+    assert err < 1e-5
