@@ -267,25 +267,31 @@ def test_backward_after_other_work_and_only_once():
     assert np.array_equal(gF0, gF1) and np.array_equal(gw0, gw1)
 
 
-@pytest.mark.parametrize("q", [27, 15])
-def test_full_size_adjoint_sampled_nodes(q):
+@pytest.mark.parametrize("q,duct", [(27, False), (15, False), (27, True)])
+def test_full_size_adjoint_sampled_nodes(q, duct):
     # One adjoint step of the benchmark configuration (512^3 FP32, Kolmogorov
     # force field, shear rate 1.9) in the launch configuration the benchmark
-    # times.  At 2048 sampled nodes (box corners included), lam(x) and dL/dF(x)
-    # against the transposed Jacobian of the oracle's collision, taken by the
-    # complex step at the pre-collision state the GPU pulled, applied to the
-    # reverse-streamed adjoint lam_next(x + e_a)_a.
+    # times, periodic and (duct) inside the square duct of its wall-bounded
+    # measurement.  At 2048 sampled fluid nodes (box corners, and with walls
+    # the nodes beside them, included), lam(x) and dL/dF(x) against the
+    # transposed Jacobian of the oracle's collision, taken by the complex step
+    # at the pre-collision state the GPU pulled, applied to the
+    # reverse-streamed adjoint: lam_next(x + e_a)_a, or lam_next(x)_abar where
+    # x + e_a is solid (half-way bounce-back).
     from oracle import collision
-    print(f"case adjoint full512 q{q}", flush=True)
+    print(f"case adjoint full512 q{q} duct={duct}", flush=True)
     n = 512
     lat = LATTICES[q]
     om = shear_rates(q, 1.9)
-    sim = gpu_setup(q, (n, n, n), F32, om)
+    solid = inp.duct_mask(n, n, n) if duct else np.zeros((n, n, n), dtype=bool)
+    sim = gpu_setup(q, (n, n, n), F32, om, None, solid if duct else None)
     F = torch.from_numpy(inp.kolmogorov_force(n)).to("cuda", torch.float32)
     sim.set_force(F)
     g = torch.Generator(device="cuda").manual_seed(2)
     rho0 = torch.ones((n, n, n), device="cuda", dtype=torch.float32)
     u0 = 0.03 * (torch.rand((3, n, n, n), device="cuda", generator=g) - 0.5)
+    if duct:
+        u0[:, torch.from_numpy(solid).cuda()] = 0.0
     x, pre = sim.init_equilibrium(rho0, u0)
     del rho0, u0
     lam_next = torch.randn((q, n, n, n), device="cuda", generator=g)
@@ -295,9 +301,18 @@ def test_full_size_adjoint_sampled_nodes(q):
     sim.adjoint_step(x, lam_next, lam, dLdF, dLdw)
     pre = sim.gather(x, out=pre)
     rng = np.random.default_rng(4)
-    idx = rng.integers(0, n**3, 2048)
-    idx[:4] = [0, n - 1, n * n - 1, n**3 - 1]
+    if duct:   # fluid nodes, a quarter of them beside a wall
+        z = rng.integers(1, n - 1, 2048)
+        y = rng.integers(1, n - 1, 2048)
+        xx = rng.integers(0, n, 2048)
+        z[:512:2], y[1:512:2] = 1 + (n - 3) * rng.integers(0, 2, 256), 1 + (n - 3) * rng.integers(0, 2, 256)
+        z[:4], y[:4], xx[:4] = [1, 1, n - 2, n - 2], [1, n - 2, 1, n - 2], [0, n - 1, 0, n - 1]
+        idx = z * n * n + y * n + xx
+    else:
+        idx = rng.integers(0, n**3, 2048)
+        idx[:4] = [0, n - 1, n * n - 1, n**3 - 1]
     z, y, xx = idx // (n * n), (idx // n) % n, idx % n
+    assert not solid.reshape(-1)[idx].any()
     idx_t = torch.from_numpy(idx).to("cuda")
     f_in = pre.reshape(q, -1)[:, idx_t].double().cpu().numpy().T            # (nodes, q)
     Fs = F.reshape(3, -1)[:, idx_t].double().cpu().numpy().T                 # (nodes, 3)
@@ -305,10 +320,13 @@ def test_full_size_adjoint_sampled_nodes(q):
     got_F = dLdF.reshape(3, -1)[:, idx_t].cpu().numpy().T
     ln = lam_next.reshape(q, -1)
     post = np.empty((len(idx), q))
+    sflat = solid.reshape(-1)
     for a in range(q):
         ex, ey, ez = (int(c) for c in lat.E[a])
         nb = ((z + ez) % n) * n * n + ((y + ey) % n) * n + (xx + ex) % n
-        post[:, a] = ln[a, torch.from_numpy(nb).to("cuda")].double().cpu().numpy()
+        fwd = ln[a, torch.from_numpy(nb).to("cuda")].double().cpu().numpy()
+        back = ln[lat.opp[a], idx_t].double().cpu().numpy()
+        post[:, a] = np.where(sflat[nb], back, fwd)
     del x, pre, lam, lam_next, dLdF
     torch.cuda.empty_cache()
     # lam_b = sum_a post_a dC_a/dfbar_b: every b at once, one complex-step column each
@@ -320,7 +338,7 @@ def test_full_size_adjoint_sampled_nodes(q):
     want_F = np.einsum("na,nca->nc", post, CF.imag / H)
     err = np.abs(got - want).max() / np.abs(want).max()
     err_F = np.abs(got_F - want_F).max() / np.abs(want_F).max()
-    print(f"adjoint full512 q{q}: lam rel err {err:.2e}, dL/dF rel err {err_F:.2e}", flush=True)
+    print(f"adjoint full512 q{q} duct={duct}: lam rel err {err:.2e}, dL/dF rel err {err_F:.2e}", flush=True)
     assert err < 1e-5 and err_F < 1e-5
 
 
