@@ -274,35 +274,62 @@ def test_misaligned_buffers_rejected():
     assert int(torch.count_nonzero(short)) == 0
 
 
-@pytest.mark.parametrize("q,prec", [(27, F32), (15, F32), (27, F16), (15, BF16)])
-def test_full_size_sampled_nodes(q, prec):
+@pytest.mark.parametrize("q,prec,duct", [(27, F32, False), (15, F32, False), (27, F16, False), (15, BF16, False),
+                                          (27, F32, True)])
+def test_full_size_sampled_nodes(q, prec, duct):
     # The benchmark configuration: 512^3 FP32 D3Q27 (and D3Q15) with the
     # Kolmogorov force field F_x = 1e-6 sin(2 pi 4 y / 512), shear rate 1.9,
-    # and the same lattice with 16-bit deviation storage.  One step from a
-    # perturbed state; the oracle collides 4096 sampled nodes from the
+    # the same lattice with 16-bit deviation storage, and (duct) inside the
+    # square duct of the benchmark's wall-bounded measurement.  One step from a
+    # perturbed state; the oracle collides 4096 sampled fluid nodes from the
     # pre-collision populations the GPU pulled (decoded, for 16-bit storage).
-    print(f"case full512 q{q} p{prec}", flush=True)
+    # With walls the pulled populations themselves are checked first, bit for
+    # bit, against the stored state streamed by the half-way bounce-back rule.
+    print(f"case full512 q{q} p{prec} duct={duct}", flush=True)
     n = 512
-    sim = gpu_setup(q, (n, n, n), prec, shear_rates(q, 1.9))
+    lat = LATTICES[q]
+    solid = inp.duct_mask(n, n, n) if duct else None
+    sim = gpu_setup(q, (n, n, n), prec, shear_rates(q, 1.9), None, solid)
     F = torch.from_numpy(inp.kolmogorov_force(n)).to("cuda", torch.float32)
     sim.set_force(F)
     rho0 = torch.ones((n, n, n), device="cuda", dtype=torch.float32)
     g = torch.Generator(device="cuda").manual_seed(1)
     u0 = 0.03 * (torch.rand((3, n, n, n), device="cuda", generator=g) - 0.5)
+    if duct:
+        u0[:, torch.from_numpy(solid).cuda()] = 0.0
     f_post, f_pre = sim.init_equilibrium(rho0, u0)
     del u0, rho0
     out = sim.populations()
     sim.step(f_post, out)
     pre = sim.gather(f_post, out=f_pre)
     rng = np.random.default_rng(3)
-    idx = rng.integers(0, n**3, 4096)
-    idx[:4] = [0, n - 1, n * n - 1, n**3 - 1]          # corners of the periodic box
+    if duct:   # fluid nodes, half of them beside a wall
+        z, y, xx = rng.integers(1, n - 1, 4096), rng.integers(1, n - 1, 4096), rng.integers(0, n, 4096)
+        z[:2048:2] = 1 + (n - 3) * rng.integers(0, 2, 1024)
+        y[1:2048:2] = 1 + (n - 3) * rng.integers(0, 2, 1024)
+        idx = z * n * n + y * n + xx
+    else:
+        idx = rng.integers(0, n**3, 4096)
+        idx[:4] = [0, n - 1, n * n - 1, n**3 - 1]          # corners of the periodic box
     idx_t = torch.from_numpy(idx).to("cuda")
     f_in = pre.reshape(q, -1)[:, idx_t].double().cpu().numpy().T
+    if duct:
+        zz, yy, xs = idx // (n * n), (idx // n) % n, idx % n
+        sflat = solid.reshape(-1)
+        assert not sflat[idx].any()
+        stored = sim.export_populations(f_post).reshape(q, -1)
+        for a in range(q):
+            ex, ey, ez = (int(c) for c in lat.E[a])
+            src = ((zz - ez) % n) * n * n + ((yy - ey) % n) * n + (xs - ex) % n
+            fwd = stored[a, torch.from_numpy(src).to("cuda")].double().cpu().numpy()
+            back = stored[lat.opp[a], idx_t].double().cpu().numpy()
+            assert np.array_equal(f_in[:, a], np.where(sflat[src], back, fwd)), a
+        del stored
+        torch.cuda.empty_cache()
     post = sim.export_populations(out, out=f_pre)          # pre no longer needed past this point
     f_gpu = post.reshape(q, -1)[:, idx_t].double().cpu().numpy().T
     Fs = F.reshape(3, -1)[:, idx_t].double().cpu().numpy().T
-    want = collision.collide(LATTICES[q], f_in, Fs, shear_rates(q, 1.9))
+    want = collision.collide(lat, f_in, Fs, shear_rates(q, 1.9))
     if prec == F32:
         assert np.abs(f_gpu - want).max() < 2e-6
     else:   # the stored deviation f - w_a rounded to 16 bits: half an ulp of it, plus FP32 arithmetic
