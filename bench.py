@@ -13,8 +13,8 @@ force loads), the FP64 CPU oracle timed on a bounded sample, the
 adjoint/forward time ratio of a 100-step checkpointed adjoint, and the
 per-launch step time of every lattice/storage variant on the same workload,
 two-buffer and in-place, of the FP32 adjoint step of both lattices, and
-(`walls`) of the step, the adjoint step and the wall-layout sensitivity of
-the same workload inside a square duct.
+(`walls`) of the step (two-buffer and in place), the adjoint step and the
+wall-layout sensitivity of the same workload inside a square duct.
 
 Accuracy, measured in the same run: every variant's state after its timed
 steps against the FP64 variant's (velocity relative L2, kinetic energy), the
@@ -358,7 +358,18 @@ def wall_sweep(n, launches=6):
         gbs = bpn * n**3 / (ms * 1e-3) / 1e9
         out[name] = {"ms": round(ms, 4), "bytes_per_node": bpn, "GBs": round(gbs, 1),
                      "frac": round(gbs / HBM_PEAK_GBS, 4)}
-    del sim, x, x1, lam_a, lam_b, bufs, xs, dLdF, dphi
+    del x, x1, lam_a, lam_b, bufs, xs, dLdF, dphi
+    torch.cuda.empty_cache()
+    # the same duct stepped in place (one buffer: collide phase, scatter phase)
+    b = sim.init_equilibrium_inplace(torch.ones((n, n, n), device=dev), torch.zeros((3, n, n, n), device=dev))
+    for i in range(2):
+        sim.step_inplace(b, i & 1)
+    t_in = _launch_ms(lambda i: sim.step_inplace(b, i & 1), 2 * (launches // 2), per_launch=True)
+    ms_even, ms_odd = sum(t_in[0::2]) / len(t_in[0::2]), sum(t_in[1::2]) / len(t_in[1::2])
+    gbs = 228 * n**3 / ((ms_even + ms_odd) / 2 * 1e-3) / 1e9
+    out["inplace"] = {"ms_collide_phase": round(ms_even, 4), "ms_scatter_phase": round(ms_odd, 4),
+                      "bytes_per_node": 228, "GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    del sim, b
     torch.cuda.empty_cache()
     return out
 
