@@ -616,12 +616,15 @@ __global__ __launch_bounds__(CMLBM_STEP_BLOCK) void k_step_inplace(StepArgs<type
           }
           if constexpr (MASK) {
             // x + e_a = x - e_abar solid: the population returns into slot abar
-            // of x.  Both stores are issued and each lane drops the one that
-            // does not apply (offset past the bound): no branch, so neither the
-            // descriptor nor the uniform offset becomes a per-lane choice.
+            // of x.  The neighbour store is issued for every lane, the lanes
+            // that bounce dropping theirs (offset past the bound); the bounce
+            // store only by wavefronts with a bouncing lane (a wave-uniform
+            // branch), the other lanes dropping it.  Neither the descriptor nor
+            // the uniform offset ever becomes a per-lane choice.
             const bool back = (solid >> ab) & 1u;
-            buf_store<kInplaceAux>(v[a], rs, back ? cbase : kDropOffset, uint32_t(ab) * lenB);
             buf_store<kInplaceAux>(v[a], rt, back ? kDropOffset : off, soff);
+            if (__builtin_amdgcn_ballot_w64(back))
+              buf_store<kInplaceAux>(v[a], rs, back ? cbase : kDropOffset, uint32_t(ab) * lenB);
           } else {
             buf_store<kInplaceAux>(v[a], rt, off, soff);
           }
@@ -765,11 +768,19 @@ __global__ __launch_bounds__(CMLBM_STEP_BLOCK) void k_scatter_periodic(StepArgs<
     // (same contraction as the two-buffer step).
     pin_all<ST, Q>(v);
   }
-  // One lane writes both edges (lane 63's values read across the wavefront).
+  // Lane 63's values, read with every lane active: inside the lane-0 branch
+  // below, the compiler may finish a value (extract a 16-bit half from a
+  // packed register) under that branch's single lane, and the read of lane 63
+  // would then see a register that lane never wrote.  The reads are
+  // convergent, so the compiler keeps them, and what feeds them, out here.
+  T up63[Q];
+#pragma unroll
+  for (int a = 0; a < Q; ++a) up63[a] = Lattice<Q>::e(a).x > 0 ? read_lane63(v[a]) : T(0);
+  // One lane writes both edges.
   if (lane == 0) {
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
-      if (Lattice<Q>::e(a).x > 0) edge_up[wave][a] = read_lane63(v[a]);
+      if (Lattice<Q>::e(a).x > 0) edge_up[wave][a] = up63[a];
       if (Lattice<Q>::e(a).x < 0) edge_dn[wave][a] = v[a];
     }
   }
@@ -789,6 +800,12 @@ __global__ __launch_bounds__(CMLBM_STEP_BLOCK) void k_scatter_periodic(StepArgs<
   const uint32_t off_before = x == x0 ? (bp * uint32_t(Q) + (xp - bp)) * sz : kDrop;
   const uint32_t len_after = min(64u, nx - bn) * sz, len_before = min(64u, nx - bp) * sz;
   const int wprev = wave > 0 ? wave - 1 : 0, wnext = wave + 1 < kWaves ? wave + 1 : wave;
+  // Only the wavefront holding the segment's last node (first node) has a
+  // store across the segment's end to issue: a wave-uniform branch skips
+  // those instructions in the others.
+  const uint32_t wv = __builtin_amdgcn_readfirstlane(uint32_t(wave));
+  const bool has_last = x0 + 64u * wv <= xend - 1 && xend - 1 < x0 + 64u * (wv + 1);
+  const bool has_first = wv == 0;
 #pragma unroll
   for (int a = 0; a < Q; ++a) {
     const Vel e = Lattice<Q>::e(a);
@@ -797,10 +814,10 @@ __global__ __launch_bounds__(CMLBM_STEP_BLOCK) void k_scatter_periodic(StepArgs<
       buf_store<kInplaceAux>(v[a], rt, off_own, uint32_t(a) * lenB);
     } else if (e.x > 0) {              // slot a of x receives fbar~_a(x - 1)
       buf_store<kInplaceAux>(from_lane_below(v[a], edge_up[wprev][a]), rt, off_prev, uint32_t(a) * lenB);
-      buf_store<kInplaceAux>(v[a], rt, off_after, uint32_t(a) * len_after);      // to x + 1
+      if (has_last) buf_store<kInplaceAux>(v[a], rt, off_after, uint32_t(a) * len_after);      // to x + 1
     } else {                           // slot a of x receives fbar~_a(x + 1)
       buf_store<kInplaceAux>(from_lane_above(v[a], edge_dn[wnext][a]), rt, off_next, uint32_t(a) * lenB);
-      buf_store<kInplaceAux>(v[a], rt, off_before, uint32_t(a) * len_before);    // to x - 1
+      if (has_first) buf_store<kInplaceAux>(v[a], rt, off_before, uint32_t(a) * len_before);    // to x - 1
     }
   }
   if constexpr (TOT) {
