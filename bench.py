@@ -18,7 +18,8 @@ wall-layout sensitivity of the same workload inside a square duct.
 
 Accuracy, measured in the same run: every variant's state after its timed
 steps against the FP64 variant's (velocity relative L2, kinetic energy), the
-FP16 deviations' subnormal fraction, and (`accuracy`) every variant and the
+count of non-finite stored populations of every final state, the FP16
+deviations' subnormal fraction, and (`accuracy`) every variant and the
 FP64/FP32 adjoint on the CPU-baseline sample against the oracle's own result
 of that sample, which the CPU-baseline leg computes beside its timing.
 """
@@ -230,8 +231,8 @@ def variant_sweep(n, steps=30, warmup=3):
     two-buffer step and for the in-place step (mean of its two phases).  Each
     variant's state after its warmup + timed two-buffer steps is compared with
     the FP64 variant's state after the same steps (velocity relative L2, mean
-    kinetic energy), and for FP16 deviation storage the stored values'
-    subnormal and zero fractions are counted."""
+    kinetic energy), its non-finite stored populations are counted, and for
+    FP16 deviation storage the stored values' subnormal and zero fractions."""
     import torch
     import lbm_inputs as inp
     from paper_1202_6081_amd import cmlbm
@@ -254,7 +255,7 @@ def variant_sweep(n, steps=30, warmup=3):
             ms = _launch_ms(lambda i: sim.step(bufs[(warmup + i) & 1], bufs[(warmup + i + 1) & 1]), steps)
             last = bufs[(warmup + steps) & 1]
             u, ke = _velocity_and_ke(sim, last)
-            acc = {"steps": warmup + steps, "ke": ke}
+            acc = {"steps": warmup + steps, "ke": ke, "nonfinite_populations": sim.check_finite(last)}
             if prec == cmlbm.F64:
                 u64, ke64 = u, ke
             else:
@@ -473,6 +474,7 @@ def main():
     achieved = BYTES_PER_NODE * N / (kernel_ms * 1e-3) / 1e9
     traffic = measured_traffic(N)
     tot = sim.totals(last)
+    nonfinite = sim.check_finite(last)
 
     result = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
@@ -488,6 +490,7 @@ def main():
                      "algorithmic_bytes_per_node": BYTES_PER_NODE, "kernel": "k_step<27,StF32,false>",
                      "kernel_ms_avg": round(kernel_ms, 4)},
         "mass_total_fp64": tot[0],
+        "nonfinite_populations": nonfinite,
         "hbm_ceiling": None if ceiling is None else {
             "step_traffic_GBs": ceiling["step_traffic_pull_GBs"],
             "step_traffic_own_node_GBs": ceiling["step_traffic_own_node_GBs"],

@@ -310,6 +310,19 @@ cmlbm_status cmlbm_wall_sensitivity(cmlbm_sim *sim, const void *f_post_prev, con
 cmlbm_status cmlbm_wall_sensitivity_post(cmlbm_sim *sim, const void *f_post, const void *lam,
                                          double *dLdphi_dev, void *stream);
 
+/* Stability check (no operation of the paper: the relaxation rates of Sec. 7
+ * lie in (0, 2) and are tuned for stability, which they do not guarantee):
+ * *nonfinite = the number of stored populations of fluid nodes (every node
+ * without a mask) in f_buf whose stored value is NaN or +-Inf.  f_buf is any
+ * population buffer (blocked layout, storage type): the post-collision buffer
+ * of cmlbm_step, or an in-place buffer in either phase.  For the 16-bit
+ * deviation formats the stored deviation fbar_a - w_a is checked; FP16 rounds
+ * |fbar_a - w_a| > 65504 to +-Inf, so overflow counts too.  One NaN
+ * population makes every population of the node that pulls it NaN in the
+ * next step, so 0 after a run means no node has diverged.  Reads f_buf once;
+ * host output; synchronizes `stream`.  Errors: EINVAL (NULL, misaligned). */
+cmlbm_status cmlbm_check_finite(cmlbm_sim *sim, const void *f_buf, int64_t *nonfinite, void *stream);
+
 /* Kinetic-energy loss of a pre-collision state: *out = sum over fluid nodes of
  * |rho u|^2 / (2 rho), rho u = sum fbar e + F/2 (Eqs. densitycalculation,
  * velocitycalculation), accumulated in FP64.  f_pre: "real" [q][nz][ny][nx]

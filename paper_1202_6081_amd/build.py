@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcmlbm.so")
 
-SOURCES = ["api.cpp", "kernels.hip"]
+SOURCES = ["api.cpp", "kernels.hip", "checks.hip"]
 # -packed-fp32-ops: no v_pk_* FP32 instructions are generated.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

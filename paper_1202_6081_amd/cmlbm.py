@@ -64,6 +64,7 @@ def load_library():
         "cmlbm_adjoint_step": (i, [vp, vp, vp, vp, vp, vp, vp]),
         "cmlbm_wall_sensitivity": (i, [vp, vp, vp, vp, vp]),
         "cmlbm_wall_sensitivity_post": (i, [vp, vp, vp, vp, vp]),
+        "cmlbm_check_finite": (i, [vp, vp, ctypes.POINTER(ctypes.c_int64), vp]),
         "cmlbm_kinetic_energy_sum": (i, [vp, vp, ctypes.POINTER(d), vp]),
         "cmlbm_kinetic_energy_seed": (i, [vp, vp, d, vp, vp, vp]),
         "cmlbm_init_adjoint": (i, [vp, vp, vp, vp, vp]),
@@ -88,7 +89,7 @@ def exported_symbols():
             "cmlbm_init_equilibrium_inplace", "cmlbm_step_inplace", "cmlbm_step_inplace_totals",
             "cmlbm_run_inplace", "cmlbm_macroscopic_pre", "cmlbm_totals_pre",
             "cmlbm_adjoint_step", "cmlbm_wall_sensitivity", "cmlbm_wall_sensitivity_post",
-            "cmlbm_kinetic_energy_sum", "cmlbm_kinetic_energy_seed",
+            "cmlbm_check_finite", "cmlbm_kinetic_energy_sum", "cmlbm_kinetic_energy_seed",
             "cmlbm_init_adjoint",
             "cmlbm_status_string", "cmlbm_last_error", "cmlbm_version"]
 
@@ -264,6 +265,12 @@ def cmlbm_wall_sensitivity(h, f_post_prev, lam_next, dLdphi, stream=None):
 
 def cmlbm_wall_sensitivity_post(h, f_post, lam, dLdphi, stream=None):
     _check(load_library().cmlbm_wall_sensitivity_post(h, _ptr(f_post), _ptr(lam), _ptr(dLdphi), _stream(stream)), h)
+
+
+def cmlbm_check_finite(h, f_buf, stream=None):
+    out = ctypes.c_int64(0)
+    _check(load_library().cmlbm_check_finite(h, _ptr(f_buf), ctypes.byref(out), _stream(stream)), h)
+    return out.value
 
 
 def cmlbm_kinetic_energy_sum(h, f_pre, stream=None):
@@ -483,6 +490,11 @@ class Sim:
         self._realpop(lam, "lam")
         self._need(dLdphi, torch.float64, self.nodes, "dLdphi")
         cmlbm_wall_sensitivity_post(self.h, f_post, lam, dLdphi, stream)
+
+    def check_finite(self, f_buf, stream=None):
+        """Number of NaN or +-Inf stored populations of fluid nodes in a
+        population buffer (two-buffer or in-place, either phase)."""
+        return cmlbm_check_finite(self.h, self._pop(f_buf, "f_buf"), stream)
 
     def kinetic_energy_sum(self, f_pre, stream=None):
         return cmlbm_kinetic_energy_sum(self.h, self._realpop(f_pre, "f_pre"), stream)

@@ -11,6 +11,7 @@
 #include <initializer_list>
 #include <string>
 
+#include "checks.hpp"
 #include "kernels.hpp"
 
 struct cmlbm_sim {
@@ -598,6 +599,26 @@ cmlbm_status cmlbm_wall_sensitivity(cmlbm_sim* s, const void* f_post_prev, const
 cmlbm_status cmlbm_wall_sensitivity_post(cmlbm_sim* s, const void* f_post, const void* lam, double* dLdphi_dev,
                                          void* stream) {
   return wall_sensitivity(s, f_post, lam, dLdphi_dev, true, stream);
+}
+
+cmlbm_status cmlbm_check_finite(cmlbm_sim* s, const void* f_buf, int64_t* nonfinite, void* stream) {
+  CMLBM_WORK_ENTRY(s);
+  if (!f_buf || !nonfinite) return fail(s, CMLBM_EINVAL, "NULL buffer");
+  CMLBM_CHECK_ALIGNED(s, {f_buf, pop_bytes(s)});
+  static const cmlbm::StoreFormat fmt[4] = {cmlbm::StoreFormat::F64, cmlbm::StoreFormat::F32,
+                                            cmlbm::StoreFormat::F16, cmlbm::StoreFormat::BF16};
+  // The result slot of the synchronous reductions (32 bytes) holds the counter.
+  auto* count = reinterpret_cast<unsigned long long*>(s->totals_out);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = cmlbm::launch_check_finite(s->q, fmt[s->prec], s->g, f_buf, s->mask, count, st);
+  if (e != hipSuccess) return check_hip(s, e, "check_finite");
+  unsigned long long host = 0;
+  e = hipMemcpyAsync(&host, count, sizeof(host), hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess) return check_hip(s, e, "check_finite copy");
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return check_hip(s, e, "check_finite sync");
+  *nonfinite = int64_t(host);
+  return ok(s);
 }
 
 cmlbm_status cmlbm_kinetic_energy_sum(cmlbm_sim* s, const void* f_pre, double* out, void* stream) {

@@ -4,12 +4,14 @@
  *   - total mass is conserved and total momentum grows by N F per step
  *     (Eqs. densitycalculation, velocitycalculation: the collision conserves
  *     mass and momentum, the source adds F at every node);
- *   - the in-place run ends in the same FP64 totals as the two-buffer run;
+ *   - the in-place run ends in the same FP64 totals as the two-buffer run,
+ *     and neither final buffer holds a non-finite population;
  *   - argument errors (aliasing, counts, rates, misaligned pointers) come back
  *     as CMLBM_EINVAL with a message, before any launch.
  * Prints "abi_from_c ok" and exits 0 on success. */
 #include <hip/hip_runtime_api.h>
 #include <math.h>
+#include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
 
@@ -77,6 +79,11 @@ int main(void) {
   ok(s, cmlbm_run_inplace(s, fin, steps, NULL), "run_inplace");
   ok(s, cmlbm_totals_pre(s, fin, t2, NULL), "totals_pre");
   for (int c = 0; c < 4; ++c) CHECK(t2[c] == t1[c], "in-place total %d: %.17g vs %.17g", c, t2[c], t1[c]);
+  int64_t nonfinite = -1;
+  ok(s, cmlbm_check_finite(s, in_b ? fb : fa, &nonfinite, NULL), "check_finite");
+  CHECK(nonfinite == 0, "%lld non-finite populations after the two-buffer run", (long long)nonfinite);
+  ok(s, cmlbm_check_finite(s, fin, &nonfinite, NULL), "check_finite");
+  CHECK(nonfinite == 0, "%lld non-finite populations after the in-place run", (long long)nonfinite);
 
   /* errors */
   CHECK(cmlbm_step(s, fa, fa, NULL) == CMLBM_EINVAL, "aliased step accepted");
