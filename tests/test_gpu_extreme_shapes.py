@@ -1,0 +1,101 @@
+"""GPU parity on lattice shapes at the limits the library accepts.
+
+* The longest row: nx = 65535, the largest dimension per axis.  A row holds
+  1023 full 64-node sub-blocks and one of 63 nodes, the step cuts it into 256
+  row segments, and its FP64 populations span 14 MB, all addressed by 32-bit
+  offsets inside the row.
+* A million 3-node rows: one ragged sub-block per row, 2^20 row segments, and
+  more lanes idle than busy.
+
+One step from a perturbed state (Eq. cascadedstreaming1, then Eq.
+cascadedcollision1): the pulled pre-collision populations must equal the
+stored state streamed periodically, bit for bit, over the whole lattice; the
+oracle then collides sampled nodes (row ends, sub-block and segment edges,
+random nodes) from those populations: 1e-12 relative in FP64, 2e-6 absolute in
+FP32.  Two steps on one buffer in place must give the two-buffer run's
+populations bit for bit.
+"""
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import gpu_setup, shear_rates, to_dev
+from oracle import collision
+from oracle.lattice import LATTICES
+
+pytestmark = pytest.mark.gpu
+
+F64, F32 = 0, 1
+
+CASES = [
+    # q, precision, (nz, ny, nx), force
+    (27, F64, (2, 3, 65535), "field"),
+    (15, F32, (3, 2, 65535), "uniform"),
+    (27, F32, (1024, 1024, 3), "field"),
+]
+
+
+def _ids(c):
+    return f"q{c[0]}-p{c[1]}-{'x'.join(map(str, c[2]))}-{c[3]}"
+
+
+def _sample(shape, rng):
+    """Flat node indices: the row ends and the sub-block and row-segment
+    edges of the first, the last and 64 random rows, plus 1024 random nodes."""
+    nz, ny, nx = shape
+    rows = ny * nz
+    xs = sorted({x for x in (0, 1, 62, 63, 64, 65, 255, 256, nx - 65, nx - 64, nx - 63, nx - 2, nx - 1)
+                 if 0 <= x < nx})
+    pick_rows = np.unique(np.concatenate([[0, rows - 1], rng.integers(0, rows, 64)]))
+    idx = [r * nx + x for r in pick_rows for x in xs]
+    idx += list(rng.integers(0, nx * rows, 1024))
+    return np.unique(np.array(idx, dtype=np.int64))
+
+
+@pytest.mark.parametrize("case", CASES, ids=[_ids(c) for c in CASES])
+def test_extreme_shape_step(case):
+    q, prec, shape, fkind = case
+    print(f"case extreme {_ids(case)}", flush=True)
+    lat = LATTICES[q]
+    rng = np.random.default_rng(5)
+    F = (np.array([3e-5, -1e-5, 2e-5]) if fkind == "uniform"
+         else 2e-5 * rng.standard_normal((3,) + shape))
+    rates = shear_rates(q, 1.9)
+    sim = gpu_setup(q, shape, prec, rates, F)
+    rho0 = 1.0 + 0.01 * rng.standard_normal(shape)
+    u0 = 0.04 * (rng.random((3,) + shape) - 0.5)
+    f_post, _ = sim.init_equilibrium(to_dev(rho0, sim.real), to_dev(u0, sim.real))
+
+    # streaming: the gathered pre-collision state is the stored state moved
+    # by e_a, periodic in every axis
+    stored = sim.export_populations(f_post).cpu().numpy()
+    pre = sim.gather(f_post).cpu().numpy()
+    for a in range(q):
+        ex, ey, ez = (int(c) for c in lat.E[a])
+        assert np.array_equal(pre[a], np.roll(stored[a], shift=(ez, ey, ex), axis=(0, 1, 2))), a
+    del stored
+
+    # collision of sampled nodes against the oracle
+    out = sim.populations()
+    sim.step(f_post, out)
+    post = sim.export_populations(out).cpu().numpy().reshape(q, -1)
+    idx = _sample(shape, rng)
+    f_in = pre.reshape(q, -1)[:, idx].T.astype(np.float64)
+    Fs = np.broadcast_to(F, (idx.size, 3)) if fkind == "uniform" else F.reshape(3, -1)[:, idx].T
+    want = collision.collide(lat, f_in, np.ascontiguousarray(Fs, dtype=np.float64), rates)
+    got = post[:, idx].T.astype(np.float64)
+    if prec == F64:
+        assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+    else:
+        assert np.abs(got - want).max() < 2e-6
+    del pre, post
+
+    # two steps in place against two two-buffer steps
+    last = sim.run(f_post, out, 2)
+    two_buffer = sim.gather(last).cpu().numpy()
+    g = sim.init_equilibrium_inplace(to_dev(rho0, sim.real), to_dev(u0, sim.real))
+    sim.run_inplace(g, 2)
+    in_place = sim.export_populations(g).cpu().numpy()
+    assert np.array_equal(two_buffer, in_place)
+    sim.close()
+    torch.cuda.empty_cache()
