@@ -99,3 +99,60 @@ def test_extreme_shape_step(case):
     assert np.array_equal(two_buffer, in_place)
     sim.close()
     torch.cuda.empty_cache()
+
+
+ADJ_CASES = [(27, F64, (2, 3, 65535)), (15, F64, (3, 2, 65535)), (27, F32, (1024, 1024, 3))]
+
+
+@pytest.mark.parametrize("case", ADJ_CASES, ids=[_ids(c + ("field",)) for c in ADJ_CASES])
+def test_extreme_shape_adjoint_step(case):
+    """One adjoint step on the same shapes: at the sampled nodes, lam(x) and
+    dL/dF(x) against the transposed Jacobian of the oracle's collision (complex
+    step at the pre-collision state the GPU pulled) applied to the
+    reverse-streamed adjoint lam_next(x + e_a)_a, periodic.  1e-10 relative in
+    FP64, 1e-5 in FP32."""
+    q, prec, shape = case
+    print(f"case extreme adjoint {_ids(case + ('field',))}", flush=True)
+    H = 1e-30
+    lat = LATTICES[q]
+    nz, ny, nx = shape
+    rng = np.random.default_rng(6)
+    F = 2e-5 * rng.standard_normal((3,) + shape)
+    om = shear_rates(q, 1.9)
+    sim = gpu_setup(q, shape, prec, om, F)
+    rho0 = 1.0 + 0.01 * rng.standard_normal(shape)
+    u0 = 0.04 * (rng.random((3,) + shape) - 0.5)
+    x, _ = sim.init_equilibrium(to_dev(rho0, sim.real), to_dev(u0, sim.real))
+    lam_next_h = rng.standard_normal((q,) + shape)
+    lam_next = to_dev(lam_next_h, sim.real)
+    lam = sim.real_populations()
+    dLdF = torch.zeros((3,) + shape, dtype=torch.float64, device="cuda")
+    dLdw = torch.zeros(q - 4, dtype=torch.float64, device="cuda")
+    sim.adjoint_step(x, lam_next, lam, dLdF, dLdw)
+    pre = sim.gather(x).cpu().numpy().reshape(q, -1)
+    idx = _sample(shape, rng)
+    z, y, xx = idx // (nx * ny), (idx // nx) % ny, idx % nx
+    f_in = pre[:, idx].T.astype(np.float64)
+    Fs = F.reshape(3, -1)[:, idx].T
+    if prec == F32:   # the force as the device holds it
+        Fs = Fs.astype(np.float32).astype(np.float64)
+    ln = lam_next.double().cpu().numpy().reshape(q, -1)
+    post = np.empty((idx.size, q))
+    for a in range(q):
+        ex, ey, ez = (int(c) for c in lat.E[a])
+        post[:, a] = ln[a, ((z + ez) % nz) * nx * ny + ((y + ey) % ny) * nx + (xx + ex) % nx]
+    got = lam.double().cpu().numpy().reshape(q, -1)[:, idx].T
+    got_F = dLdF.cpu().numpy().reshape(3, -1)[:, idx].T
+    fc = f_in[:, None, :] + 1j * H * np.eye(q)[None, :, :]
+    Cc = collision.collide(lat, fc, np.repeat(Fs[:, None, :], q, axis=1).astype(complex), np.array(om, dtype=complex))
+    want = np.einsum("na,nba->nb", post, Cc.imag / H)
+    Fc = Fs[:, None, :] + 1j * H * np.eye(3)[None, :, :]
+    CF = collision.collide(lat, np.repeat(f_in[:, None, :], 3, axis=1).astype(complex), Fc, np.array(om, dtype=complex))
+    want_F = np.einsum("na,nca->nc", post, CF.imag / H)
+    err = np.abs(got - want).max() / np.abs(want).max()
+    err_F = np.abs(got_F - want_F).max() / np.abs(want_F).max()
+    print(f"extreme adjoint {_ids(case + ('field',))}: lam rel err {err:.2e}, dL/dF rel err {err_F:.2e}", flush=True)
+    tol = 1e-10 if prec == F64 else 1e-5
+    assert err < tol and err_F < tol
+    sim.close()
+    torch.cuda.empty_cache()
