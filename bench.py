@@ -474,7 +474,10 @@ def main():
     achieved = BYTES_PER_NODE * N / (kernel_ms * 1e-3) / 1e9
     traffic = measured_traffic(N)
     tot = sim.totals(last)
-    nonfinite = sim.check_finite(last)
+    torch.cuda.synchronize()
+    t_chk = time.perf_counter()
+    nonfinite = sim.check_finite(last)      # synchronizes
+    check_ms = (time.perf_counter() - t_chk) * 1e3
 
     result = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
@@ -491,6 +494,7 @@ def main():
                      "kernel_ms_avg": round(kernel_ms, 4)},
         "mass_total_fp64": tot[0],
         "nonfinite_populations": nonfinite,
+        "check_finite_ms": round(check_ms, 3),
         "hbm_ceiling": None if ceiling is None else {
             "step_traffic_GBs": ceiling["step_traffic_pull_GBs"],
             "step_traffic_own_node_GBs": ceiling["step_traffic_own_node_GBs"],

@@ -35,15 +35,15 @@ __global__ void k_count_zero(unsigned long long* count) { *count = 0ull; }
 template <int Q, typename U>
 __global__ __launch_bounds__(kCheckBlock) void k_check_finite(Geom g, const U* buf, const uint8_t* mask, U ones,
                                                               unsigned long long* count) {
-  const uint32_t nx = uint32_t(g.nx);
+  // N < 2^31 (the library's limit), so node indices and rows fit 32 bits
+  const uint32_t nx = uint32_t(g.nx), N = uint32_t(g.N);
   const uint64_t rowQ = uint64_t(nx) * Q;
   uint32_t bad = 0;
-  for (uint64_t n = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; n < g.N;
-       n += uint64_t(gridDim.x) * blockDim.x) {
+  for (uint32_t n = blockIdx.x * blockDim.x + threadIdx.x; n < N; n += gridDim.x * blockDim.x) {
     if (mask && mask[n]) continue;
-    const uint64_t row = n / nx;
-    const uint32_t x = uint32_t(n - row * nx);
-    const U* rp = buf + row * rowQ;
+    const uint32_t row = n / nx;
+    const uint32_t x = n - row * nx;
+    const U* rp = buf + uint64_t(row) * rowQ;
 #pragma unroll
     for (int a = 0; a < Q; ++a) bad += (rp[row_offset<Q>(nx, a, x)] & ones) == ones ? 1u : 0u;
   }
