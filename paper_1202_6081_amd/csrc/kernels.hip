@@ -240,6 +240,15 @@ __device__ __forceinline__ void pull(const typename ST::T* __restrict__ fin, con
       nlen[i] = min(64u, nx - bb) * sz;
     }
     const T* own = fin + uint64_t(row0) * rowQ;
+    // bit a: x - e_a solid.  One round of mask loads ahead of the population
+    // loads, which then issue back to back (a mask byte tested per direction
+    // made each population load wait for its own mask load).  Direction 0
+    // reads the node's own slot 0 either way.
+    uint32_t solid = 0;
+    if constexpr (MASK) {
+#pragma unroll
+      for (int a = 1; a < Q; ++a) solid |= uint32_t(mask[st.node(Lattice<Q>::e(a), nx)] != 0) << a;
+    }
     // When every block of a row is full (nx a multiple of 64), the blocks of
     // the x-neighbours have the same direction stride lenB, and that part of
     // their offsets is wave-uniform too.
@@ -259,7 +268,7 @@ __device__ __forceinline__ void pull(const typename ST::T* __restrict__ fin, con
           else
             v = buf_load<T>(array_rsrc(rp, rowB), nbase[e.x + 1] + uint32_t(a) * nlen[e.x + 1], 0u);
         } else {
-          if (MASK && mask[st.node(e, nx)])
+          if (MASK && ((solid >> a) & 1u))
             v = ldb<T>(reinterpret_cast<const char*>(own) + uint32_t(opposite<Q>(a)) * lenB, cbase);
           else if (e.x == 0)
             v = ldb<T>(reinterpret_cast<const char*>(rp) + uint32_t(a) * lenB, cbase);
@@ -276,13 +285,18 @@ __device__ __forceinline__ void pull(const typename ST::T* __restrict__ fin, con
     else
       gather(std::false_type{});
   } else {
+    uint32_t solid = 0;   // bit a: x - e_a solid, as above
+    if constexpr (MASK) {
+#pragma unroll
+      for (int a = 1; a < Q; ++a) solid |= uint32_t(mask[st.node(Lattice<Q>::e(a), uint32_t(g.nx))] != 0) << a;
+    }
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
       const Vel e = Lattice<Q>::e(a);
       const T* rp = fin + uint64_t(st.row[e.y + 1][e.z + 1]) * rowQ;
       T v;
       if constexpr (MASK) {
-        if (mask[st.node(e, uint32_t(g.nx))])
+        if ((solid >> a) & 1u)
           v = ld32(fin + uint64_t(row0) * rowQ, in_row<Q>(uint32_t(g.nx), opposite<Q>(a), x));
         else
           v = ld32(rp, in_row<Q>(uint32_t(g.nx), a, st.xs[e.x + 1]));
@@ -1391,16 +1405,31 @@ __global__ __launch_bounds__(CMLBM_STEP_BLOCK) void k_wall_gather(AdjArgs<typena
   const T* fin = static_cast<const T*>(args.fpost);
   const uint32_t rowQB = nx * uint32_t(Q) * sz, rowB = nx * rz;
   const uint64_t N = per_item(g.N);
-  double acc = 0.0;
+  // all 3 (Q - 1) loads are issued before the first term is formed (the
+  // pins below): interleaved with the FP64 sums, the compiler let the loads
+  // in flight drain to a handful several times per node
+  T v[Q];
+  R own[Q], arrived[Q];
+  v[0] = T(0);
 #pragma unroll
   for (int a = 1; a < Q; ++a) {
     const Vel e = Lattice<Q>::e(a);
     const uint32_t ab = uint32_t(opposite<Q>(a));
     const uint32_t srow = up.row[e.y + 1][e.z + 1], xs = up.xs[e.x + 1];
-    const T v = buf_load<T>(array_rsrc(fin + uint64_t(srow) * nx * Q, rowQB), in_row<Q>(nx, a, xs) * sz, 0u);
-    const R own = buf_load<R>(array_rsrc(args.lam_next + uint64_t(ab) * N + uint64_t(srow) * nx, rowB), xs * rz, 0u);
-    const R arrived = buf_load<R>(array_rsrc(args.lam_next + uint64_t(a) * N + uint64_t(row) * nx, rowB), x * rz, 0u);
-    const double term = double(decode<ST, Q>(v, a)) * (double(own) - double(arrived));
+    v[a] = buf_load<T>(array_rsrc(fin + uint64_t(srow) * nx * Q, rowQB), in_row<Q>(nx, a, xs) * sz, 0u);
+    own[a] = buf_load<R>(array_rsrc(args.lam_next + uint64_t(ab) * N + uint64_t(srow) * nx, rowB), xs * rz, 0u);
+    arrived[a] = buf_load<R>(array_rsrc(args.lam_next + uint64_t(a) * N + uint64_t(row) * nx, rowB), x * rz, 0u);
+  }
+  pin_all<ST, Q>(v);
+#pragma unroll
+  for (int a = 1; a < Q; ++a) {
+    asm volatile("" : "+v"(own[a]));
+    asm volatile("" : "+v"(arrived[a]));
+  }
+  double acc = 0.0;
+#pragma unroll
+  for (int a = 1; a < Q; ++a) {
+    const double term = double(decode<ST, Q>(v[a], a)) * (double(own[a]) - double(arrived[a]));
     acc += ((solid >> a) & 1u) ? 0.0 : term;
   }
   dLdphi[uint64_t(row) * nx + x] += acc;
