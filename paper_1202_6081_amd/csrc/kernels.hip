@@ -879,13 +879,21 @@ __global__ __launch_bounds__(256) void k_convert(Geom g, const void* in, void* o
   const uint64_t rowQ = uint64_t(g.nx) * Q;
   for (uint32_t n = blockIdx.x * blockDim.x + threadIdx.x; n < g.N; n += gridDim.x * blockDim.x) {
     const uint32_t row = n / uint32_t(g.nx), x = n - row * uint32_t(g.nx);
+    // all Q loads first, then the stores: the buffers may alias as far as the
+    // compiler knows, so a store between two loads would make the second wait
+    if constexpr (EXPORT) {
+      R v[Q];
 #pragma unroll
-    for (int a = 0; a < Q; ++a) {
-      const uint64_t blk = uint64_t(row) * rowQ + in_row<Q>(uint32_t(g.nx), a, x);
-      if constexpr (EXPORT)
-        static_cast<R*>(out)[uint64_t(a) * g.N + n] = decode<ST, Q>(static_cast<const T*>(in)[blk], a);
-      else
-        static_cast<T*>(out)[blk] = encode<ST, Q>(static_cast<const R*>(in)[uint64_t(a) * g.N + n], a);
+      for (int a = 0; a < Q; ++a)
+        v[a] = decode<ST, Q>(static_cast<const T*>(in)[uint64_t(row) * rowQ + in_row<Q>(uint32_t(g.nx), a, x)], a);
+#pragma unroll
+      for (int a = 0; a < Q; ++a) static_cast<R*>(out)[uint64_t(a) * g.N + n] = v[a];
+    } else {
+      T v[Q];
+#pragma unroll
+      for (int a = 0; a < Q; ++a) v[a] = encode<ST, Q>(static_cast<const R*>(in)[uint64_t(a) * g.N + n], a);
+#pragma unroll
+      for (int a = 0; a < Q; ++a) static_cast<T*>(out)[uint64_t(row) * rowQ + in_row<Q>(uint32_t(g.nx), a, x)] = v[a];
     }
   }
 }
@@ -1091,16 +1099,22 @@ __global__ __launch_bounds__(256) void k_scatter_post(Geom g, const typename ST:
       continue;
     }
     const Stencil st(g, c, -1);    // x + e_a
+    // the mask bytes in one round, then every load, then the stores (the
+    // buffers may alias as far as the compiler knows)
+    uint32_t solid = 0;            // bit a: x + e_a solid
+    if constexpr (MASK) {
+#pragma unroll
+      for (int a = 1; a < Q; ++a) solid |= uint32_t(mask[st.node(Lattice<Q>::e(a), uint32_t(g.nx))] != 0) << a;
+    }
+    R v[Q];
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
       const uint32_t dst = st.node(Lattice<Q>::e(a), uint32_t(g.nx));
-      R v;
-      if (MASK && mask[dst])
-        v = fpre[uint64_t(opposite<Q>(a)) * g.N + n];
-      else
-        v = fpre[uint64_t(a) * g.N + dst];
-      fpost[base + in_row<Q>(uint32_t(g.nx), a, uint32_t(c.x))] = encode<ST, Q>(v, a);
+      const uint64_t at = ((solid >> a) & 1u) ? uint64_t(opposite<Q>(a)) * g.N + n : uint64_t(a) * g.N + dst;
+      v[a] = fpre[at];
     }
+#pragma unroll
+    for (int a = 0; a < Q; ++a) fpost[base + in_row<Q>(uint32_t(g.nx), a, uint32_t(c.x))] = encode<ST, Q>(v[a], a);
   }
 }
 
