@@ -54,6 +54,9 @@ def test_null_handle_and_out():
     assert lib.cmlbm_create(27, 4, 4, 4, 1, None) == -1
     assert lib.cmlbm_step(None, None, None, None) == -1
     assert lib.cmlbm_set_rates(None, None, 23) == -1
+    count = ctypes.c_int64(-7)
+    assert lib.cmlbm_check_finite(None, None, ctypes.byref(count), None) == -1
+    assert count.value == -7          # left untouched on error
     lib.cmlbm_destroy(None)
 
 
