@@ -6,10 +6,14 @@
   offsets inside the row.
 * A million 3-node rows: one ragged sub-block per row, 2^20 row segments, and
   more lanes idle than busy.
+* Both shapes with random walls (a fifth of the nodes solid): the masked pull,
+  which reads its neighbours' mask bytes in one round before its population
+  loads, on ragged rows.
 
 One step from a perturbed state (Eq. cascadedstreaming1, then Eq.
 cascadedcollision1): the pulled pre-collision populations must equal the
-stored state streamed periodically, bit for bit, over the whole lattice; the
+stored state streamed periodically, bit for bit, over the whole lattice (with
+walls, the half-way bounce-back of Sec. 9 on links from solid nodes); the
 oracle then collides sampled nodes (row ends, sub-block and segment edges,
 random nodes) from those populations: 1e-12 relative in FP64, 2e-6 absolute in
 FP32.  Two steps on one buffer in place must give the two-buffer run's
@@ -28,15 +32,18 @@ pytestmark = pytest.mark.gpu
 F64, F32 = 0, 1
 
 CASES = [
-    # q, precision, (nz, ny, nx), force
-    (27, F64, (2, 3, 65535), "field"),
-    (15, F32, (3, 2, 65535), "uniform"),
-    (27, F32, (1024, 1024, 3), "field"),
+    # q, precision, (nz, ny, nx), force, fraction of solid nodes (random walls)
+    (27, F64, (2, 3, 65535), "field", 0.0),
+    (15, F32, (3, 2, 65535), "uniform", 0.0),
+    (27, F32, (1024, 1024, 3), "field", 0.0),
+    (27, F32, (3, 4, 65535), "field", 0.2),
+    (15, F64, (512, 512, 3), "uniform", 0.2),
 ]
 
 
 def _ids(c):
-    return f"q{c[0]}-p{c[1]}-{'x'.join(map(str, c[2]))}-{c[3]}"
+    walls = f"-solid{c[4]}" if len(c) > 4 and c[4] else ""
+    return f"q{c[0]}-p{c[1]}-{'x'.join(map(str, c[2]))}-{c[3]}{walls}"
 
 
 def _sample(shape, rng):
@@ -54,25 +61,35 @@ def _sample(shape, rng):
 
 @pytest.mark.parametrize("case", CASES, ids=[_ids(c) for c in CASES])
 def test_extreme_shape_step(case):
-    q, prec, shape, fkind = case
+    q, prec, shape, fkind, frac = case
     print(f"case extreme {_ids(case)}", flush=True)
     lat = LATTICES[q]
     rng = np.random.default_rng(5)
     F = (np.array([3e-5, -1e-5, 2e-5]) if fkind == "uniform"
          else 2e-5 * rng.standard_normal((3,) + shape))
     rates = shear_rates(q, 1.9)
-    sim = gpu_setup(q, shape, prec, rates, F)
+    solid = rng.random(shape) < frac if frac else None
+    sim = gpu_setup(q, shape, prec, rates, F, solid)
     rho0 = 1.0 + 0.01 * rng.standard_normal(shape)
     u0 = 0.04 * (rng.random((3,) + shape) - 0.5)
+    if solid is not None:
+        u0[:, solid] = 0.0
     f_post, _ = sim.init_equilibrium(to_dev(rho0, sim.real), to_dev(u0, sim.real))
 
     # streaming: the gathered pre-collision state is the stored state moved
-    # by e_a, periodic in every axis
+    # by e_a, periodic in every axis; with walls, a link from a solid node
+    # takes the node's own opposite population (half-way bounce-back), and
+    # solid nodes read zero
     stored = sim.export_populations(f_post).cpu().numpy()
     pre = sim.gather(f_post).cpu().numpy()
     for a in range(q):
         ex, ey, ez = (int(c) for c in lat.E[a])
-        assert np.array_equal(pre[a], np.roll(stored[a], shift=(ez, ey, ex), axis=(0, 1, 2))), a
+        want = np.roll(stored[a], shift=(ez, ey, ex), axis=(0, 1, 2))
+        if solid is not None:
+            from_solid = np.roll(solid, shift=(ez, ey, ex), axis=(0, 1, 2))
+            want = np.where(from_solid, stored[lat.opp[a]], want)
+            want[solid] = 0.0
+        assert np.array_equal(pre[a], want), a
     del stored
 
     # collision of sampled nodes against the oracle
@@ -80,6 +97,8 @@ def test_extreme_shape_step(case):
     sim.step(f_post, out)
     post = sim.export_populations(out).cpu().numpy().reshape(q, -1)
     idx = _sample(shape, rng)
+    if solid is not None:
+        idx = idx[~solid.reshape(-1)[idx]]
     f_in = pre.reshape(q, -1)[:, idx].T.astype(np.float64)
     Fs = np.broadcast_to(F, (idx.size, 3)) if fkind == "uniform" else F.reshape(3, -1)[:, idx].T
     want = collision.collide(lat, f_in, np.ascontiguousarray(Fs, dtype=np.float64), rates)
