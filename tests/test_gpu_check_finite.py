@@ -149,3 +149,38 @@ def test_full_size_buffer_64bit_offsets():
     del flat, buf
     sim.close()
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("q", [27, 15])
+@pytest.mark.parametrize("prec", PRECS)
+def test_one_nan_through_the_scatter_phase(q, prec):
+    """The in-place scatter phase (parity 1) on a 300-node row (four full
+    64-node sub-blocks and one of 44; row segments of 256): a NaN in slot s of
+    node n is read by t = n - e_s alone, whose collision turns its Q results
+    NaN, and those are written to slot b of t + e_b, one slot each: after the
+    step exactly the Q values fbar_b(t + e_b) of the exported state are NaN.
+    The nodes t sit on wavefront and row-segment edges, where the 16-bit
+    scatter exchanges values across lanes and through LDS."""
+    lat = LATTICES[q]
+    shape = (3, 4, 300)
+    nz, ny, nx = shape
+    sim = gpu_setup(q, shape, prec, shear_rates(q, 1.6), F=[1e-4, 0, 0])
+    f = _state(sim, shape, 6)
+    rng = np.random.default_rng(21 + q + prec)
+    for tx in (0, 63, 64, 127, 255, 256, 257, nx - 1):
+        tz, ty = int(rng.integers(0, nz)), int(rng.integers(0, ny))
+        s = int(rng.integers(0, q))
+        ex, ey, ez = (int(c) for c in lat.E[s])
+        n = ((tz + ez) % nz, (ty + ey) % ny, (tx + ex) % nx)     # t = n - e_s
+        g = f.copy()
+        g[(s,) + n] = np.nan
+        buf = sim.import_populations(torch.from_numpy(g))
+        assert sim.check_finite(buf) == 1
+        sim.step_inplace(buf, 1)
+        assert sim.check_finite(buf) == q, (tx, s)
+        bad = np.isnan(sim.export_populations(buf).double().cpu().numpy())
+        want = np.zeros_like(bad)
+        for b in range(q):
+            bx, by, bz = (int(c) for c in lat.E[b])
+            want[b, (tz + bz) % nz, (ty + by) % ny, (tx + bx) % nx] = True
+        assert np.array_equal(bad, want), (tx, s)
