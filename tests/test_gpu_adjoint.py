@@ -387,3 +387,40 @@ def test_config4_reduced_lattice_vs_oracle_golden(prec):
     tol = GOLDEN4_TOL[prec]
     assert errs["dF.v"] <= tol and errs["dw_shear"] <= tol and errs["entries"] <= tol
     assert errs["loss"] <= GOLDEN4_LOSS_TOL[prec]
+
+
+@pytest.mark.parametrize("q", [27, 15])
+@pytest.mark.parametrize("prec", [F64, F32])
+def test_one_nan_through_the_reverse_gather(q, prec):
+    """Reverse streaming addresses exactly: a NaN in lam_next(m)_a is gathered
+    by x = m - e_a alone (mu_a(x) = lam_next(x + e_a)_a, periodic), so after
+    one adjoint step NaN appears in lam(x) and dL/dF(x) only, and lam(x)_a, which
+    holds mu_a itself, is NaN.  The nodes x sit on wavefront and row-segment
+    edges of a 300-node row."""
+    lat = LATTICES[q]
+    shape = (3, 4, 300)
+    nz, ny, nx = shape
+    rng = np.random.default_rng(31 + q + prec)
+    F = 1e-4 * rng.standard_normal((3,) + shape)
+    sim = gpu_setup(q, shape, prec, shear_rates(q, 1.6), F)
+    rho0 = torch.from_numpy(1.0 + 0.01 * rng.standard_normal(shape)).to("cuda", sim.real)
+    u0 = torch.from_numpy(0.04 * (rng.random((3,) + shape) - 0.5)).to("cuda", sim.real)
+    x, _ = sim.init_equilibrium(rho0, u0)
+    base = torch.from_numpy(rng.standard_normal((q,) + shape)).to("cuda", sim.real)
+    for tx in (0, 63, 64, 127, 255, 256, 257, nx - 1):
+        tz, ty = int(rng.integers(0, nz)), int(rng.integers(0, ny))
+        a = int(rng.integers(0, q))
+        ex, ey, ez = (int(c) for c in lat.E[a])
+        lam_next = base.clone()
+        lam_next[a, (tz + ez) % nz, (ty + ey) % ny, (tx + ex) % nx] = float("nan")
+        lam = sim.real_populations()
+        dLdF = torch.zeros((3,) + shape, dtype=torch.float64, device="cuda")
+        dLdw = torch.zeros(q - 4, dtype=torch.float64, device="cuda")
+        sim.adjoint_step(x, lam_next, lam, dLdF, dLdw)
+        bad = torch.isnan(lam).cpu().numpy()
+        assert bad[a, tz, ty, tx], (tx, a)
+        bad[:, tz, ty, tx] = False
+        assert not bad.any(), (tx, a)
+        badF = torch.isnan(dLdF).cpu().numpy()
+        badF[:, tz, ty, tx] = False
+        assert not badF.any(), (tx, a)
