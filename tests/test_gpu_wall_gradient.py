@@ -237,3 +237,66 @@ def test_full_size_wall_term_sampled_nodes():
     err = np.abs(got - want).max() / np.abs(want).max()
     print(f"wall term full512: rel err {err:.2e} over {len(picks)} nodes", flush=True)
     assert err < 1e-5
+
+
+@pytest.mark.parametrize("q", [27, 15])
+@pytest.mark.parametrize("frac", [0.0, 0.2])
+def test_one_nan_through_the_wall_term(q, frac):
+    """Addressing of the gather form, row tiles included (20 planes: tiles of
+    8, 8 and 4), on 130-node rows: dL/dphi(t) += sum_a x_a(s) (lam_abar(s) -
+    lam_a(t)), s = t - e_a, terms from solid sources dropped.  A NaN in
+    lam_b(m) enters the term of t = m (as lam_a(t), a = b) and of t = m - e_b
+    (as lam_abar(s), s = m), both only when m and m - e_b are fluid; a NaN in
+    x_a(s) enters the term of t = s + e_a only, when s and t are fluid.
+    Exactly those entries of dL/dphi must be NaN."""
+    lat = LATTICES[q]
+    shape = (20, 6, 130)
+    nz, ny, nx = shape
+    rng = np.random.default_rng(41 + q + int(10 * frac))
+    solid = rng.random(shape) < frac if frac else None
+    fluid = np.ones(shape, dtype=bool) if solid is None else ~solid
+    sim = gpu_setup(q, shape, F32, shear_rates(q, 1.6), [1e-4, 0, 0], solid)
+    u0 = 0.04 * (rng.random((3,) + shape) - 0.5)
+    if solid is not None:
+        u0[:, solid] = 0.0
+    x, _ = sim.init_equilibrium(torch.ones(shape, device="cuda"), torch.from_numpy(u0).to("cuda", torch.float32))
+    x_h = sim.export_populations(x).cpu().numpy()
+    lam_base = torch.from_numpy(rng.standard_normal((q,) + shape)).to("cuda", torch.float32)
+
+    def wrap(p):
+        return (p[0] % nz, p[1] % ny, p[2] % nx)
+
+    def shifted(p, b, sign):
+        ex, ey, ez = (int(c) for c in lat.E[b])
+        return wrap((p[0] + sign * ez, p[1] + sign * ey, p[2] + sign * ex))
+
+    def run(lam, xbuf):
+        d = torch.zeros(shape, dtype=torch.float64, device="cuda")
+        sim.wall_sensitivity_post(xbuf, lam, d)
+        return torch.isnan(d).cpu().numpy()
+
+    checked = 0
+    for _ in range(12):
+        b = int(rng.integers(1, q))
+        m = (int(rng.integers(0, nz)), int(rng.integers(0, ny)), int(rng.integers(0, nx)))
+        lam = lam_base.clone()
+        lam[(b,) + m] = float("nan")
+        want = np.zeros(shape, dtype=bool)
+        t2 = shifted(m, b, -1)
+        if fluid[m] and fluid[t2]:
+            want[m] = want[t2] = True
+            checked += 1
+        assert np.array_equal(run(lam, x), want), (b, m)
+    for _ in range(12):
+        a = int(rng.integers(1, q))
+        s = (int(rng.integers(0, nz)), int(rng.integers(0, ny)), int(rng.integers(0, nx)))
+        xh = x_h.copy()
+        xh[(a,) + s] = np.nan
+        xbuf = sim.import_populations(torch.from_numpy(xh))
+        want = np.zeros(shape, dtype=bool)
+        t = shifted(s, a, +1)
+        if fluid[s] and fluid[t]:
+            want[t] = True
+            checked += 1
+        assert np.array_equal(run(lam_base, xbuf), want), (a, s)
+    assert checked >= 8
